@@ -1,0 +1,84 @@
+"""Dual certificate (test infrastructure: oracle only).
+
+Theorem "Dual Optimality Certificate": at a BM local optimum U there is a
+unique y with Z(y) U^T = 0 (eq. bm_first_order_optimality), Z(y) = Q - sum
+y_i A_i (eq. Zofy); if Z(y) is PSD the point is globally optimal for the SDP.
+
+The A_i (App. "Proof of LICQ condition") act on the diagonal 3x3 blocks only:
+for frames k >= 1 they span the traceless symmetric matrices (B^1..B^5), for
+frame 0 one more constraint (unit diagonal) makes the span all of S^3.  So
+sum y_i A_i = blkdiag(Lambda_k); solving Lambda_k U_k^T = (Q U^T)_k gives
+Lambda_k = (Q U^T)_k U_k / alpha_k with alpha_k = s_k^2, symmetrised, and made
+traceless for k >= 1.  The dual objective b^T y is tr(Lambda_0).
+
+Readings (listed in the design notes): the PSD test uses a relative
+tolerance, certified <=> lambda_min >= -tau * qbar, qbar = tr(Q)/3N; the
+minimum eigenvalue is taken on the orthogonal complement of the rows of U
+(Z U^T = 0 puts those directions at zero); the escape vector is normalised
+to unit length with its largest-magnitude entry positive.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import manifold as mf
+
+
+def dual_lambda(Q, U, s):
+    """Lambda [N, 3, 3]: Lambda_k = sym((Q U^T)_k U_k) / s_k^2, traceless for k >= 1."""
+    N = U.shape[1] // 3
+    QU = (Q @ U.T)                                  # 3N x r
+    L = np.empty((N, 3, 3))
+    for k in range(N):
+        Uk = U[:, 3 * k:3 * k + 3]                  # r x 3
+        Lk = QU[3 * k:3 * k + 3, :] @ Uk / (s[k] ** 2)
+        Lk = 0.5 * (Lk + Lk.T)
+        if k > 0:
+            Lk = Lk - np.trace(Lk) / 3.0 * np.eye(3)
+        L[k] = Lk
+    return L
+
+
+def dual_matrix(Q, Lam):
+    """Z = Q - blkdiag(Lambda)."""
+    Z = Q.copy()
+    for k in range(Lam.shape[0]):
+        Z[3 * k:3 * k + 3, 3 * k:3 * k + 3] -= Lam[k]
+    return Z
+
+
+def min_eig(Z, U):
+    """Minimum eigenvalue of Z on the orthogonal complement of rows(U), with its
+    eigenvector (unit norm, largest |entry| positive).  Also the minimum of the
+    full spectrum.  Dense eigendecomposition."""
+    n = Z.shape[0]
+    Qf, _ = np.linalg.qr(U.T, mode="complete")
+    r = np.linalg.matrix_rank(U)
+    C = Qf[:, r:]
+    lam, V = np.linalg.eigh(C.T @ Z @ C)
+    v = C @ V[:, 0]
+    v = v / np.linalg.norm(v)
+    if v[np.argmax(np.abs(v))] < 0:
+        v = -v
+    full = float(np.linalg.eigvalsh(Z)[0])
+    return float(lam[0]), v, full
+
+
+def certify(Q, R, s, tau):
+    """Certificate at (R, s): dict with lambda_min (complement), lambda_min_full,
+    primal tr(Q U^T U), dual tr(Lambda_0), certified flag and escape vector."""
+    U = mf.to_U(R, s)
+    Lam = dual_lambda(Q, U, s)
+    Z = dual_matrix(Q, Lam)
+    lam, v, full = min_eig(Z, U)
+    N = R.shape[0]
+    qbar = float(np.trace(Q)) / (3 * N)
+    primal = float(np.sum(U * (U @ Q)))
+    dual = float(np.trace(Lam[0]))
+    return {"lambda_min": lam, "lambda_min_full": full, "v": v, "primal": primal,
+            "dual": dual, "certified": bool(lam >= -tau * qbar), "qbar": qbar, "Lambda": Lam}
+
+
+def suboptimality(rho_hat, rho_sdp):
+    """eta = (rho_hat - rho_sdp) / (1 + |rho_hat| + |rho_sdp|)   (eq. suboptimality)."""
+    return (rho_hat - rho_sdp) / (1.0 + abs(rho_hat) + abs(rho_sdp))
