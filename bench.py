@@ -1,0 +1,248 @@
+#!/usr/bin/env python
+"""Benchmark of the XM hot path on one MI355X.
+
+Workload: the large unordered scene (N = 10155 frames, M = 2M landmarks, ~8M
+observations, 20 camera clusters, 5% outlier observations; synthetic, seeded).
+One step = the whole hot path on that scene with inputs resident in HBM:
+xm_build_Q (Q assembly, FP64), xm_bm_solve in the FP32 form (FP32 products,
+tCG and retraction; FP64 dual certificate inside the staircase) and xm_round
+(FP64).  The reported value is the time-to-certified-optimum of the step
+(solve + certificate + rounding, Q already resident), the metric's own
+definition; Q assembly is reported beside it.  The plain FP64 solve and the
+BF16-stored-Q solve of the same scene are timed once after the steps.
+
+Prints one JSON line.  --gpus N with N > 1 is refused (one GPU per box).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-certified-optimum (s) + BSR SpMM GB/s, FP32 vs FP64, N=10k frames"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def sub_scene(sc, n_frames):
+    """The n_frames cameras nearest to camera 0 and the landmarks they share
+    (largest connected piece, re-indexed): a bounded sample of the workload."""
+    import numpy as np
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    import scenes
+    c = sc.gt["c"]
+    order = np.argsort(np.linalg.norm(c - c[0], axis=1))[:n_frames]
+    keepf = np.zeros(sc.N, bool)
+    keepf[order] = True
+    m = keepf[sc.frame]
+    fr, lm, u, w = sc.frame[m], sc.landmark[m], sc.u[m], sc.w[m]
+    cnt = np.bincount(lm, minlength=sc.M)
+    m2 = cnt[lm] >= 2
+    fr, lm, u, w = fr[m2], lm[m2], u[m2], w[m2]
+    # connected piece containing frame 0
+    o = np.argsort(lm, kind="stable")
+    lms, frs = lm[o], fr[o]
+    starts = np.flatnonzero(np.r_[True, lms[1:] != lms[:-1]])
+    first = np.repeat(frs[starts], np.diff(np.r_[starts, lms.shape[0]]))
+    A = coo_matrix((np.ones(frs.shape[0]), (first, frs)), shape=(sc.N, sc.N)).tocsr()
+    _, lab = connected_components(A, directed=False)
+    keep2 = lab[fr] == lab[0]
+    fr, lm, u, w = fr[keep2], lm[keep2], u[keep2], w[keep2]
+    fmap = -np.ones(sc.N, np.int64)
+    uf = np.unique(fr)
+    uf = np.r_[0, uf[uf != 0]]                      # frame 0 stays the anchor
+    fmap[uf] = np.arange(uf.size)
+    ul, lmap = np.unique(lm, return_inverse=True)
+    return scenes.Scene(int(uf.size), int(ul.size), fmap[fr].astype(np.int32), lmap.astype(np.int32),
+                        u.copy(), w.copy(), {}, "large-sub")
+
+
+def cpu_baseline(sc, n3_full, budget_frames=400):
+    """The FP64 oracle (Q by block elimination, staircase from the same lifted
+    start rule, certificate, rounding) timed on a sub-scene of the workload."""
+    import numpy as np
+
+    from oracle import data_matrix, manifold, rounding, staircase
+    sub = sub_scene(sc, budget_frames)
+    threads = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp:
+        threads = min(threads, int(omp))
+    t0 = time.perf_counter()
+    Q = data_matrix.q_block_elimination(sub.N, sub.M, sub.frame, sub.landmark, sub.u, sub.w)
+    t1 = time.perf_counter()
+    R0, s0 = manifold.initial_point(sub.N, 5)
+    rng = np.random.default_rng(2025)
+    R0 = manifold.gram_schmidt(R0 + rng.uniform(-1, 1, R0.shape))
+    R, s, info = staircase.staircase(Q, r0=5, r_max=7, grad_tol=1e-9, tau=1e-7, R0=R0, s0=s0)
+    rounding.round_solution(manifold.to_U(R, s))
+    t2 = time.perf_counter()
+    n3s = 3 * sub.N
+    scale = (n3_full / n3s) ** 2
+    return {
+        "value": round((t2 - t1) * scale, 3),
+        "unit": "s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle time-to-certified-optimum (staircase + dense eigh certificate + rounding, FP64, "
+                   f"Q resident) on the {sub.N}-frame sub-scene nearest camera 0 ({sub.n_obs} obs): "
+                   f"{t2 - t1:.2f} s measured, scaled by (3N_full/3N_sub)^2 = {scale:.1f} for the per-product "
+                   f"cost; Q build {t1 - t0:.2f} s not included; certified={info['certified']} r={info['r']}"),
+        "measured_s": round(t2 - t1, 3),
+        "sub_frames": sub.N,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / BF16 comparison solves")
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU sharding is a design note only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2502_04640_amd as xm
+    import scenes
+
+    t = time.perf_counter()
+    sc = scenes.make_scene(args.workload, args.seed)
+    log(f"scene {args.workload}: N={sc.N} M={sc.M} n_obs={sc.n_obs} ({time.perf_counter() - t:.1f} s)")
+    dev = torch.device("cuda:0")
+    fr = torch.from_numpy(sc.frame).to(dev)
+    lm = torch.from_numpy(sc.landmark).to(dev)
+    u = torch.from_numpy(sc.u).to(dev)
+    w = torch.from_numpy(sc.w).to(dev)
+    torch.cuda.synchronize()
+    opts32 = xm.SolveOptions(compute="f32", verbose=args.verbose)
+
+    def step(timing=False):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = xm.build_Q(sc.N, sc.M, fr, lm, u, w, keep=("f32", "bf16"))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if timing:
+            P.spmm_timing(True)
+        Y, info = P.solve(opts32)
+        R, s, rho_hat = P.round(Y)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return P, Y, info, rho_hat, (t1 - t0), (t2 - t1)
+
+    for i in range(args.warmup):
+        P, Y, info, rho_hat, tb, ts = step()
+        log(f"warmup {i}: build {tb:.3f} s, solve+cert+round {ts:.3f} s, certified={info['certified']} r={info['r']}")
+        del P
+    builds, ttcs, infos = [], [], []
+    P = None
+    torch.cuda.synchronize()
+    t_all0 = time.perf_counter()
+    for i in range(args.steps):
+        if P is not None:
+            del P
+        P, Y, info, rho_hat, tb, ts = step(timing=True)
+        builds.append(tb)
+        ttcs.append(ts)
+        infos.append(info)
+        log(f"step {i}: build {tb:.3f} s, ttc {ts:.3f} s, certified={info['certified']} r={info['r']} "
+            f"outer={info['outer_iters']} inner={info['inner_iters']} spmm={info['spmm_count']} "
+            f"lanczos={info['lanczos_iters']} cost={info['cost']:.10e}")
+    torch.cuda.synchronize()
+    t_all1 = time.perf_counter()
+    stats = P.spmm_stats(reset=True)
+    pinfo = P.info()
+    last = infos[-1]
+    rho = rho_hat
+    eta = (rho - last["cost"]) / (1 + abs(rho) + abs(last["cost"]))
+
+    # dominant product kernel within the timed steps (per-launch HIP-event durations)
+    dom = max(("f32", "f64", "bf16"), key=lambda k: stats[k]["total_ms"])
+    d = stats[dom]
+    avg_ms = d["total_ms"] / max(1, d["launches"])
+    achieved = d["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 if d["launches"] else 0.0
+    spmm_gbs = {k: (stats[k]["bytes_per_launch"] / (stats[k]["total_ms"] / stats[k]["launches"] * 1e-3) / 1e9
+                    if stats[k]["launches"] else None) for k in stats}
+    out = {
+        "metric": METRIC,
+        "value": round(statistics.median(ttcs), 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * (t_all1 - t_all0) / args.steps, 2),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: N={sc.N} frames, M={sc.M} landmarks, n_obs={sc.n_obs}, "
+                               "20 camera clusters, track length 1+Geom(1/3) over 50 nearest cameras, "
+                               "sigma=0.02, depth scales U[0.5,2], 5% outlier observations",
+                   "N": sc.N, "M": sc.M, "n_obs": sc.n_obs, "seed": args.seed,
+                   "solver": {"r0": opts32.r0, "r_max": opts32.r_max, "lift": opts32.lift}},
+        "certified": bool(last["certified"]),
+        "rank": last["r"],
+        "cost": last["cost"],
+        "rho_hat": rho,
+        "eta": eta,
+        "lambda_min": last["lambda_min"],
+        "build_Q_s": round(statistics.median(builds), 4),
+        "solve_ms": round(last["solve_ms"], 2),
+        "cert_ms": round(last["cert_ms"], 2),
+        "iters": {"outer": last["outer_iters"], "inner": last["inner_iters"], "spmm": last["spmm_count"],
+                  "lanczos": last["lanczos_iters"], "stair_steps": last["stair_steps"]},
+        "spmm_GBps": {k: (round(v, 1) if v else None) for k, v in spmm_gbs.items()},
+        "spmm_launches": {k: stats[k]["launches"] for k in stats},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"spmm_split_kernel ({dom} Q)", "bytes_per_launch": d["bytes_per_launch"],
+                     "avg_launch_ms": round(avg_ms, 4)},
+    }
+    if not args.no_compare:
+        for name in ("f64", "bf16"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Yc, ic = P.solve(xm.SolveOptions(compute=name))
+            Rc, sc_, rc = P.round(Yc)
+            torch.cuda.synchronize()
+            tc = time.perf_counter() - t0
+            out[f"ttc_{name}_s"] = round(tc, 4)
+            out[f"{name}_solve"] = {"certified": bool(ic["certified"]), "rank": ic["r"], "cost": ic["cost"],
+                                    "outer": ic["outer_iters"], "inner": ic["inner_iters"],
+                                    "lanczos": ic["lanczos_iters"], "rho_hat": rc}
+            log(f"{name}: ttc {tc:.3f} s certified={ic['certified']} r={ic['r']} cost={ic['cost']:.10e}")
+        st2 = P.spmm_stats(reset=True)
+        out["spmm_GBps_compare"] = {k: (round(st2[k]["bytes_per_launch"] / (st2[k]["total_ms"] / st2[k]["launches"]
+                                                                          * 1e-3) / 1e9, 1)
+                                        if st2[k]["launches"] else None) for k in st2}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a sub-scene) ...")
+        out["cpu_baseline"] = cpu_baseline(sc, 3 * sc.N)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,256 @@
+/*
+ * xm.h -- C ABI of the MI355X (gfx950) XM library.
+ *
+ * Solves scaled bundle adjustment (SBA, eq. sba of Han & Yang, "Building Rome
+ * with Convex Optimization", arXiv 2502.04640) to certified global optimality:
+ *
+ *   xm_build_Q   eliminate translations and landmarks in closed form and
+ *                assemble the 3N x 3N rotation-only data matrix Q
+ *                (Prop. "Scaled-Rotation-Only Formulation", App. A);
+ *   xm_bm_solve  Burer-Monteiro factorisation of the SDP relaxation
+ *                (Prop. "SDP Relaxation", Prop. "BM Factorization") solved by
+ *                the Riemannian staircase (Algorithm "Riemannian Staircase")
+ *                with a trust-region / truncated-CG local optimiser
+ *                (Prop. "BM Riemannian Optimization");
+ *   xm_certify   dual certificate Z = Q - blkdiag(Lambda) and its minimum
+ *                eigenvalue (Theorem "Dual Optimality Certificate");
+ *   xm_round     rounding of the low-rank factor to anchored scaled rotations
+ *                and the suboptimality gap (eq. suboptimality).
+ *
+ * Conventions (all entry points):
+ *  - Every pointer argument named "device" is GPU memory owned by the caller
+ *    (for example torch.Tensor.data_ptr()).  Host pointers are marked "host".
+ *  - `stream` is a hipStream_t passed as void*.  Work is enqueued on it; the
+ *    entry points that return scalars (info structs) synchronise that stream
+ *    before returning.  NULL means the default stream.
+ *  - Indices are 0-based.  Frame 0 is the anchor (the paper's frame 1:
+ *    R = I, t = 0, s = 1, Section "Anchoring").
+ *  - A low-rank factor Y (the paper's U) is a device array of doubles,
+ *    row-major [r][3N]: column 3k+c of row a is (s_k R_k)[a][c] for the r x 3
+ *    Stiefel block R_k of frame k.
+ *  - Rotations are returned row-major [N][3][3] in the SBA camera->world
+ *    convention (footnote to eq. sba): R_i (s_i u_ik) + t_i = p_k.
+ *  - Return value: XM_OK (0) or a negative xm_status; xm_last_error() then
+ *    gives a message (thread-local, valid until the next call on the thread).
+ *    On XM_EINVAL / XM_EGRAPH no output has been written.
+ *  - The library is not re-entrant on one problem handle: calls that use the
+ *    same handle must be serialised by the caller.
+ */
+#ifndef XM_H_
+#define XM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  XM_OK = 0,
+  XM_EINVAL = -1,   /* bad argument: sizes, NaN/Inf keypoint, weight <= 0, index out of range */
+  XM_ENOMEM = -2,   /* device allocation failed */
+  XM_EHIP = -3,     /* a HIP runtime call failed */
+  XM_EGRAPH = -4,   /* a frame without observations, or a disconnected view graph */
+  XM_ENOCONV = -5   /* iteration cap reached; outputs hold the last iterate */
+} xm_status;
+
+typedef enum { XM_F64 = 0, XM_F32 = 1, XM_BF16 = 2 } xm_dtype;
+
+/* Opaque problem handle: device-resident Q (FP64 master and optional FP32 /
+ * BF16 copies) plus the workspaces of the solver.  Owned by the library,
+ * released with xm_free. */
+typedef struct xm_problem xm_problem;
+
+/* Bits of `copies` in xm_build_Q. */
+#define XM_KEEP_F32 (1u << 1)
+#define XM_KEEP_BF16 (1u << 2)
+
+/*
+ * Assemble Q from the observations of the view graph.
+ *
+ * Operation (Prop. "Scaled-Rotation-Only Formulation", App. A): the SBA cost
+ * sum_{(i,k)} w_ik || R_i (s_i u_ik) + t_i - p_k ||^2 is minimised over the
+ * landmarks p_k and translations t_i (t_0 = 0) in closed form, leaving
+ * tr(Q U^T U).  The landmarks are eliminated per landmark (Schur complement
+ * of the diagonal landmark block), the translations by the inverse of the
+ * grounded frame Laplacian.  Q is built in FP64.
+ *
+ * N        number of frames (>= 2, < 65536)
+ * M        number of landmarks (>= 1); landmark ids lie in [0, M)
+ * n_obs    number of observations (>= 1, < 2^31)
+ * frame    device int32 [n_obs], frame index of each observation
+ * landmark device int32 [n_obs], landmark index of each observation
+ * u        device [n_obs][3] lifted keypoints u_ik (eq. 3D-lifting), dtype u_dtype
+ * u_dtype  XM_F64 or XM_F32
+ * w        device [n_obs] weights w_ik > 0, dtype w_dtype, or NULL for all ones
+ * w_dtype  XM_F64 or XM_F32 (ignored when w is NULL)
+ * copies   XM_KEEP_F32 | XM_KEEP_BF16: reduced-precision copies of Q to keep
+ *          for xm_bm_solve with compute = XM_F32 / XM_BF16
+ * stream   hipStream_t
+ * out      host: receives the new handle
+ *
+ * Observations may come in any order; a landmark seen once contributes
+ * nothing.  Errors: XM_EINVAL (sizes, index out of range, non-finite u,
+ * w <= 0), XM_EGRAPH (frame without observations, disconnected graph).
+ * Synchronises `stream`.
+ */
+xm_status xm_build_Q(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame,
+                     const int32_t* landmark, const void* u, xm_dtype u_dtype,
+                     const void* w, xm_dtype w_dtype, uint32_t copies, void* stream,
+                     xm_problem** out);
+
+/* Release a handle and all device memory it owns.  NULL is allowed. */
+void xm_free(xm_problem* p);
+
+typedef struct {
+  int32_t N, M;
+  int64_t n_obs;
+  int64_t nnz_blocks;    /* co-visibility blocks (frame pairs sharing a landmark, incl. diagonal) */
+  int64_t n_pairs;       /* per-landmark observation pairs reduced into the blocks */
+  int32_t ld;            /* leading dimension (elements) of the dense row-major Q copies */
+  int32_t copies;        /* bitmask: 1 (FP64) | XM_KEEP_F32 | XM_KEEP_BF16 */
+  double qbar;           /* tr(Q) / 3N, the scale used by the relative tolerances */
+  double build_ms;       /* device time of the last xm_build_Q, milliseconds */
+} xm_problem_info;
+
+/* Fill `info` (host) for a handle. */
+xm_status xm_get_info(const xm_problem* p, xm_problem_info* info);
+
+/*
+ * Copy rows [row0, row0 + nrows) of the FP64 Q into `out` (device, row-major
+ * [nrows][3N]).  For checks against a reference.  Synchronises `stream`.
+ */
+xm_status xm_get_Q_rows(const xm_problem* p, int32_t row0, int32_t nrows, double* out,
+                        void* stream);
+
+/*
+ * Y Q product with the stored Q of precision `dtype` (XM_F64 / XM_F32 /
+ * XM_BF16 copy): out[a][j] = sum_i Y[a][i] Q[i][j] for a < r, the block-
+ * sparse product of the local solver (Euclidean gradient Gamma = 2 Y Q,
+ * Section "C++/CUDA-based Riemannian Optimization").  Y and out are device
+ * [r][3N] doubles, 1 <= r <= 8.  Accumulation is FP64 for XM_F64 and FP32
+ * otherwise.  Exposed for measurement and checks.
+ */
+xm_status xm_spmm(xm_problem* p, xm_dtype dtype, const double* Y, int32_t r, double* out,
+                  void* stream);
+
+typedef struct {
+  int32_t r0;          /* initial rank (>= 3); the staircase starts here */
+  int32_t r_max;       /* maximum rank (r0 <= r_max <= 7) */
+  double lift;         /* start point when Y0 is NULL: U^0 = [I, ..., I] padded
+                          with zero rows (the paper's initialisation) perturbed
+                          by a seeded uniform [-lift, lift] and re-orthonormalised
+                          per block; 0 gives the paper's U^0 exactly */
+  xm_dtype compute;    /* XM_F64: FP64 everywhere; XM_F32: FP32 products and
+                          manifold arithmetic; XM_BF16: BF16-stored Q for the
+                          Hessian products, FP32 Q for gradient and cost */
+  double grad_tol;     /* stop when ||grad|| <= grad_tol * qbar * ||Y||_F
+                          (<= 0: 1e-9 for XM_F64, 1e-6 otherwise) */
+  double cert_tol;     /* certified iff lambda_min(Z) >= -cert_tol * qbar
+                          (<= 0: 1e-7 for XM_F64, 1e-5 otherwise) */
+  int32_t max_outer;   /* trust-region iterations per rank (<= 0: 300) */
+  int32_t max_inner;   /* truncated-CG iterations per outer step (<= 0: 3N*r) */
+  double delta0;       /* initial trust radius (<= 0: sqrt(3N)/8) */
+  int32_t lanczos_max; /* Lanczos iterations per certificate (<= 0: 400) */
+  double lanczos_tol;  /* Ritz residual tolerance relative to qbar (<= 0: 1e-6) */
+  int32_t verbose;     /* 1: one line per outer iteration on stderr */
+} xm_solve_opts;
+
+/* Fill `opts` with the defaults: compute = XM_F64, r0 = 5, r_max = 7,
+ * lift = 1 (a lifted start; set r0 = 3, lift = 0 for the paper's U^0), every
+ * other field 0 (= the documented default). */
+void xm_default_opts(xm_solve_opts* opts);
+
+typedef struct {
+  int32_t r;             /* final rank */
+  int32_t certified;     /* 1 if the final certificate holds */
+  int32_t outer_iters;   /* trust-region iterations, all ranks */
+  int32_t inner_iters;   /* truncated-CG iterations, all ranks */
+  int32_t stair_steps;   /* rank increases taken */
+  int32_t spmm_count;    /* Y Q products in the solve (excluding the certificate) */
+  int32_t lanczos_iters; /* Lanczos iterations, all certificates */
+  int32_t converged;     /* 1 if the gradient tolerance was met at the final rank */
+  double cost;           /* f = tr(Q Y^T Y), FP64 */
+  double grad_norm;      /* final Riemannian gradient norm from FP64 products */
+  double lambda_min;     /* minimum eigenvalue of Z at the final point */
+  double primal, dual;   /* tr(Q Y^T Y) and tr(Lambda_0) */
+  double solve_ms;       /* wall time of the local solves, milliseconds */
+  double cert_ms;        /* wall time of the certificates, milliseconds */
+} xm_solve_info;
+
+/*
+ * Riemannian staircase (Algorithm "Riemannian Staircase").
+ *
+ * Y0     device [r_in][3N] initial factor (feasible: Y0_k^T Y0_k = alpha_k I,
+ *        alpha_0 = 1), or NULL for U^0 = [I, ..., I] at rank opts->r0.
+ * r_in   rank of Y0 (ignored when Y0 is NULL).
+ * Y_out  device [opts->r_max][3N]; rows [0, info->r) hold the solution, the
+ *        rest are zero.
+ * info   host, filled on return.
+ * Returns XM_OK, or XM_ENOCONV if an iteration cap stopped the final local
+ * solve (Y_out still holds the last iterate).  Synchronises `stream`.
+ */
+xm_status xm_bm_solve(xm_problem* p, const xm_solve_opts* opts, const double* Y0, int32_t r_in,
+                      double* Y_out, xm_solve_info* info, void* stream);
+
+typedef struct {
+  double lambda_min;     /* minimum eigenvalue of Z on the complement of rows(Y) */
+  double ritz_residual;  /* residual norm of the Ritz pair of lambda_min */
+  double primal;         /* tr(Q Y^T Y) */
+  double dual;           /* tr(Lambda_0), the dual objective b^T y */
+  double qbar;           /* tr(Q) / 3N */
+  double grad_norm;      /* || Z Y^T ||_F, the stationarity residual */
+  int32_t certified;     /* lambda_min >= -tol * qbar */
+  int32_t iters;         /* Lanczos iterations */
+} xm_cert;
+
+/*
+ * Dual certificate at Y (Theorem "Dual Optimality Certificate").
+ * Lambda_k = sym((Q Y^T)_k Y_k) / alpha_k (traceless for k >= 1),
+ * Z = Q - blkdiag(Lambda), lambda_min(Z) by FP64 Lanczos with full
+ * reorthogonalisation, deflated against the rows of Y.
+ * Y      device [r][3N], 1 <= r <= 8;  tol: relative tolerance (<= 0: 1e-7)
+ * v_min  device [3N] unit eigenvector of lambda_min, or NULL.
+ * Synchronises `stream`.
+ */
+xm_status xm_certify(xm_problem* p, const double* Y, int32_t r, double tol, int32_t max_iter,
+                     double* v_min, xm_cert* cert, void* stream);
+
+/*
+ * Rounding (Prop. "SDP Relaxation" and the text after it): top-3 eigenvectors
+ * of X = Y^T Y (through the r x r Gram Y Y^T), projection of each 3x3 block
+ * to a scaled rotation with the majority determinant sign, anchoring
+ * R_k <- R_0^T R_k, s_k <- s_k / s_0, and rho_hat = tr(Q Uhat^T Uhat) in FP64.
+ * Y      device [r][3N], 3 <= r <= 8
+ * R_out  device [N][3][3] row-major rotations;  s_out device [N] scales
+ * rho_hat host: cost of the rounded point (may be NULL)
+ * Synchronises `stream`.
+ */
+xm_status xm_round(xm_problem* p, const double* Y, int32_t r, double* R_out, double* s_out,
+                   double* rho_hat, void* stream);
+
+/*
+ * Measurement hooks for the Y Q product kernel (the HBM-bound kernel of the
+ * local solver and of the Lanczos certificate).  With timing enabled, every
+ * launch of the product kernel on a handle is bracketed by two HIP events on
+ * the stream it runs on.  xm_spmm_stats synchronises those events and returns,
+ * per stored precision (index = xm_dtype), the number of launches, their total
+ * device time and the algorithmic bytes of one launch, (3N)^2 times the
+ * element size (each stored element of Q is read once).  reset != 0 forgets
+ * the recorded launches.
+ */
+typedef struct {
+  int64_t launches[3];
+  double total_ms[3];
+  double bytes_per_launch[3];
+} xm_spmm_counters;
+xm_status xm_spmm_timing(xm_problem* p, int32_t enable);
+xm_status xm_spmm_stats(xm_problem* p, xm_spmm_counters* out, int32_t reset);
+
+/* Message for the last failure on this thread ("" if none). */
+const char* xm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XM_H_ */

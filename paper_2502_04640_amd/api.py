@@ -1,0 +1,268 @@
+"""ctypes binding of libxm (argument marshalling only).
+
+Every function here forwards torch device pointers, sizes and the current HIP
+stream to the C ABI declared in include/xm.h; no step of the computation runs
+in Python.  Tensors must live on the ROCm device (torch "cuda" device type).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+XM_OK, XM_EINVAL, XM_ENOMEM, XM_EHIP, XM_EGRAPH, XM_ENOCONV = 0, -1, -2, -3, -4, -5
+XM_F64, XM_F32, XM_BF16 = 0, 1, 2
+XM_KEEP_F32, XM_KEEP_BF16 = 1 << 1, 1 << 2
+_DT = {"f64": XM_F64, "f32": XM_F32, "bf16": XM_BF16}
+_STATUS = {XM_EINVAL: "XM_EINVAL", XM_ENOMEM: "XM_ENOMEM", XM_EHIP: "XM_EHIP", XM_EGRAPH: "XM_EGRAPH",
+           XM_ENOCONV: "XM_ENOCONV"}
+
+
+class XMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _ProblemInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("n_obs", ctypes.c_int64),
+                ("nnz_blocks", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("ld", ctypes.c_int32),
+                ("copies", ctypes.c_int32), ("qbar", ctypes.c_double), ("build_ms", ctypes.c_double)]
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("r0", ctypes.c_int32), ("r_max", ctypes.c_int32), ("lift", ctypes.c_double),
+                ("compute", ctypes.c_int32),
+                ("grad_tol", ctypes.c_double), ("cert_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
+                ("max_inner", ctypes.c_int32), ("delta0", ctypes.c_double), ("lanczos_max", ctypes.c_int32),
+                ("lanczos_tol", ctypes.c_double), ("verbose", ctypes.c_int32)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("certified", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("inner_iters", ctypes.c_int32), ("stair_steps", ctypes.c_int32), ("spmm_count", ctypes.c_int32),
+                ("lanczos_iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("cost", ctypes.c_double),
+                ("grad_norm", ctypes.c_double), ("lambda_min", ctypes.c_double), ("primal", ctypes.c_double),
+                ("dual", ctypes.c_double), ("solve_ms", ctypes.c_double), ("cert_ms", ctypes.c_double)]
+
+
+class _Cert(ctypes.Structure):
+    _fields_ = [("lambda_min", ctypes.c_double), ("ritz_residual", ctypes.c_double), ("primal", ctypes.c_double),
+                ("dual", ctypes.c_double), ("qbar", ctypes.c_double), ("grad_norm", ctypes.c_double),
+                ("certified", ctypes.c_int32), ("iters", ctypes.c_int32)]
+
+
+class _SpmmStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 3), ("total_ms", ctypes.c_double * 3),
+                ("bytes_per_launch", ctypes.c_double * 3)]
+
+
+def library_path() -> str:
+    return os.environ.get("XM_LIBRARY", os.path.join(HERE, "libxm.so"))
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libxm.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"libxm.so not found at {path}: build it with "
+                          "`python -m paper_2502_04640_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P, V, I32, I64, U32, D = (ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                              ctypes.c_uint32, ctypes.c_double)
+    lib.xm_build_Q.argtypes = [I32, I32, I64, V, V, V, ctypes.c_int, V, ctypes.c_int, U32, V,
+                               ctypes.POINTER(ctypes.c_void_p)]
+    lib.xm_build_Q.restype = ctypes.c_int
+    lib.xm_free.argtypes = [P]
+    lib.xm_free.restype = None
+    lib.xm_get_info.argtypes = [P, ctypes.POINTER(_ProblemInfo)]
+    lib.xm_get_info.restype = ctypes.c_int
+    lib.xm_get_Q_rows.argtypes = [P, I32, I32, V, V]
+    lib.xm_get_Q_rows.restype = ctypes.c_int
+    lib.xm_spmm.argtypes = [P, ctypes.c_int, V, I32, V, V]
+    lib.xm_spmm.restype = ctypes.c_int
+    lib.xm_default_opts.argtypes = [ctypes.POINTER(_SolveOpts)]
+    lib.xm_default_opts.restype = None
+    lib.xm_bm_solve.argtypes = [P, ctypes.POINTER(_SolveOpts), V, I32, V, ctypes.POINTER(_SolveInfo), V]
+    lib.xm_bm_solve.restype = ctypes.c_int
+    lib.xm_certify.argtypes = [P, V, I32, D, I32, V, ctypes.POINTER(_Cert), V]
+    lib.xm_certify.restype = ctypes.c_int
+    lib.xm_round.argtypes = [P, V, I32, V, V, ctypes.POINTER(ctypes.c_double), V]
+    lib.xm_round.restype = ctypes.c_int
+    lib.xm_spmm_timing.argtypes = [P, I32]
+    lib.xm_spmm_timing.restype = ctypes.c_int
+    lib.xm_spmm_stats.argtypes = [P, ctypes.POINTER(_SpmmStats), I32]
+    lib.xm_spmm_stats.restype = ctypes.c_int
+    lib.xm_last_error.argtypes = []
+    lib.xm_last_error.restype = ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _check(code: int, allow=()):
+    if code != XM_OK and code not in allow:
+        raise XMError(code, load_library().xm_last_error().decode())
+    return code
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dev_tensor(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+@dataclasses.dataclass
+class SolveOptions:
+    r0: int = 5
+    r_max: int = 7
+    lift: float = 1.0             # 0 with r0 = 3: the paper's U^0 = [I, ..., I]
+    compute: str = "f64"          # "f64" | "f32" | "bf16"
+    grad_tol: float = 0.0         # <= 0: library default
+    cert_tol: float = 0.0
+    max_outer: int = 0
+    max_inner: int = 0
+    delta0: float = 0.0
+    lanczos_max: int = 0
+    lanczos_tol: float = 0.0
+    verbose: bool = False
+
+    def to_c(self) -> _SolveOpts:
+        o = _SolveOpts()
+        load_library().xm_default_opts(ctypes.byref(o))
+        o.r0, o.r_max, o.lift, o.compute = self.r0, self.r_max, self.lift, _DT[self.compute]
+        o.grad_tol, o.cert_tol = self.grad_tol, self.cert_tol
+        o.max_outer, o.max_inner, o.delta0 = self.max_outer, self.max_inner, self.delta0
+        o.lanczos_max, o.lanczos_tol, o.verbose = self.lanczos_max, self.lanczos_tol, int(self.verbose)
+        return o
+
+
+class Problem:
+    """A device-resident data matrix Q built by xm_build_Q (and its handle)."""
+
+    def __init__(self, handle: int, N: int, M: int):
+        self._h = ctypes.c_void_p(handle)
+        self.N, self.M = N, M
+        self.n3 = 3 * N
+
+    def close(self):
+        if self._h and self._h.value:
+            load_library().xm_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = _ProblemInfo()
+        _check(load_library().xm_get_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _ProblemInfo._fields_}
+
+    def Q_rows(self, row0: int, nrows: int) -> torch.Tensor:
+        out = torch.empty((nrows, self.n3), dtype=torch.float64, device="cuda")
+        _check(load_library().xm_get_Q_rows(self._h, row0, nrows, _ptr(out), _stream()))
+        return out
+
+    def spmm(self, Y: torch.Tensor, dtype: str = "f64") -> torch.Tensor:
+        Y = _dev_tensor(Y, torch.float64, "Y")
+        out = torch.empty_like(Y)
+        _check(load_library().xm_spmm(self._h, _DT[dtype], _ptr(Y), Y.shape[0], _ptr(out), _stream()))
+        return out
+
+    def spmm_timing(self, enable: bool = True):
+        _check(load_library().xm_spmm_timing(self._h, int(enable)))
+
+    def spmm_stats(self, reset: bool = True) -> dict:
+        st = _SpmmStats()
+        _check(load_library().xm_spmm_stats(self._h, ctypes.byref(st), int(reset)))
+        out = {}
+        for name, k in _DT.items():
+            out[name] = {"launches": st.launches[k], "total_ms": st.total_ms[k],
+                         "bytes_per_launch": st.bytes_per_launch[k]}
+        return out
+
+    def solve(self, opts: Optional[SolveOptions] = None, Y0: Optional[torch.Tensor] = None):
+        """Riemannian staircase.  Returns (Y [r][3N] float64, info dict)."""
+        opts = opts or SolveOptions()
+        o = opts.to_c()
+        Y_out = torch.empty((opts.r_max, self.n3), dtype=torch.float64, device="cuda")
+        info = _SolveInfo()
+        r_in = 0
+        if Y0 is not None:
+            Y0 = _dev_tensor(Y0, torch.float64, "Y0")
+            r_in = Y0.shape[0]
+        code = load_library().xm_bm_solve(self._h, ctypes.byref(o), _ptr(Y0), r_in, _ptr(Y_out),
+                                          ctypes.byref(info), _stream())
+        _check(code, allow=(XM_ENOCONV,))
+        d = {f: getattr(info, f) for f, _ in _SolveInfo._fields_}
+        d["status"] = code
+        return Y_out[: info.r].contiguous(), d
+
+    def certify(self, Y: torch.Tensor, tol: float = 0.0, max_iter: int = 0, want_vector: bool = False):
+        Y = _dev_tensor(Y, torch.float64, "Y")
+        v = torch.empty(self.n3, dtype=torch.float64, device="cuda") if want_vector else None
+        c = _Cert()
+        _check(load_library().xm_certify(self._h, _ptr(Y), Y.shape[0], tol, max_iter, _ptr(v), ctypes.byref(c),
+                                         _stream()))
+        d = {f: getattr(c, f) for f, _ in _Cert._fields_}
+        if want_vector:
+            d["v_min"] = v
+        return d
+
+    def round(self, Y: torch.Tensor):
+        """Rounded anchored rotations [N,3,3], scales [N] and rho_hat."""
+        Y = _dev_tensor(Y, torch.float64, "Y")
+        R = torch.empty((self.N, 3, 3), dtype=torch.float64, device="cuda")
+        s = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        rho = ctypes.c_double(0.0)
+        _check(load_library().xm_round(self._h, _ptr(Y), Y.shape[0], _ptr(R), _ptr(s), ctypes.byref(rho),
+                                       _stream()))
+        return R, s, rho.value
+
+
+def build_Q(N: int, M: int, frame: torch.Tensor, landmark: torch.Tensor, u: torch.Tensor,
+            w: Optional[torch.Tensor] = None, keep=("f32",)) -> Problem:
+    """xm_build_Q on device tensors (frame/landmark int32, u [n,3] and w [n] float64 or float32)."""
+    lib = load_library()
+    frame = _dev_tensor(frame, torch.int32, "frame")
+    landmark = _dev_tensor(landmark, torch.int32, "landmark")
+    if u.dtype not in (torch.float64, torch.float32):
+        raise TypeError("u must be float64 or float32")
+    u = _dev_tensor(u, u.dtype, "u")
+    u_dt = XM_F64 if u.dtype == torch.float64 else XM_F32
+    w_dt = XM_F64
+    if w is not None:
+        if w.dtype not in (torch.float64, torch.float32):
+            raise TypeError("w must be float64 or float32")
+        w = _dev_tensor(w, w.dtype, "w")
+        w_dt = XM_F64 if w.dtype == torch.float64 else XM_F32
+    if u.dim() != 2 or u.shape[1] != 3 or u.shape[0] != frame.shape[0] or landmark.shape[0] != frame.shape[0]:
+        raise ValueError("shapes: frame [n], landmark [n], u [n, 3]")
+    copies = 0
+    for k in keep:
+        copies |= {"f32": XM_KEEP_F32, "bf16": XM_KEEP_BF16}[k]
+    h = ctypes.c_void_p(0)
+    _check(lib.xm_build_Q(N, M, frame.shape[0], _ptr(frame), _ptr(landmark), _ptr(u), u_dt, _ptr(w), w_dt,
+                          copies, _stream(), ctypes.byref(h)))
+    return Problem(h.value, N, M)

@@ -1,0 +1,198 @@
+// C ABI of libxm (declared and documented in include/xm.h).
+#include <string>
+
+#include "problem.h"
+
+xm_problem::~xm_problem() {
+  for (auto& e : events) {
+    (void)hipEventDestroy(e.start);
+    (void)hipEventDestroy(e.stop);
+  }
+}
+
+namespace {
+thread_local std::string g_err;
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+xm_status fail(xm_status code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace
+
+#define XM_API_TRY \
+  try {            \
+    g_err.clear();
+#define XM_API_CATCH                                    \
+  }                                                     \
+  catch (const xm::Error& e) {                          \
+    return fail(e.code, e.what());                      \
+  }                                                     \
+  catch (const std::bad_alloc&) {                       \
+    return fail(XM_ENOMEM, "host allocation failed");   \
+  }                                                     \
+  catch (const std::exception& e) {                     \
+    return fail(XM_EHIP, e.what());                     \
+  }
+
+extern "C" {
+
+xm_status xm_build_Q(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame, const int32_t* landmark,
+                     const void* u, xm_dtype u_dtype, const void* w, xm_dtype w_dtype, uint32_t copies,
+                     void* stream, xm_problem** out) {
+  XM_API_TRY
+  if (!out) return fail(XM_EINVAL, "out must be non-NULL");
+  *out = nullptr;
+  auto P = xm::build_problem(N, M, n_obs, frame, landmark, u, u_dtype, w, w_dtype, copies, as_stream(stream));
+  *out = P.release();
+  return XM_OK;
+  XM_API_CATCH
+}
+
+void xm_free(xm_problem* p) { delete p; }
+
+xm_status xm_get_info(const xm_problem* p, xm_problem_info* info) {
+  if (!p || !info) return fail(XM_EINVAL, "NULL argument");
+  info->N = p->N;
+  info->M = p->M;
+  info->n_obs = p->n_obs;
+  info->nnz_blocks = p->nnzb;
+  info->n_pairs = p->n_pairs;
+  info->ld = p->ld;
+  info->copies = static_cast<int32_t>(p->copies);
+  info->qbar = p->qbar;
+  info->build_ms = p->build_ms;
+  g_err.clear();
+  return XM_OK;
+}
+
+xm_status xm_get_Q_rows(const xm_problem* p, int32_t row0, int32_t nrows, double* out, void* stream) {
+  XM_API_TRY
+  if (!p || !out) return fail(XM_EINVAL, "NULL argument");
+  if (row0 < 0 || nrows < 0 || row0 + static_cast<int64_t>(nrows) > p->n3) return fail(XM_EINVAL, "row range out of bounds");
+  if (nrows == 0) return XM_OK;
+  hipStream_t s = as_stream(stream);
+  XM_HIP(hipMemcpy2DAsync(out, p->n3 * sizeof(double), p->Q64.ptr + static_cast<int64_t>(row0) * p->ld,
+                          p->ld * sizeof(double), p->n3 * sizeof(double), nrows, hipMemcpyDeviceToDevice, s));
+  XM_HIP(hipStreamSynchronize(s));
+  return XM_OK;
+  XM_API_CATCH
+}
+
+xm_status xm_spmm(xm_problem* p, xm_dtype dtype, const double* Y, int32_t r, double* out, void* stream) {
+  XM_API_TRY
+  if (!p || !Y || !out) return fail(XM_EINVAL, "NULL argument");
+  if (r < 1 || r > 8) return fail(XM_EINVAL, "r must be in [1, 8]");
+  hipStream_t s = as_stream(stream);
+  const int n = p->n3;
+  if (dtype == XM_F64) {
+    xm::DevBuf<double> Yt(static_cast<size_t>(n) * r), G(static_cast<size_t>(n) * r);
+    xm::transpose_rows<double, double>(Y, r, n, Yt.ptr, s);
+    xm::spmm_yt<double>(p, XM_F64, Yt.ptr, r, G.ptr, s);
+    xm::transpose_rows<double, double>(G.ptr, n, r, out, s);
+    XM_HIP(hipStreamSynchronize(s));
+  } else if (dtype == XM_F32 || dtype == XM_BF16) {
+    xm::DevBuf<float> Yt(static_cast<size_t>(n) * r), G(static_cast<size_t>(n) * r);
+    xm::transpose_rows<double, float>(Y, r, n, Yt.ptr, s);
+    xm::spmm_yt<float>(p, dtype, Yt.ptr, r, G.ptr, s);
+    xm::transpose_rows<float, double>(G.ptr, n, r, out, s);
+    XM_HIP(hipStreamSynchronize(s));
+  } else {
+    return fail(XM_EINVAL, "unknown dtype");
+  }
+  return XM_OK;
+  XM_API_CATCH
+}
+
+void xm_default_opts(xm_solve_opts* o) {
+  if (!o) return;
+  *o = xm_solve_opts{};
+  o->r0 = 5;
+  o->r_max = 7;
+  o->lift = 1.0;
+  o->compute = XM_F64;
+  o->grad_tol = 0.0;
+  o->cert_tol = 0.0;
+  o->max_outer = 0;
+  o->max_inner = 0;
+  o->delta0 = 0.0;
+  o->lanczos_max = 0;
+  o->lanczos_tol = 0.0;
+  o->verbose = 0;
+}
+
+xm_status xm_bm_solve(xm_problem* p, const xm_solve_opts* opts, const double* Y0, int32_t r_in, double* Y_out,
+                      xm_solve_info* info, void* stream) {
+  XM_API_TRY
+  if (!p || !opts) return fail(XM_EINVAL, "NULL argument");
+  const xm_status st = xm::bm_solve(p, *opts, Y0, r_in, Y_out, info, as_stream(stream));
+  if (st == XM_ENOCONV) g_err = "iteration cap reached before the gradient tolerance";
+  return st;
+  XM_API_CATCH
+}
+
+xm_status xm_certify(xm_problem* p, const double* Y, int32_t r, double tol, int32_t max_iter, double* v_min,
+                     xm_cert* cert, void* stream) {
+  XM_API_TRY
+  if (!p || !Y || !cert) return fail(XM_EINVAL, "NULL argument");
+  if (r < 1 || r > 8) return fail(XM_EINVAL, "r must be in [1, 8]");
+  hipStream_t s = as_stream(stream);
+  const int n = p->n3;
+  xm::DevBuf<double> Yt(static_cast<size_t>(n) * r);
+  xm::transpose_rows<double, double>(Y, r, n, Yt.ptr, s);
+  const double t = (tol > 0) ? tol : 1e-7;
+  const xm::CertResult c = xm::certify_yt(p, Yt.ptr, r, t, max_iter, 0.0, v_min, s);
+  cert->lambda_min = c.lambda_min;
+  cert->ritz_residual = c.ritz_residual;
+  cert->primal = c.primal;
+  cert->dual = c.dual;
+  cert->qbar = p->qbar;
+  cert->grad_norm = c.stat_res;
+  cert->certified = c.certified ? 1 : 0;
+  cert->iters = c.iters;
+  return XM_OK;
+  XM_API_CATCH
+}
+
+xm_status xm_round(xm_problem* p, const double* Y, int32_t r, double* R_out, double* s_out, double* rho_hat,
+                   void* stream) {
+  XM_API_TRY
+  if (!p) return fail(XM_EINVAL, "NULL argument");
+  xm::round_yt(p, Y, r, R_out, s_out, rho_hat, as_stream(stream));
+  return XM_OK;
+  XM_API_CATCH
+}
+
+xm_status xm_spmm_timing(xm_problem* p, int32_t enable) {
+  XM_API_TRY
+  if (!p) return fail(XM_EINVAL, "NULL argument");
+  p->timing = enable != 0;
+  return XM_OK;
+  XM_API_CATCH
+}
+
+xm_status xm_spmm_stats(xm_problem* p, xm_spmm_counters* out, int32_t reset) {
+  XM_API_TRY
+  if (!p || !out) return fail(XM_EINVAL, "NULL argument");
+  *out = xm_spmm_counters{};
+  const double elems = static_cast<double>(p->n3) * static_cast<double>(p->n3);
+  out->bytes_per_launch[XM_F64] = elems * 8.0;
+  out->bytes_per_launch[XM_F32] = elems * 4.0;
+  out->bytes_per_launch[XM_BF16] = elems * 2.0;
+  for (size_t i = 0; i < p->events_used; ++i) {
+    auto& e = p->events[i];
+    XM_HIP(hipEventSynchronize(e.stop));
+    float ms = 0.f;
+    XM_HIP(hipEventElapsedTime(&ms, e.start, e.stop));
+    out->launches[e.dtype] += 1;
+    out->total_ms[e.dtype] += ms;
+  }
+  if (reset) p->events_used = 0;
+  return XM_OK;
+  XM_API_CATCH
+}
+
+const char* xm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

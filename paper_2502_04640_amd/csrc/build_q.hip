@@ -1,0 +1,664 @@
+// Assembly of the rotation-only data matrix Q (Prop. "Scaled-Rotation-Only
+// Formulation", App. A) on the GPU, in FP64.
+//
+// With h = [u; 1], the SBA cost of one landmark k with observations O_k and
+// total weight W_k = sum w, minimised over p_k, is
+//   sum_{o,o' in O_k} (delta_oo' w_o - w_o w_o' / W_k) x_{i(o)} h_o . x_{i(o')} h_o'
+// for x_i = [Y_i, t_i] (r x 4).  Every ordered observation pair of a landmark
+// therefore adds a 4x4 block to the frame pair (i(o), i(o')) of a 4N x 4N
+// matrix H; its rotation part is A_rr, its mixed part A_rt and its
+// translation part the weighted co-visibility Laplacian A_tt.  The
+// translations are then removed with frame 0 grounded:
+//   Q = A_rr - A_rt[:,1:] A_tt[1:,1:]^{-1} A_rt[:,1:]^T.
+//
+// GPU steps (no global atomics; the reduction order is fixed, so Q is
+// bitwise reproducible):
+//   validate -> radix-sort observations by landmark -> per-landmark weight
+//   and pair counts -> emit (frame pair key, observation pair) for every
+//   ordered pair -> radix-sort by key -> one wavefront per distinct frame
+//   pair sums its 4x4 contributions (lane-strided, butterfly reduction) and
+//   writes the A_rr block into Q, the A_rt / A_tt entries into the sparse
+//   pattern -> dense grounded Laplacian G -> in-place block sweep
+//   (Gauss-Jordan) to -G^{-1} -> P = A_rt G^{-1} and Q -= P A_rt^T by two
+//   sparse-row x dense products -> symmetrise -> tr(Q) -> FP32/BF16 copies.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "problem.h"
+
+namespace xm {
+namespace {
+
+constexpr int kB = 256;
+
+// ---------------------------------------------------------------------------
+__global__ void validate_kernel(int32_t N, int32_t M, int64_t n, const int32_t* __restrict__ frame,
+                                const int32_t* __restrict__ landmark, const void* __restrict__ u,
+                                int u_f32, const void* __restrict__ w, int w_f32, int* flags) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (e >= n) return;
+  const int32_t f = frame[e], l = landmark[e];
+  if (f < 0 || f >= N || l < 0 || l >= M) flags[0] = 1;
+  double a, b, c;
+  if (u_f32) {
+    const float* uf = static_cast<const float*>(u);
+    a = uf[3 * e]; b = uf[3 * e + 1]; c = uf[3 * e + 2];
+  } else {
+    const double* ud = static_cast<const double*>(u);
+    a = ud[3 * e]; b = ud[3 * e + 1]; c = ud[3 * e + 2];
+  }
+  if (!isfinite(a) || !isfinite(b) || !isfinite(c)) flags[1] = 1;
+  if (w) {
+    const double wv = w_f32 ? static_cast<double>(static_cast<const float*>(w)[e])
+                            : static_cast<const double*>(w)[e];
+    if (!(wv > 0.0) || !isfinite(wv)) flags[2] = 1;
+  }
+}
+
+__global__ void iota_kernel(const int32_t* __restrict__ landmark, int64_t n, uint32_t* keys,
+                            uint64_t* vals) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (e >= n) return;
+  keys[e] = static_cast<uint32_t>(landmark[e]);
+  vals[e] = static_cast<uint64_t>(e);
+}
+
+__global__ void gather_obs_kernel(const uint64_t* __restrict__ order, int64_t n,
+                                  const int32_t* __restrict__ frame, const int32_t* __restrict__ landmark,
+                                  const void* __restrict__ u, int u_f32, const void* __restrict__ w,
+                                  int w_f32, int32_t* fr_s, int32_t* lm_s, double* u_s, double* w_s,
+                                  int64_t* perm) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (p >= n) return;
+  const int64_t o = static_cast<int64_t>(order[p]);
+  perm[p] = o;
+  fr_s[p] = frame[o];
+  lm_s[p] = landmark[o];
+  if (u_f32) {
+    const float* uf = static_cast<const float*>(u);
+    u_s[3 * p] = uf[3 * o]; u_s[3 * p + 1] = uf[3 * o + 1]; u_s[3 * p + 2] = uf[3 * o + 2];
+  } else {
+    const double* ud = static_cast<const double*>(u);
+    u_s[3 * p] = ud[3 * o]; u_s[3 * p + 1] = ud[3 * o + 1]; u_s[3 * p + 2] = ud[3 * o + 2];
+  }
+  w_s[p] = w ? (w_f32 ? static_cast<double>(static_cast<const float*>(w)[o])
+                      : static_cast<const double*>(w)[o])
+             : 1.0;
+}
+
+// ptr[k] = first position p with seg(p) >= k, for k in [0, nseg]; seg() sorted.
+__global__ void segment_offsets_kernel(const int32_t* __restrict__ seg, int64_t n, int64_t nseg,
+                                       int64_t* ptr) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (p > n) return;
+  const int64_t lo = (p == 0) ? 0 : static_cast<int64_t>(seg[p - 1]) + 1;
+  const int64_t hi = (p == n) ? nseg : static_cast<int64_t>(seg[p]);
+  for (int64_t k = lo; k <= hi; ++k) ptr[k] = p;
+}
+
+__global__ void landmark_stats_kernel(const int64_t* __restrict__ lm_ptr, int32_t M,
+                                      const double* __restrict__ w_s, double* Wl, int64_t* cnt) {
+  const int k = blockIdx.x * kB + threadIdx.x;
+  if (k >= M) return;
+  const int64_t a = lm_ptr[k], b = lm_ptr[k + 1];
+  double W = 0.0;
+  for (int64_t p = a; p < b; ++p) W += w_s[p];
+  Wl[k] = W;
+  const int64_t L = b - a;
+  cnt[k] = (L >= 2) ? L * L : 0;
+}
+
+__global__ void emit_pairs_kernel(const int64_t* __restrict__ lm_ptr, int32_t M, int32_t N,
+                                  const int32_t* __restrict__ fr_s, const int64_t* __restrict__ poff,
+                                  uint32_t* keys, uint64_t* vals) {
+  const int k = blockIdx.x * kB + threadIdx.x;
+  if (k >= M) return;
+  const int64_t p0 = lm_ptr[k], L = lm_ptr[k + 1] - p0;
+  if (L < 2) return;
+  int64_t q = poff[k];
+  for (int64_t a = 0; a < L; ++a) {
+    const uint32_t fa = static_cast<uint32_t>(fr_s[p0 + a]) * static_cast<uint32_t>(N);
+    for (int64_t b = 0; b < L; ++b, ++q) {
+      keys[q] = fa + static_cast<uint32_t>(fr_s[p0 + b]);
+      vals[q] = (static_cast<uint64_t>(p0 + a) << 32) | static_cast<uint64_t>(p0 + b);
+    }
+  }
+}
+
+__global__ void head_flags_kernel(const uint32_t* __restrict__ keys, int64_t n, int64_t* flags) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (p >= n) return;
+  flags[p] = (p == 0 || keys[p] != keys[p - 1]) ? 1 : 0;
+}
+
+__global__ void segment_starts_kernel(const uint32_t* __restrict__ keys, const int64_t* __restrict__ sidx,
+                                      int64_t n, int64_t* seg_start, uint32_t* seg_key) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (p > n) return;
+  if (p == n) {
+    seg_start[sidx[n]] = n;
+    return;
+  }
+  if (p == 0 || keys[p] != keys[p - 1]) {
+    seg_start[sidx[p]] = p;
+    seg_key[sidx[p]] = keys[p];
+  }
+}
+
+// One wavefront per frame pair: sum the 4x4 contributions of its observation
+// pairs, write the rotation block into Q and the A_rt / A_tt entries.
+__global__ __launch_bounds__(kB) void reduce_blocks_kernel(
+    const int64_t* __restrict__ seg_start, const uint32_t* __restrict__ seg_key, int64_t S, int32_t N,
+    const uint64_t* __restrict__ vals, const double* __restrict__ u_s, const double* __restrict__ w_s,
+    const int32_t* __restrict__ lm_s, const double* __restrict__ Wl, double* Q, int32_t ld,
+    double* Art, double* Att) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * (kB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (s >= S) return;
+  const int64_t lo = seg_start[s], hi = seg_start[s + 1];
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int64_t q = lo + lane; q < hi; q += 64) {
+    const uint64_t v = vals[q];
+    const int64_t pa = static_cast<int64_t>(v >> 32), pb = static_cast<int64_t>(v & 0xffffffffull);
+    const double wa = w_s[pa], wb = w_s[pb];
+    const double Wk = Wl[lm_s[pa]];
+    const double coef = ((pa == pb) ? wa : 0.0) - wa * wb / Wk;
+    const double ha[4] = {u_s[3 * pa], u_s[3 * pa + 1], u_s[3 * pa + 2], 1.0};
+    const double hb[4] = {u_s[3 * pb], u_s[3 * pb + 1], u_s[3 * pb + 2], 1.0};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double ca = coef * ha[a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a * 4 + b] += ca * hb[b];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = wave_sum(acc[q]);
+  if (lane == 0) {
+    const uint32_t key = seg_key[s];
+    const int64_t i = key / static_cast<uint32_t>(N), j = key % static_cast<uint32_t>(N);
+    double* Qb = Q + (3 * i) * static_cast<int64_t>(ld) + 3 * j;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Qb[a * static_cast<int64_t>(ld) + b] = acc[a * 4 + b];
+    Art[3 * s] = acc[3];
+    Art[3 * s + 1] = acc[7];
+    Art[3 * s + 2] = acc[11];
+    Att[s] = acc[15];
+  }
+}
+
+__global__ void pattern_kernel(const uint32_t* __restrict__ seg_key, int64_t S, int32_t N,
+                               int32_t* row_ptr, int32_t* col) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (p > S) return;
+  const int64_t lo = (p == 0) ? 0 : static_cast<int64_t>(seg_key[p - 1] / static_cast<uint32_t>(N)) + 1;
+  const int64_t hi = (p == S) ? N : static_cast<int64_t>(seg_key[p] / static_cast<uint32_t>(N));
+  for (int64_t k = lo; k <= hi; ++k) row_ptr[k] = static_cast<int32_t>(p);
+  if (p < S) col[p] = static_cast<int32_t>(seg_key[p] % static_cast<uint32_t>(N));
+}
+
+// A frame must have a positive diagonal Laplacian entry (otherwise it has no
+// pair observation and its pose is unconstrained).
+__global__ void check_diag_kernel(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                  const double* __restrict__ Att, int32_t N, int* flags) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= N) return;
+  bool ok = false;
+  for (int32_t s = row_ptr[i]; s < row_ptr[i + 1]; ++s)
+    if (col[s] == i) ok = Att[s] > 0.0;
+  if (!ok) flags[3] = 1;
+}
+
+__global__ void scatter_grounded_kernel(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                        const double* __restrict__ Att, int32_t N, double* G, int32_t ldg) {
+  const int i = blockIdx.x;  // frame row
+  if (i == 0 || i >= N) return;
+  for (int32_t s = row_ptr[i] + threadIdx.x; s < row_ptr[i + 1]; s += blockDim.x) {
+    const int j = col[s];
+    if (j >= 1) G[static_cast<int64_t>(i - 1) * ldg + (j - 1)] = Att[s];
+  }
+}
+
+// ---- block sweep (in-place inversion of the SPD grounded Laplacian) --------
+// Sweeping the pivot set K of a symmetric A:
+//   A_KK <- -A_KK^{-1}, A_iK <- A_iK A_KK^{-1}, A_Kj <- A_KK^{-1} A_Kj,
+//   A_ij <- A_ij - A_iK A_KK^{-1} A_Kj   (i, j not in K).
+// Sweeping every index in turn leaves -A^{-1}.
+constexpr int kNB = 64;
+
+__global__ __launch_bounds__(kB) void sweep_pivot_kernel(const double* __restrict__ A, int32_t lda,
+                                                         int32_t k0, int32_t nb, double dscale,
+                                                         double* Dinv, int* flags) {
+  __shared__ double D[kNB][kNB + 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < nb * nb; e += kB) D[e / nb][e % nb] = A[static_cast<int64_t>(k0 + e / nb) * lda + k0 + e % nb];
+  __syncthreads();
+  for (int p = 0; p < nb; ++p) {
+    const double d = D[p][p];
+    if (!(d > 1e-11 * dscale)) {
+      if (t == 0) flags[4] = 1;
+      return;  // uniform across the block: every thread read the same d
+    }
+    // update all (i, j) != p using the old row/column p
+    double upd[(kNB * kNB) / kB];
+    int c = 0;
+    for (int e = t; e < nb * nb; e += kB, ++c) {
+      const int i = e / nb, j = e % nb;
+      upd[c] = (i != p && j != p) ? D[i][j] - D[i][p] * D[p][j] / d : D[i][j];
+    }
+    __syncthreads();
+    c = 0;
+    for (int e = t; e < nb * nb; e += kB, ++c) {
+      const int i = e / nb, j = e % nb;
+      if (i != p && j != p) D[i][j] = upd[c];
+    }
+    __syncthreads();
+    if (t < nb && t != p) {
+      D[t][p] /= d;
+      D[p][t] /= d;
+    }
+    if (t == 0) D[p][p] = -1.0 / d;
+    __syncthreads();
+  }
+  for (int e = t; e < nb * nb; e += kB) Dinv[e] = -D[e / nb][e % nb];
+}
+
+// Ct[q][i] = sum_p A[i][k0+p] Dinv[p][q] (0 for i in K); Pt[q][i] = A[i][k0+q].
+__global__ __launch_bounds__(kB) void sweep_panel_kernel(const double* __restrict__ A, int32_t lda, int32_t n,
+                                                         int32_t k0, int32_t nb, const double* __restrict__ Dinv,
+                                                         double* Ct, double* Pt, int32_t ldt) {
+  __shared__ double Ds[kNB * kNB];
+  for (int e = threadIdx.x; e < nb * nb; e += kB) Ds[e] = Dinv[e];
+  __syncthreads();
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= n || q >= nb) return;
+  const double* Ai = A + static_cast<int64_t>(i) * lda + k0;
+  double acc = 0.0;
+  for (int p = 0; p < nb; ++p) acc += Ai[p] * Ds[p * nb + q];
+  const bool inK = (i >= k0 && i < k0 + nb);
+  Ct[static_cast<int64_t>(q) * ldt + i] = inK ? 0.0 : acc;
+  Pt[static_cast<int64_t>(q) * ldt + i] = Ai[q];
+}
+
+// A[i][j] -= sum_p Ct[p][i] Pt[p][j] over a 64 x 64 tile (4 x 4 per thread).
+__global__ __launch_bounds__(kB) void sweep_update_kernel(double* A, int32_t lda, int32_t n,
+                                                          const double* __restrict__ Ct,
+                                                          const double* __restrict__ Pt, int32_t ldt,
+                                                          int32_t nb) {
+  __shared__ double Cs[kNB][64];
+  __shared__ double Ps[kNB][64];
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int t = threadIdx.x;
+  for (int e = t; e < nb * 64; e += kB) {
+    const int p = e / 64, c = e % 64;
+    Cs[p][c] = (i0 + c < n) ? Ct[static_cast<int64_t>(p) * ldt + i0 + c] : 0.0;
+    Ps[p][c] = (j0 + c < n) ? Pt[static_cast<int64_t>(p) * ldt + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int tx = t & 15, ty = t >> 4;
+  double acc[4][4] = {};
+  for (int p = 0; p < nb; ++p) {
+    double a[4], b[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      a[q] = Cs[p][ty * 4 + q];
+      b[q] = Ps[p][tx * 4 + q];
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int i = i0 + ty * 4 + x;
+    if (i >= n) continue;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int j = j0 + tx * 4 + y;
+      if (j < n) A[static_cast<int64_t>(i) * lda + j] -= acc[x][y];
+    }
+  }
+}
+
+__global__ void sweep_finish_kernel(double* A, int32_t lda, int32_t n, int32_t k0, int32_t nb,
+                                    const double* __restrict__ Ct, int32_t ldt,
+                                    const double* __restrict__ Dinv) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  const int p = blockIdx.y;
+  if (i >= n || p >= nb) return;
+  if (i >= k0 && i < k0 + nb) {
+    A[static_cast<int64_t>(k0 + p) * lda + i] = -Dinv[p * nb + (i - k0)];
+  } else {
+    const double c = Ct[static_cast<int64_t>(p) * ldt + i];
+    A[static_cast<int64_t>(i) * lda + k0 + p] = c;
+    A[static_cast<int64_t>(k0 + p) * lda + i] = c;
+  }
+}
+
+// ---- sparse rows x dense:  out[3i+a][c] (+)= sum_{s in row i, j >= 1} Art[s][a] D[j-1][c]
+constexpr int kVPT = 4;
+__global__ __launch_bounds__(kB) void gather_product_kernel(const int32_t* __restrict__ row_ptr,
+                                                            const int32_t* __restrict__ col,
+                                                            const double* __restrict__ Art,
+                                                            const double* __restrict__ D, int32_t ldd,
+                                                            int32_t K, double* out, int32_t ldo,
+                                                            int accumulate) {
+  const int i = blockIdx.y;
+  const int c0 = blockIdx.x * (kB * kVPT) + threadIdx.x;
+  double acc[3][kVPT] = {};
+  const int32_t s0 = row_ptr[i], s1 = row_ptr[i + 1];
+  for (int32_t s = s0; s < s1; ++s) {
+    const int j = col[s];
+    if (j == 0) continue;
+    const double a0 = Art[3 * s], a1 = Art[3 * s + 1], a2 = Art[3 * s + 2];
+    const double* Dj = D + static_cast<int64_t>(j - 1) * ldd;
+#pragma unroll
+    for (int v = 0; v < kVPT; ++v) {
+      const int c = c0 + v * kB;
+      const double d = (c < K) ? Dj[c] : 0.0;
+      acc[0][v] += a0 * d;
+      acc[1][v] += a1 * d;
+      acc[2][v] += a2 * d;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double* o = out + static_cast<int64_t>(3 * i + a) * ldo;
+#pragma unroll
+    for (int v = 0; v < kVPT; ++v) {
+      const int c = c0 + v * kB;
+      if (c < K) {
+        if (accumulate) o[c] += acc[a][v];
+        else o[c] = acc[a][v];
+      }
+    }
+  }
+}
+
+// out[c][r] = in[r][c]  (64 x 64 tiles through LDS)
+__global__ __launch_bounds__(kB) void transpose_kernel(const double* __restrict__ in, int32_t rows, int32_t cols,
+                                                       int32_t ldi, double* out, int32_t ldo) {
+  __shared__ double tile[64][65];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += kB) {
+    const int r = e / 64, c = e % 64;
+    tile[r][c] = (r0 + r < rows && c0 + c < cols) ? in[static_cast<int64_t>(r0 + r) * ldi + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += kB) {
+    const int c = e / 64, r = e % 64;
+    if (r0 + r < rows && c0 + c < cols) out[static_cast<int64_t>(c0 + c) * ldo + r0 + r] = tile[r][c];
+  }
+}
+
+// Q <- (Q + Q^T) / 2, one 32 x 32 tile pair (I <= J) per block.
+__global__ __launch_bounds__(kB) void symmetrize_kernel(double* Q, int32_t n, int32_t ld) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I > J) return;
+  __shared__ double a[32][33], b[32][33];
+  const int r0 = I * 32, c0 = J * 32;
+  for (int e = threadIdx.x; e < 32 * 32; e += kB) {
+    const int r = e / 32, c = e % 32;
+    a[r][c] = (r0 + r < n && c0 + c < n) ? Q[static_cast<int64_t>(r0 + r) * ld + c0 + c] : 0.0;  // tile (I, J)
+    b[r][c] = (c0 + r < n && r0 + c < n) ? Q[static_cast<int64_t>(c0 + r) * ld + r0 + c] : 0.0;  // tile (J, I)
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += kB) {
+    const int r = e / 32, c = e % 32;
+    if (r0 + r < n && c0 + c < n) {
+      const double m = 0.5 * (a[r][c] + b[c][r]);
+      Q[static_cast<int64_t>(r0 + r) * ld + c0 + c] = m;
+      Q[static_cast<int64_t>(c0 + c) * ld + r0 + r] = m;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kB) void trace_kernel(const double* __restrict__ Q, int32_t n, int32_t ld,
+                                                   double* out) {
+  __shared__ double lds[4];
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < n; i += kB) v[0] += Q[static_cast<int64_t>(i) * ld + i];
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) out[0] = v[0];
+}
+
+__global__ void to_f32_kernel(const double* __restrict__ in, int64_t n, float* out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (e < n) out[e] = static_cast<float>(in[e]);
+}
+
+// round-to-nearest-even FP64 -> BF16 (through FP32; NaN not expected here)
+__global__ void to_bf16_kernel(const double* __restrict__ in, int64_t n, uint16_t* out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (e >= n) return;
+  const uint32_t x = __float_as_uint(static_cast<float>(in[e]));
+  const uint32_t lsb = (x >> 16) & 1u;
+  out[e] = static_cast<uint16_t>((x + 0x7fffu + lsb) >> 16);
+}
+
+int bits_for(uint64_t v) {  // number of bits needed to represent values < v
+  int b = 1;
+  while (b < 64 && (uint64_t(1) << b) < v) ++b;
+  return b;
+}
+
+}  // namespace
+
+std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame,
+                                          const int32_t* landmark, const void* u, xm_dtype u_dtype,
+                                          const void* w, xm_dtype w_dtype, uint32_t copies,
+                                          hipStream_t s) {
+  require(N >= 2 && N < 65536, XM_EINVAL, "N must be in [2, 65535]");
+  require(M >= 1, XM_EINVAL, "M must be >= 1");
+  require(n_obs >= 1 && n_obs < (int64_t(1) << 31), XM_EINVAL, "n_obs must be in [1, 2^31)");
+  require(frame && landmark && u, XM_EINVAL, "frame, landmark and u must be non-NULL");
+  require(u_dtype == XM_F64 || u_dtype == XM_F32, XM_EINVAL, "u_dtype must be XM_F64 or XM_F32");
+  require(!w || w_dtype == XM_F64 || w_dtype == XM_F32, XM_EINVAL, "w_dtype must be XM_F64 or XM_F32");
+  require((copies & ~(XM_KEEP_F32 | XM_KEEP_BF16 | 1u)) == 0, XM_EINVAL, "unknown bits in copies");
+
+  hipEvent_t ev0, ev1;
+  XM_HIP(hipEventCreate(&ev0));
+  XM_HIP(hipEventCreate(&ev1));
+  XM_HIP(hipEventRecord(ev0, s));
+
+  auto P = std::make_unique<xm_problem>();
+  P->N = N; P->M = M; P->n_obs = n_obs; P->n3 = 3 * N;
+  P->ld = static_cast<int32_t>(round_up(3 * static_cast<size_t>(N), 64));
+  const int u32 = (u_dtype == XM_F32), w32 = (w_dtype == XM_F32);
+  const int64_t n = n_obs;
+
+  // a1: validate
+  DevBuf<int> flags(8);
+  XM_HIP(hipMemsetAsync(flags.ptr, 0, 8 * sizeof(int), s));
+  hipLaunchKernelGGL(validate_kernel, dim3(cdiv(n, kB)), dim3(kB), 0, s, N, M, n, frame, landmark, u, u32,
+                     w, w32, flags.ptr);
+  XM_LAUNCH_CHECK("validate_kernel");
+  int hflags[8];
+  XM_HIP(hipMemcpyAsync(hflags, flags.ptr, sizeof(hflags), hipMemcpyDeviceToHost, s));
+  XM_HIP(hipStreamSynchronize(s));
+  require(!hflags[0], XM_EINVAL, "frame or landmark index out of range");
+  require(!hflags[1], XM_EINVAL, "non-finite keypoint u");
+  require(!hflags[2], XM_EINVAL, "weights must be finite and > 0");
+
+  // a1: sort observations by landmark
+  {
+    DevBuf<uint32_t> keys(n), ktmp(n);
+    DevBuf<uint64_t> vals(n), vtmp(n);
+    hipLaunchKernelGGL(iota_kernel, dim3(cdiv(n, kB)), dim3(kB), 0, s, landmark, n, keys.ptr, vals.ptr);
+    XM_LAUNCH_CHECK("iota_kernel");
+    radix_sort_pairs(keys.ptr, vals.ptr, ktmp.ptr, vtmp.ptr, n, bits_for(static_cast<uint64_t>(M)), s);
+    P->fr_s.alloc(n); P->lm_s.alloc(n); P->u_s.alloc(3 * n); P->w_s.alloc(n); P->perm.alloc(n);
+    hipLaunchKernelGGL(gather_obs_kernel, dim3(cdiv(n, kB)), dim3(kB), 0, s, vals.ptr, n, frame, landmark, u,
+                       u32, w, w32, P->fr_s.ptr, P->lm_s.ptr, P->u_s.ptr, P->w_s.ptr, P->perm.ptr);
+    XM_LAUNCH_CHECK("gather_obs_kernel");
+    XM_HIP(hipStreamSynchronize(s));
+  }
+  P->lm_ptr.alloc(M + 1);
+  hipLaunchKernelGGL(segment_offsets_kernel, dim3(cdiv(n + 1, kB)), dim3(kB), 0, s, P->lm_s.ptr, n,
+                     static_cast<int64_t>(M), P->lm_ptr.ptr);
+  XM_LAUNCH_CHECK("segment_offsets_kernel");
+  P->Wl.alloc(M);
+  DevBuf<int64_t> poff(M + 1);
+  hipLaunchKernelGGL(landmark_stats_kernel, dim3(cdiv(M, kB)), dim3(kB), 0, s, P->lm_ptr.ptr, M, P->w_s.ptr,
+                     P->Wl.ptr, poff.ptr);
+  XM_LAUNCH_CHECK("landmark_stats_kernel");
+  exclusive_scan_i64(poff.ptr, poff.ptr, M, s);
+  int64_t npairs = 0;
+  XM_HIP(hipMemcpyAsync(&npairs, poff.ptr + M, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  XM_HIP(hipStreamSynchronize(s));
+  require(npairs > 0, XM_EGRAPH, "no landmark is observed twice");
+  require(npairs < (int64_t(1) << 31), XM_EINVAL, "too many observation pairs (sum of squared track lengths)");
+  P->n_pairs = npairs;
+
+  // a2-i: emit and sort observation pairs by frame pair
+  DevBuf<uint32_t> pkeys(npairs);
+  DevBuf<uint64_t> pvals(npairs);
+  {
+    DevBuf<uint32_t> ktmp(npairs);
+    DevBuf<uint64_t> vtmp(npairs);
+    hipLaunchKernelGGL(emit_pairs_kernel, dim3(cdiv(M, kB)), dim3(kB), 0, s, P->lm_ptr.ptr, M, N, P->fr_s.ptr,
+                       poff.ptr, pkeys.ptr, pvals.ptr);
+    XM_LAUNCH_CHECK("emit_pairs_kernel");
+    radix_sort_pairs(pkeys.ptr, pvals.ptr, ktmp.ptr, vtmp.ptr, npairs,
+                     bits_for(static_cast<uint64_t>(N) * static_cast<uint64_t>(N)), s);
+  }
+  poff.release();
+  DevBuf<int64_t> sidx(npairs + 1);
+  hipLaunchKernelGGL(head_flags_kernel, dim3(cdiv(npairs, kB)), dim3(kB), 0, s, pkeys.ptr, npairs, sidx.ptr);
+  XM_LAUNCH_CHECK("head_flags_kernel");
+  exclusive_scan_i64(sidx.ptr, sidx.ptr, npairs, s);
+  int64_t S = 0;
+  XM_HIP(hipMemcpyAsync(&S, sidx.ptr + npairs, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  XM_HIP(hipStreamSynchronize(s));
+  P->nnzb = S;
+  DevBuf<int64_t> seg_start(S + 1);
+  DevBuf<uint32_t> seg_key(S);
+  hipLaunchKernelGGL(segment_starts_kernel, dim3(cdiv(npairs + 1, kB)), dim3(kB), 0, s, pkeys.ptr, sidx.ptr,
+                     npairs, seg_start.ptr, seg_key.ptr);
+  XM_LAUNCH_CHECK("segment_starts_kernel");
+  sidx.release();
+
+  // Q storage (zeroed) and the per-block reduction
+  const size_t qn = static_cast<size_t>(P->n3) * P->ld;
+  P->Q64.alloc(qn);
+  XM_HIP(hipMemsetAsync(P->Q64.ptr, 0, qn * sizeof(double), s));
+  P->Art.alloc(3 * S);
+  P->Att.alloc(S);
+  hipLaunchKernelGGL(reduce_blocks_kernel, dim3(cdiv(S, kB / 64)), dim3(kB), 0, s, seg_start.ptr, seg_key.ptr,
+                     S, N, pvals.ptr, P->u_s.ptr, P->w_s.ptr, P->lm_s.ptr, P->Wl.ptr, P->Q64.ptr, P->ld,
+                     P->Art.ptr, P->Att.ptr);
+  XM_LAUNCH_CHECK("reduce_blocks_kernel");
+  P->row_ptr.alloc(N + 1);
+  P->col.alloc(S);
+  hipLaunchKernelGGL(pattern_kernel, dim3(cdiv(S + 1, kB)), dim3(kB), 0, s, seg_key.ptr, S, N, P->row_ptr.ptr,
+                     P->col.ptr);
+  XM_LAUNCH_CHECK("pattern_kernel");
+  hipLaunchKernelGGL(check_diag_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, P->row_ptr.ptr, P->col.ptr,
+                     P->Att.ptr, N, flags.ptr);
+  XM_LAUNCH_CHECK("check_diag_kernel");
+  XM_HIP(hipMemcpyAsync(hflags, flags.ptr, sizeof(hflags), hipMemcpyDeviceToHost, s));
+  XM_HIP(hipStreamSynchronize(s));
+  pkeys.release(); pvals.release(); seg_start.release(); seg_key.release();
+  require(!hflags[3], XM_EGRAPH, "a frame has no observation shared with another frame");
+
+  // a2-ii: translations.  G = A_tt[1:,1:] (dense), swept to -G^{-1}.
+  const int32_t ng = N - 1;
+  P->ldg = static_cast<int32_t>(round_up(ng, 64));
+  P->Gm.alloc(static_cast<size_t>(ng) * P->ldg);
+  XM_HIP(hipMemsetAsync(P->Gm.ptr, 0, P->Gm.bytes(), s));
+  hipLaunchKernelGGL(scatter_grounded_kernel, dim3(N), dim3(kB), 0, s, P->row_ptr.ptr, P->col.ptr, P->Att.ptr,
+                     N, P->Gm.ptr, P->ldg);
+  XM_LAUNCH_CHECK("scatter_grounded_kernel");
+  {
+    // scale for the pivot test: largest diagonal of G
+    double dscale = 0.0;
+    {
+      // small host loop over the diagonal (N - 1 reads, once)
+      std::vector<double> hd(ng);
+      XM_HIP(hipMemcpy2DAsync(hd.data(), sizeof(double), P->Gm.ptr, (P->ldg + 1) * sizeof(double),
+                              sizeof(double), ng, hipMemcpyDeviceToHost, s));
+      XM_HIP(hipStreamSynchronize(s));
+      for (double v : hd) dscale = std::max(dscale, v);
+    }
+    DevBuf<double> Dinv(kNB * kNB);
+    DevBuf<double> Ct(static_cast<size_t>(kNB) * P->ldg), Pt(static_cast<size_t>(kNB) * P->ldg);
+    const unsigned tiles = cdiv(ng, 64);
+    for (int32_t k0 = 0; k0 < ng; k0 += kNB) {
+      const int32_t nb = std::min(kNB, ng - k0);
+      hipLaunchKernelGGL(sweep_pivot_kernel, dim3(1), dim3(kB), 0, s, P->Gm.ptr, P->ldg, k0, nb, dscale,
+                         Dinv.ptr, flags.ptr);
+      XM_LAUNCH_CHECK("sweep_pivot_kernel");
+      hipLaunchKernelGGL(sweep_panel_kernel, dim3(cdiv(ng, 64), cdiv(nb, 4)), dim3(kB), 0, s, P->Gm.ptr, P->ldg,
+                         ng, k0, nb, Dinv.ptr, Ct.ptr, Pt.ptr, P->ldg);
+      XM_LAUNCH_CHECK("sweep_panel_kernel");
+      hipLaunchKernelGGL(sweep_update_kernel, dim3(tiles, tiles), dim3(kB), 0, s, P->Gm.ptr, P->ldg, ng, Ct.ptr,
+                         Pt.ptr, P->ldg, nb);
+      XM_LAUNCH_CHECK("sweep_update_kernel");
+      hipLaunchKernelGGL(sweep_finish_kernel, dim3(cdiv(ng, kB), nb), dim3(kB), 0, s, P->Gm.ptr, P->ldg, ng, k0,
+                         nb, Ct.ptr, P->ldg, Dinv.ptr);
+      XM_LAUNCH_CHECK("sweep_finish_kernel");
+    }
+    XM_HIP(hipMemcpyAsync(hflags, flags.ptr, sizeof(hflags), hipMemcpyDeviceToHost, s));
+    XM_HIP(hipStreamSynchronize(s));
+    require(!hflags[4], XM_EGRAPH, "the view graph is disconnected (grounded Laplacian is singular)");
+  }
+
+  // P = A_rt[:,1:] (-G^{-1})   (3N x (N-1)), then Pt = P^T, then Q += A_rt[:,1:] Pt
+  {
+    const int32_t ldp = static_cast<int32_t>(round_up(ng, 64));
+    DevBuf<double> Pm(static_cast<size_t>(P->n3) * ldp);
+    hipLaunchKernelGGL(gather_product_kernel, dim3(cdiv(ng, kB * kVPT), N), dim3(kB), 0, s, P->row_ptr.ptr,
+                       P->col.ptr, P->Art.ptr, P->Gm.ptr, P->ldg, ng, Pm.ptr, ldp, 0);
+    XM_LAUNCH_CHECK("gather_product_kernel(P)");
+    DevBuf<double> Ptr(static_cast<size_t>(ng) * P->ld);
+    hipLaunchKernelGGL(transpose_kernel, dim3(cdiv(ng, 64), cdiv(P->n3, 64)), dim3(kB), 0, s, Pm.ptr, P->n3, ng,
+                       ldp, Ptr.ptr, P->ld);
+    XM_LAUNCH_CHECK("transpose_kernel");
+    hipLaunchKernelGGL(gather_product_kernel, dim3(cdiv(P->n3, kB * kVPT), N), dim3(kB), 0, s, P->row_ptr.ptr,
+                       P->col.ptr, P->Art.ptr, Ptr.ptr, P->ld, P->n3, P->Q64.ptr, P->ld, 1);
+    XM_LAUNCH_CHECK("gather_product_kernel(Q)");
+    XM_HIP(hipStreamSynchronize(s));
+  }
+  {
+    const unsigned T = cdiv(P->n3, 32);
+    hipLaunchKernelGGL(symmetrize_kernel, dim3(T, T), dim3(kB), 0, s, P->Q64.ptr, P->n3, P->ld);
+    XM_LAUNCH_CHECK("symmetrize_kernel");
+    DevBuf<double> tr(1);
+    hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(kB), 0, s, P->Q64.ptr, P->n3, P->ld, tr.ptr);
+    XM_LAUNCH_CHECK("trace_kernel");
+    double htr = 0.0;
+    XM_HIP(hipMemcpyAsync(&htr, tr.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
+    XM_HIP(hipStreamSynchronize(s));
+    P->qbar = htr / P->n3;
+  }
+  if (copies & XM_KEEP_F32) {
+    P->Q32.alloc(qn);
+    hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(qn, kB)), dim3(kB), 0, s, P->Q64.ptr, static_cast<int64_t>(qn),
+                       P->Q32.ptr);
+    XM_LAUNCH_CHECK("to_f32_kernel");
+  }
+  if (copies & XM_KEEP_BF16) {
+    P->Q16.alloc(qn);
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(cdiv(qn, kB)), dim3(kB), 0, s, P->Q64.ptr, static_cast<int64_t>(qn),
+                       P->Q16.ptr);
+    XM_LAUNCH_CHECK("to_bf16_kernel");
+  }
+  P->copies = 1u | copies;
+  XM_HIP(hipEventRecord(ev1, s));
+  XM_HIP(hipEventSynchronize(ev1));
+  float ms = 0.f;
+  XM_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+  P->build_ms = ms;
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  return P;
+}
+
+}  // namespace xm

@@ -1,0 +1,342 @@
+// Dual certificate (Theorem "Dual Optimality Certificate"), FP64.
+//
+// The constraint matrices act on the diagonal 3x3 blocks only (App. "Proof of
+// LICQ condition"): sum y_i A_i = blkdiag(Lambda_k), with Lambda_0 symmetric and
+// Lambda_k (k >= 1) symmetric traceless.  Z(y) Y^T = 0 then gives, block by
+// block, Lambda_k = sym((Q Y^T)_k Y_k) / alpha_k (alpha_k = |Y_k|^2 / 3), made
+// traceless for k >= 1.  The dual objective b^T y is tr(Lambda_0).
+//
+// lambda_min(Z) is found by Lanczos on Z = Q - blkdiag(Lambda) restricted to
+// the orthogonal complement of the rows of Y (Z Y^T = 0 at a critical point,
+// so those r directions carry zero eigenvalues): the first r basis vectors
+// are an orthonormal basis of rows(Y), every new Lanczos vector is
+// orthogonalised against all previous ones twice (classical Gram-Schmidt,
+// "twice is enough"), and alpha_j, beta_j stay on the device so that
+// iterations run without host synchronisation.  Every few iterations the host
+// takes the smallest eigenvalue of the tridiagonal T_j by Sturm bisection and
+// its eigenvector by inverse iteration; the Ritz residual is beta_j |y_j|.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "problem.h"
+
+namespace xm {
+namespace {
+
+constexpr int kB = 256;
+
+template <int R>
+__global__ __launch_bounds__(kB) void lambda_kernel(int32_t N, const double* __restrict__ Yt,
+                                                    const double* __restrict__ G, double* __restrict__ Lam,
+                                                    double* part) {
+  const int k = blockIdx.x * kB + threadIdx.x;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (k < N) {
+    double y[3][R], g[3][R];
+    double nn = 0.0;
+    for (int c = 0; c < 3; ++c)
+      for (int a = 0; a < R; ++a) {
+        y[c][a] = Yt[(3 * static_cast<int64_t>(k) + c) * R + a];
+        g[c][a] = G[(3 * static_cast<int64_t>(k) + c) * R + a];
+        nn += y[c][a] * y[c][a];
+        v[1] += y[c][a] * g[c][a];
+      }
+    const double alpha = nn / 3.0;
+    double L[3][3];
+    for (int c = 0; c < 3; ++c)
+      for (int d = 0; d < 3; ++d) {
+        double s = 0.0;
+        for (int a = 0; a < R; ++a) s += g[c][a] * y[d][a];
+        L[c][d] = s / alpha;
+      }
+    for (int c = 0; c < 3; ++c)
+      for (int d = c + 1; d < 3; ++d) L[c][d] = L[d][c] = 0.5 * (L[c][d] + L[d][c]);
+    const double tr = L[0][0] + L[1][1] + L[2][2];
+    if (k > 0)
+      for (int c = 0; c < 3; ++c) L[c][c] -= tr / 3.0;
+    else
+      v[2] = tr;
+    for (int c = 0; c < 3; ++c)
+      for (int d = 0; d < 3; ++d) Lam[9 * static_cast<int64_t>(k) + 3 * c + d] = L[c][d];
+    // stationarity residual (Q Y^T)_k - Lambda_k Y_k^T
+    for (int c = 0; c < 3; ++c)
+      for (int a = 0; a < R; ++a) {
+        double s = g[c][a];
+        for (int d = 0; d < 3; ++d) s -= L[c][d] * y[d][a];
+        v[0] += s * s;
+      }
+  }
+  __shared__ double lds[3 * (kB / 64)];
+  block_sum<3>(v, lds);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) part[blockIdx.x * 3 + q] = v[q];
+}
+
+// w = Qx - blkdiag(Lambda) x
+__global__ void zapply_kernel(int32_t N, const double* __restrict__ Lam, const double* __restrict__ x,
+                              const double* __restrict__ Qx, double* __restrict__ w) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (i >= 3 * static_cast<int64_t>(N)) return;
+  const int64_t k = i / 3;
+  const int c = static_cast<int>(i % 3);
+  const double* L = Lam + 9 * k + 3 * c;
+  w[i] = Qx[i] - (L[0] * x[3 * k] + L[1] * x[3 * k + 1] + L[2] * x[3 * k + 2]);
+}
+
+// c[b] = <V[b], w> (one block per basis vector)
+__global__ __launch_bounds__(kB) void multidot_kernel(const double* __restrict__ V, int64_t n,
+                                                      const double* __restrict__ w, double* __restrict__ c) {
+  const double* Vb = V + static_cast<int64_t>(blockIdx.x) * n;
+  double v[1] = {0.0};
+  for (int64_t i = threadIdx.x; i < n; i += kB) v[0] += Vb[i] * w[i];
+  __shared__ double lds[kB / 64];
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) c[blockIdx.x] = v[0];
+}
+
+// w[i] += sign * sum_b c[b] V[b][i]
+__global__ __launch_bounds__(kB) void multiaxpy_kernel(const double* __restrict__ V, int nv, int64_t n,
+                                                       const double* __restrict__ c, double sign,
+                                                       double* __restrict__ w) {
+  __shared__ double cs[2048];
+  for (int b = threadIdx.x; b < nv; b += kB) cs[b] = c[b];
+  __syncthreads();
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int b = 0; b < nv; ++b) acc += cs[b] * V[static_cast<int64_t>(b) * n + i];
+  w[i] += sign * acc;
+}
+
+// alpha[j] = c1[jj] + c2[jj]; beta[j] = |w|; out = w / beta (single block)
+__global__ __launch_bounds__(1024) void normalize_kernel(const double* __restrict__ w, int64_t n,
+                                                         const double* __restrict__ c1,
+                                                         const double* __restrict__ c2, int jj, double* alpha,
+                                                         double* beta, int j, double* __restrict__ out) {
+  double v[1] = {0.0};
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v[0] += w[i] * w[i];
+  __shared__ double lds[1024 / 64];
+  __shared__ double bsh;
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) {
+    const double b = sqrt(v[0]);
+    bsh = b;
+    if (beta) beta[j] = b;
+    if (alpha) alpha[j] = c1[jj] + c2[jj];
+  }
+  __syncthreads();
+  const double b = bsh;
+  const double inv = (b > 0.0) ? 1.0 / b : 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) out[i] = w[i] * inv;
+}
+
+// column a of Yt ([n][r]) -> w
+__global__ void column_kernel(const double* __restrict__ Yt, int r, int a, int64_t n, double* w) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (i < n) w[i] = Yt[i * r + a];
+}
+
+// deterministic pseudo-random start vector in [-1, 1] (splitmix64 of the index)
+__global__ void random_kernel(int64_t n, uint64_t seed, double* w) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = static_cast<uint64_t>(i) + seed * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  w[i] = static_cast<double>(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// ---- host side --------------------------------------------------------------
+// smallest eigenvalue of the symmetric tridiagonal (d, e) by Sturm bisection
+double tridiag_min_eig(const std::vector<double>& d, const std::vector<double>& e, int n) {
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i < n - 1 ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  const double scale = std::max(std::fabs(lo), std::fabs(hi)) + 1e-300;
+  auto count_below = [&](double x) {
+    int cnt = 0;
+    double q = d[0] - x;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < n; ++i) {
+      if (q == 0.0) q = 1e-300 * scale;
+      q = d[i] - x - e[i - 1] * e[i - 1] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * scale; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= 1) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// eigenvector of the tridiagonal for the eigenvalue theta (inverse iteration;
+// T - sigma I with sigma just below the smallest eigenvalue is positive definite)
+std::vector<double> tridiag_min_vec(const std::vector<double>& d, const std::vector<double>& e, int n,
+                                    double theta) {
+  double scale = 0.0;
+  for (int i = 0; i < n; ++i) scale = std::max(scale, std::fabs(d[i]) + (i < n - 1 ? std::fabs(e[i]) : 0.0));
+  const double sigma = theta - 1e-10 * (scale + 1e-300);
+  std::vector<double> y(n, 1.0), piv(n), rhs(n);
+  for (int it = 0; it < 3; ++it) {
+    // LDL^T-free Thomas solve of (T - sigma I) x = y
+    std::vector<double> cp(n), dp(n);
+    double den = d[0] - sigma;
+    cp[0] = (n > 1) ? e[0] / den : 0.0;
+    dp[0] = y[0] / den;
+    for (int i = 1; i < n; ++i) {
+      den = (d[i] - sigma) - e[i - 1] * cp[i - 1];
+      cp[i] = (i < n - 1) ? e[i] / den : 0.0;
+      dp[i] = (y[i] - e[i - 1] * dp[i - 1]) / den;
+    }
+    std::vector<double> x(n);
+    x[n - 1] = dp[n - 1];
+    for (int i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
+    double nn = 0.0;
+    for (double v : x) nn += v * v;
+    nn = std::sqrt(nn);
+    for (int i = 0; i < n; ++i) y[i] = x[i] / nn;
+  }
+  return y;
+}
+
+template <int R>
+void launch_lambda(int32_t N, const double* Yt, const double* G, double* Lam, double* part, hipStream_t s) {
+  hipLaunchKernelGGL((lambda_kernel<R>), dim3(cdiv(N, kB)), dim3(kB), 0, s, N, Yt, G, Lam, part);
+  XM_LAUNCH_CHECK("lambda_kernel");
+}
+
+}  // namespace
+
+void read_partials(const double* dev, int blocks, int nq, double* out, hipStream_t s) {
+  std::vector<double> h(static_cast<size_t>(blocks) * nq);
+  XM_HIP(hipMemcpyAsync(h.data(), dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  XM_HIP(hipStreamSynchronize(s));
+  for (int q = 0; q < nq; ++q) {
+    double acc = 0.0;
+    for (int b = 0; b < blocks; ++b) acc += h[static_cast<size_t>(b) * nq + q];
+    out[q] = acc;
+  }
+}
+
+CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int max_iter, double lanczos_tol,
+                      double* v_out, hipStream_t s) {
+  require(r >= 1 && r <= 8, XM_EINVAL, "certificate: rank must be in [1, 8]");
+  const int32_t N = p->N;
+  const int64_t n = p->n3;
+  const double qbar = p->qbar;
+  if (max_iter <= 0) max_iter = 400;
+  max_iter = std::min<int>(max_iter, static_cast<int>(std::min<int64_t>(n - r, 2000 - 8)));
+  if (lanczos_tol <= 0) lanczos_tol = 1e-6;
+  CertResult out;
+
+  DevBuf<double> G(n * r), Lam(9 * static_cast<size_t>(N)), part(static_cast<size_t>(cdiv(N, kB)) * 3);
+  spmm_yt<double>(p, XM_F64, Yt, r, G.ptr, s);
+  switch (r) {
+    case 1: launch_lambda<1>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
+    case 2: launch_lambda<2>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
+    case 3: launch_lambda<3>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
+    case 4: launch_lambda<4>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
+    case 5: launch_lambda<5>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
+    case 6: launch_lambda<6>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
+    case 7: launch_lambda<7>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
+    case 8: launch_lambda<8>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
+  }
+  double sums[3];
+  read_partials(part.ptr, cdiv(N, kB), 3, sums, s);
+  out.stat_res = std::sqrt(sums[0]);
+  out.primal = sums[1];
+  out.dual = sums[2];
+
+  // basis: [deflation rows of Y | Lanczos vectors]
+  const int cap = r + max_iter + 1;
+  DevBuf<double> V(static_cast<size_t>(cap) * n), w(n), Qx(n), c1(cap), c2(cap), alpha(max_iter), beta(max_iter);
+  const unsigned gb = cdiv(n, kB);
+  auto orthogonalize = [&](int nv) {  // w -= V[0..nv) (V^T w), twice
+    if (nv == 0) return;
+    hipLaunchKernelGGL(multidot_kernel, dim3(nv), dim3(kB), 0, s, V.ptr, n, w.ptr, c1.ptr);
+    hipLaunchKernelGGL(multiaxpy_kernel, dim3(gb), dim3(kB), 0, s, V.ptr, nv, n, c1.ptr, -1.0, w.ptr);
+    hipLaunchKernelGGL(multidot_kernel, dim3(nv), dim3(kB), 0, s, V.ptr, n, w.ptr, c2.ptr);
+    hipLaunchKernelGGL(multiaxpy_kernel, dim3(gb), dim3(kB), 0, s, V.ptr, nv, n, c2.ptr, -1.0, w.ptr);
+    XM_LAUNCH_CHECK("orthogonalize");
+  };
+  int nb = 0;
+  for (int a = 0; a < r; ++a) {
+    hipLaunchKernelGGL(column_kernel, dim3(gb), dim3(kB), 0, s, Yt, r, a, n, w.ptr);
+    orthogonalize(nb);
+    hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w.ptr, n, c1.ptr, c2.ptr, 0,
+                       static_cast<double*>(nullptr), beta.ptr, 0, V.ptr + static_cast<int64_t>(nb) * n);
+    XM_LAUNCH_CHECK("normalize_kernel");
+    double bn = 0.0;
+    XM_HIP(hipMemcpyAsync(&bn, beta.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
+    XM_HIP(hipStreamSynchronize(s));
+    if (bn > 1e-10 * std::sqrt(static_cast<double>(N))) ++nb;  // skip a dependent row
+  }
+  hipLaunchKernelGGL(random_kernel, dim3(gb), dim3(kB), 0, s, n, static_cast<uint64_t>(12345), w.ptr);
+  orthogonalize(nb);
+  hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w.ptr, n, c1.ptr, c2.ptr, 0,
+                     static_cast<double*>(nullptr), static_cast<double*>(nullptr), 0,
+                     V.ptr + static_cast<int64_t>(nb) * n);
+  XM_LAUNCH_CHECK("normalize_kernel");
+
+  std::vector<double> ha, hbv, d, e, y;
+  double theta = 0.0, res = 0.0;
+  int j = 0;
+  bool done = false;
+  for (j = 0; j < max_iter && !done; ++j) {
+    const double* x = V.ptr + static_cast<int64_t>(nb + j) * n;
+    spmm_yt<double>(p, XM_F64, x, 1, Qx.ptr, s);
+    hipLaunchKernelGGL(zapply_kernel, dim3(gb), dim3(kB), 0, s, N, Lam.ptr, x, Qx.ptr, w.ptr);
+    XM_LAUNCH_CHECK("zapply_kernel");
+    const int nv = nb + j + 1;
+    orthogonalize(nv);
+    hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w.ptr, n, c1.ptr, c2.ptr, nb + j, alpha.ptr,
+                       beta.ptr, j, V.ptr + static_cast<int64_t>(nv) * n);
+    XM_LAUNCH_CHECK("normalize_kernel");
+    const int m = j + 1;
+    if (m % 5 == 0 || m == max_iter) {
+      ha.resize(m);
+      hbv.resize(m);
+      XM_HIP(hipMemcpyAsync(ha.data(), alpha.ptr, m * sizeof(double), hipMemcpyDeviceToHost, s));
+      XM_HIP(hipMemcpyAsync(hbv.data(), beta.ptr, m * sizeof(double), hipMemcpyDeviceToHost, s));
+      XM_HIP(hipStreamSynchronize(s));
+      d.assign(ha.begin(), ha.end());
+      e.assign(hbv.begin(), hbv.end());  // e[i] couples i and i+1; e[m-1] = beta_{m-1} is the residual factor
+      theta = tridiag_min_eig(d, e, m);
+      y = tridiag_min_vec(d, e, m, theta);
+      res = std::fabs(hbv[m - 1] * y[m - 1]);
+      const bool breakdown = hbv[m - 1] <= 1e-14 * (std::fabs(theta) + qbar);
+      const bool converged = res <= lanczos_tol * qbar || res <= 1e-3 * std::fabs(theta);
+      const bool negative = theta + res < -tol * qbar;
+      if (breakdown || converged || negative) done = true;
+    }
+  }
+  out.iters = j;
+  out.lambda_min = theta;
+  out.ritz_residual = res;
+  out.certified = (theta - res) >= -tol * qbar;
+  if (v_out) {
+    const int m = static_cast<int>(y.size());
+    DevBuf<double> yd(m);
+    XM_HIP(hipMemcpyAsync(yd.ptr, y.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
+    XM_HIP(hipMemsetAsync(w.ptr, 0, n * sizeof(double), s));
+    hipLaunchKernelGGL(multiaxpy_kernel, dim3(gb), dim3(kB), 0, s, V.ptr + static_cast<int64_t>(nb) * n, m, n,
+                       yd.ptr, 1.0, w.ptr);
+    XM_LAUNCH_CHECK("multiaxpy_kernel");
+    hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w.ptr, n, c1.ptr, c2.ptr, 0,
+                       static_cast<double*>(nullptr), static_cast<double*>(nullptr), 0, v_out);
+    XM_LAUNCH_CHECK("normalize_kernel");
+    XM_HIP(hipStreamSynchronize(s));
+  }
+  XM_HIP(hipStreamSynchronize(s));
+  return out;
+}
+
+}  // namespace xm

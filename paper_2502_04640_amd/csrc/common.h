@@ -1,0 +1,140 @@
+// Internal definitions shared by the HIP sources of libxm (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/xm.h"
+
+namespace xm {
+
+// ---------------------------------------------------------------------------
+// Errors: C++ exceptions inside the library, converted to xm_status at the ABI.
+struct Error : public std::runtime_error {
+  xm_status code;
+  Error(xm_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+inline void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(XM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define XM_HIP(expr) ::xm::hip_check((expr), #expr)
+#define XM_LAUNCH_CHECK(name) ::xm::hip_check(hipGetLastError(), name)
+
+inline void require(bool ok, xm_status code, const std::string& msg) {
+  if (!ok) throw Error(code, msg);
+}
+
+// ---------------------------------------------------------------------------
+// Owning device buffer.
+template <typename T>
+struct DevBuf {
+  T* ptr = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), n(o.n) { o.ptr = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); ptr = o.ptr; n = o.n; o.ptr = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&ptr), count * sizeof(T));
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      (void)hipGetLastError();
+      throw Error(XM_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) +
+                                 " bytes failed: " + hipGetErrorString(e));
+    }
+    n = count;
+  }
+  // grow-only reallocation (contents are not kept)
+  void ensure(size_t count) {
+    if (count > n) alloc(count);
+  }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+// Pinned host scratch for scalars read back after a stream sync.
+struct HostScalars {
+  double* p = nullptr;
+  size_t n = 0;
+  explicit HostScalars(size_t count = 64) {
+    XM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), count * sizeof(double), hipHostMallocDefault));
+    n = count;
+  }
+  HostScalars(const HostScalars&) = delete;
+  HostScalars& operator=(const HostScalars&) = delete;
+  ~HostScalars() { if (p) (void)hipHostFree(p); }
+};
+
+inline unsigned cdiv(size_t a, size_t b) { return static_cast<unsigned>((a + b - 1) / b); }
+inline size_t round_up(size_t a, size_t b) { return ((a + b - 1) / b) * b; }
+
+// ---------------------------------------------------------------------------
+// Device helpers.
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic block reduction of NQ doubles per thread (fixed tree order).
+// `lds` must hold NQ * (blockDim.x / 64) doubles.  Result valid in thread 0.
+template <int NQ>
+__device__ __forceinline__ void block_sum(double (&v)[NQ], double* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = wave_sum(v[q]);
+  if (lane == 0)
+    for (int q = 0; q < NQ; ++q) lds[q * nw + wid] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < NQ; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += lds[q * nw + w];
+      v[q] = s;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+#endif
+
+// ---------------------------------------------------------------------------
+// Launchers implemented in the .hip files (host-callable).
+
+// sort.hip ------------------------------------------------------------------
+// Stable LSD radix sort of (key, value) pairs by the low `key_bits` bits.
+// keys/vals are sorted in place using the scratch buffers.
+void radix_sort_pairs(uint32_t* keys, uint64_t* vals, uint32_t* keys_tmp, uint64_t* vals_tmp,
+                      int64_t n, int key_bits, hipStream_t s);
+// Exclusive prefix sum of int64 values (in -> out, may alias).  Returns nothing;
+// the total is written to out[n] (out must hold n + 1 entries).
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+
+// reduce.hip ----------------------------------------------------------------
+// Deterministic sum of `parts` rows of `nq` doubles laid out [parts][nq] into out[nq].
+void sum_partials(const double* partials, int parts, int nq, double* out, hipStream_t s);
+
+}  // namespace xm

@@ -1,0 +1,89 @@
+// The problem handle and the internal launch interfaces of libxm.
+#pragma once
+
+#include <memory>
+
+#include "common.h"
+
+struct xm_problem {
+  int32_t N = 0, M = 0;
+  int64_t n_obs = 0;
+  int32_t n3 = 0;   // 3N
+  int32_t ld = 0;   // leading dimension of the dense Q copies (multiple of 64)
+  uint32_t copies = 1;
+  double qbar = 0.0;
+  double build_ms = 0.0;
+  int64_t nnzb = 0, n_pairs = 0;
+
+  // Q, row-major [3N][ld], zero padding columns
+  xm::DevBuf<double> Q64;
+  xm::DevBuf<float> Q32;
+  xm::DevBuf<uint16_t> Q16;
+
+  // observations sorted by landmark (kept for recovery of t, p and the adjoint)
+  xm::DevBuf<int32_t> fr_s, lm_s;
+  xm::DevBuf<double> u_s, w_s;     // [n][3], [n]
+  xm::DevBuf<int64_t> perm;        // sorted position -> original index
+  xm::DevBuf<int64_t> lm_ptr;      // [M+1]
+  xm::DevBuf<double> Wl;           // per-landmark weight sum
+  // co-visibility pattern (rows = frames), with the eliminated-landmark blocks
+  xm::DevBuf<int32_t> row_ptr, col;  // [N+1], [nnzb]
+  xm::DevBuf<double> Art;            // [nnzb][3]: A_rt[3i+a][j]
+  xm::DevBuf<double> Att;            // [nnzb]:    A_tt[i][j]
+  // -(A_tt[1:,1:])^{-1}, row-major [N-1][ldg]
+  xm::DevBuf<double> Gm;
+  int32_t ldg = 0;
+
+  // split-row partial sums of the Y Q product (grown on demand)
+  xm::DevBuf<char> spmm_scratch;
+
+  // optional HIP-event timing of the Y Q product kernel (xm_spmm_timing)
+  struct TimedLaunch {
+    hipEvent_t start, stop;
+    int dtype;
+  };
+  bool timing = false;
+  std::vector<TimedLaunch> events;
+  size_t events_used = 0;
+
+  ~xm_problem();
+};
+
+namespace xm {
+
+// build_q.hip
+std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame,
+                                          const int32_t* landmark, const void* u, xm_dtype u_dtype,
+                                          const void* w, xm_dtype w_dtype, uint32_t copies,
+                                          hipStream_t s);
+
+// spmm.hip: out (3N x r, row-major, frame-major "Yt" layout, ld = r) = Q * Yt.
+// Yt is [3N][r] (row i holds Y[0..r)[i]).  T is the vector precision.
+template <typename T>
+void spmm_yt(const xm_problem* p, xm_dtype qtype, const T* Yt, int r, T* out, hipStream_t s);
+
+// layout conversions between the ABI layout Y[r][3N] and the internal Yt[3N][r]
+template <typename Ts, typename Td>
+void transpose_rows(const Ts* in, int rows, int cols, Td* out, hipStream_t s);
+
+// certify.hip: certificate at Yt (FP64, [3N][r]).
+struct CertResult {
+  double lambda_min = 0, ritz_residual = 0, primal = 0, dual = 0, stat_res = 0;
+  int iters = 0;
+  bool certified = false;
+};
+CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int max_iter, double lanczos_tol,
+                      double* v_out, hipStream_t s);
+
+// solver.hip
+xm_status bm_solve(xm_problem* p, const xm_solve_opts& o, const double* Y0, int r_in, double* Y_out,
+                   xm_solve_info* info, hipStream_t s);
+
+// round.hip
+void round_yt(xm_problem* p, const double* Y, int r, double* R_out, double* s_out, double* rho_hat,
+              hipStream_t s);
+
+// Host sum of per-block partials [blocks][nq] (fixed order) after a stream sync.
+void read_partials(const double* dev, int blocks, int nq, double* out, hipStream_t s);
+
+}  // namespace xm

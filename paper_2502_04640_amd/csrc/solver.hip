@@ -1,0 +1,275 @@
+// Riemannian staircase (Algorithm "Riemannian Staircase") with a trust-region
+// / truncated-CG local optimiser (Absil et al. 2008; Boumal 2023), driven from
+// the host, all vector work in the kernels of manifold.hip / spmm.hip.
+//
+// Parameters the paper leaves open (textbook defaults): tCG stops at
+// |r| <= |r0| min(|r0|^theta, kappa), kappa = 0.1, theta = 1; steps are
+// accepted when rho > 0.1; the radius is quartered when rho < 1/4 and doubled
+// (up to sqrt(3N)) when rho > 3/4 on a boundary step; initial radius
+// sqrt(3N)/8; rho carries the usual max(1,|f|) 1e3 eps regularisation.  The
+// cost decrease is evaluated as <Y+ - Y, Q (Y+ + Y)> from the two products
+// already computed, which stays accurate in FP32 where f(Y+) - f(Y) would
+// cancel.  The staircase escape follows Theorem "Descent Direction": block k of
+// [Y; alpha v^T] is re-orthonormalised (scale kept), alpha halved until the
+// cost drops, at most 40 times.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "manifold.h"
+#include "problem.h"
+
+namespace xm {
+namespace {
+
+template <typename T>
+struct Vecs {
+  int N, rmax;
+  size_t nv;
+  DevBuf<T> Rt, s, Yt, G, Rt2, s2, Yt2, G2, gR, gs, Sc, ec;
+  DevBuf<T> etaR, etas, HetaR, Hetas, resR, ress, dR, ds, HdR, Hds, Ydot, Gd;
+  DevBuf<double> part;
+  Vecs(int n, int rm) : N(n), rmax(rm), nv(static_cast<size_t>(3) * n * rm) {
+    for (DevBuf<T>* b : {&Rt, &Yt, &G, &Rt2, &Yt2, &G2, &gR, &etaR, &HetaR, &resR, &dR, &HdR, &Ydot, &Gd})
+      b->alloc(nv);
+    for (DevBuf<T>* b : {&s, &s2, &gs, &ec, &etas, &Hetas, &ress, &ds, &Hds}) b->alloc(n);
+    Sc.alloc(static_cast<size_t>(9) * n);
+    part.alloc(static_cast<size_t>(cdiv(n, 256)) * 8);
+  }
+};
+
+struct RtrOut {
+  double f = 0, gnorm = 0, ynorm = 0;
+  int outer = 0, inner = 0, spmm = 0;
+  bool converged = false;
+};
+
+template <typename T>
+RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_solve_opts& o, double grad_tol,
+           hipStream_t st) {
+  const int N = p->N;
+  const Manifold<T> mf(N);
+  const int nb = static_cast<int>(mf.blocks());
+  const double qbar = p->qbar;
+  const double Dbar = std::sqrt(3.0 * N);
+  double Delta = (o.delta0 > 0) ? o.delta0 : Dbar / 8.0;
+  const int max_outer = (o.max_outer > 0) ? o.max_outer : 300;
+  const int max_inner = (o.max_inner > 0) ? o.max_inner : std::min(3 * N * r, 2000);
+  const double kappa = 0.1, theta = 1.0, rho_prime = 0.1;
+  RtrOut out;
+  double sums[4];
+
+  mf.scale(r, V.Rt.ptr, V.s.ptr, V.Yt.ptr, st);
+  spmm_yt<T>(p, qg, V.Yt.ptr, r, V.G.ptr, st);
+  ++out.spmm;
+  mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
+  read_partials(V.part.ptr, nb, 3, sums, st);
+  double f = sums[0], gg = sums[1], gnorm = std::sqrt(sums[1]), ynorm = std::sqrt(sums[2]);
+  const size_t nvr = static_cast<size_t>(3) * N * r;
+  int k = 0;
+  for (k = 0; k < max_outer; ++k) {
+    if (gnorm <= grad_tol * qbar * ynorm) {
+      out.converged = true;
+      break;
+    }
+    // ---- truncated CG ----
+    XM_HIP(hipMemsetAsync(V.etaR.ptr, 0, nvr * sizeof(T), st));
+    XM_HIP(hipMemsetAsync(V.etas.ptr, 0, N * sizeof(T), st));
+    XM_HIP(hipMemsetAsync(V.HetaR.ptr, 0, nvr * sizeof(T), st));
+    XM_HIP(hipMemsetAsync(V.Hetas.ptr, 0, N * sizeof(T), st));
+    XM_HIP(hipMemcpyAsync(V.resR.ptr, V.gR.ptr, nvr * sizeof(T), hipMemcpyDeviceToDevice, st));
+    XM_HIP(hipMemcpyAsync(V.ress.ptr, V.gs.ptr, N * sizeof(T), hipMemcpyDeviceToDevice, st));
+    double r_r = gg;
+    const double norm_r0 = std::sqrt(r_r);
+    int mode = 0;
+    double beta = 0.0;
+    bool boundary = false;
+    int j = 0;
+    for (j = 1; j <= max_inner; ++j) {
+      mf.ydot(r, V.Rt.ptr, V.s.ptr, V.resR.ptr, V.ress.ptr, V.dR.ptr, V.ds.ptr, beta, mode, V.Ydot.ptr, st);
+      spmm_yt<T>(p, qh, V.Ydot.ptr, r, V.Gd.ptr, st);
+      ++out.spmm;
+      mf.hess(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.Sc.ptr, V.ec.ptr, V.dR.ptr, V.ds.ptr, V.Gd.ptr, V.etaR.ptr,
+              V.etas.ptr, V.HdR.ptr, V.Hds.ptr, V.part.ptr, st);
+      read_partials(V.part.ptr, nb, 4, sums, st);
+      const double d_Hd = sums[0], d_Pd = sums[1], e_Pd = sums[2], e_Pe = sums[3];
+      const double alpha = r_r / d_Hd;
+      const double e_Pe_new = e_Pe + 2.0 * alpha * e_Pd + alpha * alpha * d_Pd;
+      if (d_Hd <= 0.0 || e_Pe_new >= Delta * Delta) {
+        const double tau = (-e_Pd + std::sqrt(e_Pd * e_Pd + d_Pd * (Delta * Delta - e_Pe))) / d_Pd;
+        mf.tcg_update(r, V.s.ptr, tau, 1, V.dR.ptr, V.ds.ptr, V.HdR.ptr, V.Hds.ptr, V.etaR.ptr, V.etas.ptr,
+                      V.HetaR.ptr, V.Hetas.ptr, V.resR.ptr, V.ress.ptr, V.part.ptr, st);
+        boundary = true;
+        break;
+      }
+      mf.tcg_update(r, V.s.ptr, alpha, 0, V.dR.ptr, V.ds.ptr, V.HdR.ptr, V.Hds.ptr, V.etaR.ptr, V.etas.ptr,
+                    V.HetaR.ptr, V.Hetas.ptr, V.resR.ptr, V.ress.ptr, V.part.ptr, st);
+      read_partials(V.part.ptr, nb, 1, sums, st);
+      const double r_r_new = sums[0];
+      if (std::sqrt(r_r_new) <= norm_r0 * std::min(std::pow(norm_r0, theta), kappa)) break;
+      beta = r_r_new / r_r;
+      r_r = r_r_new;
+      mode = 1;
+    }
+    out.inner += std::min(j, max_inner);
+    // ---- candidate and ratio test ----
+    mf.retract(r, V.Rt.ptr, V.s.ptr, V.etaR.ptr, V.etas.ptr, V.Rt2.ptr, V.s2.ptr, V.Yt2.ptr, st);
+    spmm_yt<T>(p, qg, V.Yt2.ptr, r, V.G2.ptr, st);
+    ++out.spmm;
+    mf.model(r, V.s.ptr, V.gR.ptr, V.gs.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr, V.Yt.ptr, V.G.ptr,
+             V.Yt2.ptr, V.G2.ptr, V.part.ptr, st);
+    read_partials(V.part.ptr, nb, 3, sums, st);
+    const double mdec = -(sums[0] + 0.5 * sums[1]);
+    const double df = sums[2];
+    const double reg = std::max(1.0, std::fabs(f)) * 1e3 * 2.220446049250313e-16;
+    const double rho = (-df + reg) / (mdec + reg);
+    if (rho < 0.25) Delta *= 0.25;
+    else if (rho > 0.75 && boundary) Delta = std::min(2.0 * Delta, Dbar);
+    const bool accept = mdec > 0.0 && rho > rho_prime;
+    if (o.verbose)
+      std::fprintf(stderr, "[xm] r=%d it=%d f=%.12e |g|=%.3e Delta=%.3e rho=%.3f inner=%d %s%s\n", r, k, f, gnorm,
+                   Delta, rho, std::min(j, max_inner), boundary ? "boundary" : "interior", accept ? "" : " rejected");
+    if (accept) {
+      std::swap(V.Rt.ptr, V.Rt2.ptr);
+      std::swap(V.s.ptr, V.s2.ptr);
+      std::swap(V.Yt.ptr, V.Yt2.ptr);
+      std::swap(V.G.ptr, V.G2.ptr);
+      mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
+      read_partials(V.part.ptr, nb, 3, sums, st);
+      f = sums[0];
+      gg = sums[1];
+      gnorm = std::sqrt(gg);
+      ynorm = std::sqrt(sums[2]);
+    }
+  }
+  if (!out.converged && gnorm <= grad_tol * qbar * ynorm) out.converged = true;
+  out.outer = k;
+  out.f = f;
+  out.gnorm = gnorm;
+  out.ynorm = ynorm;
+  return out;
+}
+
+// cost and gradient norm of the current point in FP64 (for reduced-precision solves)
+struct Check {
+  double f, gnorm;
+};
+
+Check fp64_check(xm_problem* p, const double* Yt64, int r, hipStream_t st) {
+  const int N = p->N;
+  Vecs<double> V(N, r);
+  Manifold<double> mf(N);
+  mf.split(r, Yt64, V.Rt.ptr, V.s.ptr, V.Yt.ptr, st);
+  spmm_yt<double>(p, XM_F64, V.Yt.ptr, r, V.G.ptr, st);
+  mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
+  double sums[3];
+  read_partials(V.part.ptr, static_cast<int>(mf.blocks()), 3, sums, st);
+  return {sums[0], std::sqrt(sums[1])};
+}
+
+template <typename T>
+xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int r_in, double* Y_out,
+                    xm_solve_info* info, hipStream_t st) {
+  const int N = p->N;
+  const int64_t n3 = p->n3;
+  const bool f64 = std::is_same<T, double>::value;
+  const xm_dtype qg = f64 ? XM_F64 : XM_F32;
+  const xm_dtype qh = f64 ? XM_F64 : (o.compute == XM_BF16 ? XM_BF16 : XM_F32);
+  const double grad_tol = (o.grad_tol > 0) ? o.grad_tol : (f64 ? 1e-9 : 1e-6);
+  const double cert_tol = (o.cert_tol > 0) ? o.cert_tol : (f64 ? 1e-7 : 1e-5);
+  const int rmax = o.r_max;
+  Vecs<T> V(N, rmax + 1);
+  Manifold<T> mf(N);
+  DevBuf<double> Yt64(static_cast<size_t>(n3) * (rmax + 1)), vmin(n3);
+
+  int r;
+  if (Y0) {
+    require(r_in >= 3 && r_in <= rmax, XM_EINVAL, "r_in must be in [3, r_max]");
+    r = r_in;
+    transpose_rows<double, double>(Y0, r, static_cast<int>(n3), Yt64.ptr, st);
+    mf.split(r, Yt64.ptr, V.Rt.ptr, V.s.ptr, V.Yt.ptr, st);
+  } else {
+    r = o.r0;
+    mf.init(r, o.lift, V.Rt.ptr, V.s.ptr, st);
+  }
+  *info = xm_solve_info{};
+  double solve_ms = 0, cert_ms = 0;
+  RtrOut ro;
+  CertResult cr;
+  while (true) {
+    auto t0 = std::chrono::steady_clock::now();
+    ro = rtr<T>(p, V, r, qg, qh, o, grad_tol, st);
+    XM_HIP(hipStreamSynchronize(st));
+    auto t1 = std::chrono::steady_clock::now();
+    solve_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+    info->outer_iters += ro.outer;
+    info->inner_iters += ro.inner;
+    info->spmm_count += ro.spmm;
+    // FP64 copy of the factor for the certificate
+    if (f64) XM_HIP(hipMemcpyAsync(Yt64.ptr, V.Yt.ptr, n3 * r * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else transpose_rows<T, double>(V.Yt.ptr, 1, static_cast<int>(n3 * r), Yt64.ptr, st);
+    cr = certify_yt(p, Yt64.ptr, r, cert_tol, o.lanczos_max, o.lanczos_tol, vmin.ptr, st);
+    auto t2 = std::chrono::steady_clock::now();
+    cert_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
+    info->lanczos_iters += cr.iters;
+    if (o.verbose)
+      std::fprintf(stderr, "[xm] rank %d: f=%.12e |g|=%.3e lambda_min=%.6e (res %.2e, %d it) %s\n", r, ro.f,
+                   ro.gnorm, cr.lambda_min, cr.ritz_residual, cr.iters, cr.certified ? "certified" : "not certified");
+    if (cr.certified || r >= rmax) break;
+    // escape to rank r + 1 with step halving
+    const double f0 = ro.f;
+    bool moved = false;
+    double alpha = 1.0;
+    DevBuf<T> Gtmp(static_cast<size_t>(n3) * (r + 1));
+    for (int h = 0; h <= 40; ++h, alpha *= 0.5) {
+      mf.escape(r, V.Rt.ptr, V.s.ptr, vmin.ptr, alpha, V.Rt2.ptr, V.Yt2.ptr, st);
+      spmm_yt<T>(p, qg, V.Yt2.ptr, r + 1, Gtmp.ptr, st);
+      ++info->spmm_count;
+      // f(Y+) = <Yt2, Q Yt2>
+      const double fn = vec_dot<T>(V.Yt2.ptr, Gtmp.ptr, static_cast<int64_t>(n3) * (r + 1), V.part.ptr,
+                                   static_cast<int>(std::min<unsigned>(mf.blocks(), 8)), st);
+      if (fn < f0) {
+        moved = true;
+        break;
+      }
+    }
+    if (!moved) break;
+    std::swap(V.Rt.ptr, V.Rt2.ptr);
+    ++r;
+    ++info->stair_steps;
+  }
+  // final FP64 quantities
+  if (f64) XM_HIP(hipMemcpyAsync(Yt64.ptr, V.Yt.ptr, n3 * r * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else transpose_rows<T, double>(V.Yt.ptr, 1, static_cast<int>(n3 * r), Yt64.ptr, st);
+  const Check ck = fp64_check(p, Yt64.ptr, r, st);
+  XM_HIP(hipMemsetAsync(Y_out, 0, static_cast<size_t>(rmax) * n3 * sizeof(double), st));
+  transpose_rows<double, double>(Yt64.ptr, static_cast<int>(n3), r, Y_out, st);
+  XM_HIP(hipStreamSynchronize(st));
+  info->r = r;
+  info->certified = cr.certified ? 1 : 0;
+  info->converged = ro.converged ? 1 : 0;
+  info->cost = ck.f;
+  info->grad_norm = ck.gnorm;
+  info->lambda_min = cr.lambda_min;
+  info->primal = cr.primal;
+  info->dual = cr.dual;
+  info->solve_ms = solve_ms;
+  info->cert_ms = cert_ms;
+  return ro.converged ? XM_OK : XM_ENOCONV;
+}
+
+}  // namespace
+
+xm_status bm_solve(xm_problem* p, const xm_solve_opts& o, const double* Y0, int r_in, double* Y_out,
+                   xm_solve_info* info, hipStream_t s) {
+  require(o.r0 >= 3 && o.r_max >= o.r0 && o.r_max <= 7, XM_EINVAL, "need 3 <= r0 <= r_max <= 7");
+  require(Y_out != nullptr && info != nullptr, XM_EINVAL, "Y_out and info must be non-NULL");
+  if (o.compute == XM_F64) return staircase<double>(p, o, Y0, r_in, Y_out, info, s);
+  require(o.compute == XM_F32 || o.compute == XM_BF16, XM_EINVAL, "unknown compute dtype");
+  require(p->Q32.ptr != nullptr, XM_EINVAL, "reduced-precision solve needs the FP32 copy (XM_KEEP_F32)");
+  if (o.compute == XM_BF16) require(p->Q16.ptr != nullptr, XM_EINVAL, "BF16 solve needs XM_KEEP_BF16");
+  return staircase<float>(p, o, Y0, r_in, Y_out, info, s);
+}
+
+}  // namespace xm

@@ -1,0 +1,211 @@
+// Stable LSD radix sort of (u32 key, u64 value) pairs and exclusive prefix sums.
+//
+// Used by the Q assembly to group observations by landmark and observation
+// pairs by frame pair, so that the per-block reductions run without global
+// atomics and in a fixed order (bitwise reproducible FP64 Q).
+//
+// Radix pass (8-bit digits, tiles of 4096 elements, 256 threads):
+//   hist:    per-tile digit counts in LDS          -> counts[digit][tile]
+//   scan:    exclusive scan of counts (digit-major) -> global output offsets
+//   scatter: 16 rounds of 256 elements; the stable rank of an element among
+//            equal digits of its round comes from 8 wave ballots (wave64),
+//            per-wave digit counts in LDS give the cross-wave prefix.
+#include "common.h"
+
+namespace xm {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kRounds = 16;
+constexpr int kTile = kBlock * kRounds;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys,
+                                                            int64_t n, int shift, int num_tiles,
+                                                            uint32_t* __restrict__ counts) {
+  __shared__ uint32_t hist[256];
+  const int t = threadIdx.x;
+  hist[t] = 0;
+  __syncthreads();
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile;
+  for (int q = 0; q < kRounds; ++q) {
+    const int64_t e = base + q * kBlock + t;
+    if (e < n) atomicAdd(&hist[(keys[e] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  counts[static_cast<int64_t>(t) * num_tiles + blockIdx.x] = hist[t];
+}
+
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
+    const uint32_t* __restrict__ kin, const uint64_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint64_t* __restrict__ vout, int64_t n, int shift, int num_tiles,
+    const uint32_t* __restrict__ offsets) {
+  __shared__ uint32_t running[256];
+  __shared__ uint32_t wcnt[4][256];
+  const int t = threadIdx.x, wid = t >> 6;
+  running[t] = offsets[static_cast<int64_t>(t) * num_tiles + blockIdx.x];
+  wcnt[0][t] = wcnt[1][t] = wcnt[2][t] = wcnt[3][t] = 0;
+  __syncthreads();
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile;
+  const uint64_t lt = __lanemask_lt();
+  for (int q = 0; q < kRounds; ++q) {
+    const int64_t e = base + q * kBlock + t;
+    const bool valid = e < n;
+    const uint32_t key = valid ? kin[e] : 0u;
+    const uint64_t val = valid ? vin[e] : 0ull;
+    const uint32_t d = (key >> shift) & 255u;
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const int on = (d >> bit) & 1u;
+      const uint64_t b = __ballot(on);
+      m &= on ? b : ~b;
+    }
+    const uint32_t rank = __popcll(m & lt);
+    if (valid && rank == 0) wcnt[wid][d] = __popcll(m);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = running[d] + rank;
+      for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    running[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+    wcnt[0][t] = wcnt[1][t] = wcnt[2][t] = wcnt[3][t] = 0;
+    __syncthreads();
+  }
+}
+
+// ---- exclusive scan (generic over the element type) -------------------------
+template <typename T>
+__device__ T block_exclusive_scan(T v, T* lds, T* total) {
+  // Hillis-Steele over 256 thread totals in LDS.
+  const int t = threadIdx.x;
+  lds[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    T add = (t >= off) ? lds[t - off] : T(0);
+    __syncthreads();
+    lds[t] += add;
+    __syncthreads();
+  }
+  T incl = lds[t];
+  *total = lds[kBlock - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void scan_tiles_kernel(const T* __restrict__ in, T* out, int64_t n,
+                                                           T* __restrict__ tile_sums) {
+  __shared__ T lds[kBlock];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+  T loc[kScanItems];
+  T sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t e = base + i;
+    loc[i] = (e < n) ? in[e] : T(0);
+    sum += loc[i];
+  }
+  T total;
+  T pre = block_exclusive_scan<T>(sum, lds, &total);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t e = base + i;
+    if (e < n) out[e] = pre;
+    pre += loc[i];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void scan_sums_kernel(T* sums, int64_t m) {
+  // single block: exclusive scan of sums[0..m) in place, total -> sums[m]
+  __shared__ T lds[kBlock];
+  T carry = 0;
+  for (int64_t c0 = 0; c0 < m; c0 += kBlock) {
+    const int64_t e = c0 + threadIdx.x;
+    T v = (e < m) ? sums[e] : T(0);
+    T total;
+    T pre = block_exclusive_scan<T>(v, lds, &total);
+    if (e < m) sums[e] = carry + pre;
+    carry += total;
+  }
+  if (threadIdx.x == 0) sums[m] = carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void scan_add_kernel(T* out, int64_t n, const T* __restrict__ sums) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e < n) out[e] += sums[e / kScanTile];
+}
+
+template <typename T>
+void exclusive_scan(const T* in, T* out, int64_t n, T* tile_sums, hipStream_t s) {
+  const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(scan_tiles_kernel<T>, dim3(static_cast<unsigned>(tiles)), dim3(kBlock), 0, s, in,
+                     out, n, tile_sums);
+  XM_LAUNCH_CHECK("scan_tiles_kernel");
+  hipLaunchKernelGGL(scan_sums_kernel<T>, dim3(1), dim3(kBlock), 0, s, tile_sums, tiles);
+  XM_LAUNCH_CHECK("scan_sums_kernel");
+  hipLaunchKernelGGL(scan_add_kernel<T>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, out, n,
+                     static_cast<const T*>(tile_sums));
+  XM_LAUNCH_CHECK("scan_add_kernel");
+}
+
+__global__ void write_total_kernel(const int64_t* tile_sums, int64_t tiles, int64_t* out_n) {
+  *out_n = tile_sums[tiles];
+}
+
+}  // namespace
+
+void radix_sort_pairs(uint32_t* keys, uint64_t* vals, uint32_t* keys_tmp, uint64_t* vals_tmp,
+                      int64_t n, int key_bits, hipStream_t s) {
+  if (n <= 1) return;
+  require(n < (int64_t(1) << 31), XM_EINVAL, "radix sort: too many elements");
+  const int num_tiles = static_cast<int>((n + kTile - 1) / kTile);
+  const int64_t ncount = static_cast<int64_t>(num_tiles) * 256;
+  DevBuf<uint32_t> counts(ncount);
+  DevBuf<uint32_t> tile_sums((ncount + kScanTile - 1) / kScanTile + 1);
+  uint32_t *ka = keys, *kb = keys_tmp;
+  uint64_t *va = vals, *vb = vals_tmp;
+  const int passes = (key_bits + 7) / 8;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = 8 * pass;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(num_tiles), dim3(kBlock), 0, s, ka, n, shift,
+                       num_tiles, counts.ptr);
+    XM_LAUNCH_CHECK("radix_hist_kernel");
+    exclusive_scan<uint32_t>(counts.ptr, counts.ptr, ncount, tile_sums.ptr, s);
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(num_tiles), dim3(kBlock), 0, s, ka, va, kb, vb, n,
+                       shift, num_tiles, counts.ptr);
+    XM_LAUNCH_CHECK("radix_scatter_kernel");
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (ka != keys) {
+    XM_HIP(hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    XM_HIP(hipMemcpyAsync(vals, va, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+  }
+  // scratch buffers are freed at scope exit: make sure the kernels are done with them
+  XM_HIP(hipStreamSynchronize(s));
+}
+
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) {
+    XM_HIP(hipMemsetAsync(out, 0, sizeof(int64_t), s));
+    XM_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  DevBuf<int64_t> tile_sums(tiles + 1);
+  exclusive_scan<int64_t>(in, out, n, tile_sums.ptr, s);
+  hipLaunchKernelGGL(write_total_kernel, dim3(1), dim3(1), 0, s, static_cast<const int64_t*>(tile_sums.ptr),
+                     tiles, out + n);
+  XM_LAUNCH_CHECK("write_total_kernel");
+  XM_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace xm

@@ -1,0 +1,218 @@
+// Y Q product over the block-tiled dense Q (the Euclidean gradient / Hessian
+// product of the local solver and the Lanczos operator of the certificate).
+//
+// Q is symmetric, so (Y Q)[a][j] = sum_i Q[i][j] Yt[i][a] with Yt = Y^T kept
+// frame-major ([3N][r]).  Each workgroup (256 threads) owns a chunk of
+// 256*V columns and a slab of rows: every thread streams one 16-byte vector
+// of Q per row (V = 2 doubles, 4 floats or 8 bf16), coalesced across the
+// wave, and multiplies it by the r values of Yt for that row, which are the
+// same for the whole workgroup and staged once in LDS.  Row slabs give enough
+// workgroups to fill 256 CUs; their partial sums are added by a second,
+// deterministic pass.  Q is read exactly once per product: HBM-bound, with
+// 2 r FLOP per stored element.
+#include "problem.h"
+
+namespace xm {
+namespace {
+
+constexpr int kB = 256;
+constexpr int kMaxRows = 512;
+
+template <typename TQ>
+struct QVec;
+template <>
+struct QVec<double> {
+  static constexpr int V = 2;
+  static constexpr int dtype = XM_F64;
+  template <typename TA>
+  __device__ static void load(const double* p, TA* out) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    out[0] = v.x; out[1] = v.y;
+  }
+};
+template <>
+struct QVec<float> {
+  static constexpr int V = 4;
+  static constexpr int dtype = XM_F32;
+  template <typename TA>
+  __device__ static void load(const float* p, TA* out) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+  }
+};
+template <>
+struct QVec<uint16_t> {
+  static constexpr int V = 8;
+  static constexpr int dtype = XM_BF16;
+  template <typename TA>
+  __device__ static void load(const uint16_t* p, TA* out) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      out[2 * k] = __uint_as_float(w[k] << 16);
+      out[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+    }
+  }
+};
+
+template <typename TQ, typename TV, typename TA, int R>
+__global__ __launch_bounds__(kB) void spmm_split_kernel(const TQ* __restrict__ Q, int32_t ld, int32_t n3,
+                                                        const TV* __restrict__ Yt, int32_t rows_per_split,
+                                                        TA* __restrict__ part) {
+  constexpr int V = QVec<TQ>::V;
+  __shared__ TA ys[kMaxRows * R];
+  const int split = blockIdx.y;
+  const int i0 = split * rows_per_split;
+  const int i1 = min(n3, i0 + rows_per_split);
+  const int nrows = i1 - i0;
+  for (int e = threadIdx.x; e < nrows * R; e += kB) ys[e] = static_cast<TA>(Yt[static_cast<int64_t>(i0) * R + e]);
+  __syncthreads();
+  const int j = (blockIdx.x * kB + threadIdx.x) * V;
+  TA acc[V][R];
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+#pragma unroll
+    for (int a = 0; a < R; ++a) acc[v][a] = TA(0);
+  if (j < ld && nrows > 0) {
+    const TQ* q = Q + static_cast<int64_t>(i0) * ld + j;
+#pragma unroll 8
+    for (int i = 0; i < nrows; ++i) {
+      TA qv[V];
+      QVec<TQ>::load(q + static_cast<int64_t>(i) * ld, qv);
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        const TA y = ys[i * R + a];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v][a] += qv[v] * y;
+      }
+    }
+  }
+  TA* out = part + static_cast<int64_t>(split) * n3 * R;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    if (j + v < n3) {
+#pragma unroll
+      for (int a = 0; a < R; ++a) out[static_cast<int64_t>(j + v) * R + a] = acc[v][a];
+    }
+  }
+}
+
+template <typename TA, typename TV>
+__global__ void spmm_reduce_kernel(const TA* __restrict__ part, int32_t splits, int64_t m, TV* __restrict__ out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (e >= m) return;
+  TA s = TA(0);
+  for (int k = 0; k < splits; ++k) s += part[static_cast<int64_t>(k) * m + e];
+  out[e] = static_cast<TV>(s);
+}
+
+template <typename Ts, typename Td>
+__global__ void transpose_rows_kernel(const Ts* __restrict__ in, int32_t rows, int32_t cols, Td* __restrict__ out) {
+  // out[c][r] = in[r][c]; one thread per output element
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (e >= static_cast<int64_t>(rows) * cols) return;
+  const int64_t c = e / rows, r = e % rows;
+  out[e] = static_cast<Td>(in[r * cols + c]);
+}
+
+struct Split {
+  int32_t splits, rows;
+  unsigned col_blocks;
+};
+
+Split choose_split(int32_t n3, int32_t ld, int V) {
+  Split sp;
+  sp.col_blocks = cdiv(ld, static_cast<size_t>(kB) * V);
+  const int target = 2048;
+  int splits = static_cast<int>((target + sp.col_blocks - 1) / sp.col_blocks);
+  splits = std::max(1, std::min(splits, static_cast<int>(cdiv(n3, 32))));
+  int rows = static_cast<int>(cdiv(n3, splits));
+  if (rows > kMaxRows) rows = kMaxRows;
+  sp.rows = rows;
+  sp.splits = static_cast<int32_t>(cdiv(n3, rows));
+  return sp;
+}
+
+template <typename TQ, typename TV, typename TA, int R>
+void launch(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStream_t s) {
+  const Split sp = choose_split(p->n3, p->ld, QVec<TQ>::V);
+  auto& scratch = const_cast<xm_problem*>(p)->spmm_scratch;
+  const size_t need = static_cast<size_t>(sp.splits) * p->n3 * R * sizeof(TA);
+  if (scratch.n < need) {
+    XM_HIP(hipStreamSynchronize(s));
+    scratch.alloc(need);
+  }
+  TA* part = reinterpret_cast<TA*>(scratch.ptr);
+  xm_problem::TimedLaunch* ev = nullptr;
+  if (p->timing) {
+    auto* mp = const_cast<xm_problem*>(p);
+    if (mp->events_used == mp->events.size()) {
+      xm_problem::TimedLaunch t{};
+      XM_HIP(hipEventCreate(&t.start));
+      XM_HIP(hipEventCreate(&t.stop));
+      mp->events.push_back(t);
+    }
+    ev = &mp->events[mp->events_used++];
+    ev->dtype = QVec<TQ>::dtype;
+    XM_HIP(hipEventRecord(ev->start, s));
+  }
+  hipLaunchKernelGGL((spmm_split_kernel<TQ, TV, TA, R>), dim3(sp.col_blocks, sp.splits), dim3(kB), 0, s, Q,
+                     p->ld, p->n3, Yt, sp.rows, part);
+  XM_LAUNCH_CHECK("spmm_split_kernel");
+  if (ev) XM_HIP(hipEventRecord(ev->stop, s));
+  const int64_t m = static_cast<int64_t>(p->n3) * R;
+  hipLaunchKernelGGL((spmm_reduce_kernel<TA, TV>), dim3(cdiv(m, kB)), dim3(kB), 0, s, part, sp.splits, m, out);
+  XM_LAUNCH_CHECK("spmm_reduce_kernel");
+}
+
+template <typename TQ, typename TV, typename TA>
+void dispatch_r(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, hipStream_t s) {
+  switch (r) {
+    case 1: launch<TQ, TV, TA, 1>(p, Q, Yt, out, s); break;
+    case 2: launch<TQ, TV, TA, 2>(p, Q, Yt, out, s); break;
+    case 3: launch<TQ, TV, TA, 3>(p, Q, Yt, out, s); break;
+    case 4: launch<TQ, TV, TA, 4>(p, Q, Yt, out, s); break;
+    case 5: launch<TQ, TV, TA, 5>(p, Q, Yt, out, s); break;
+    case 6: launch<TQ, TV, TA, 6>(p, Q, Yt, out, s); break;
+    case 7: launch<TQ, TV, TA, 7>(p, Q, Yt, out, s); break;
+    case 8: launch<TQ, TV, TA, 8>(p, Q, Yt, out, s); break;
+    default: throw Error(XM_EINVAL, "rank must be in [1, 8]");
+  }
+}
+
+}  // namespace
+
+template <>
+void spmm_yt<double>(const xm_problem* p, xm_dtype qtype, const double* Yt, int r, double* out, hipStream_t s) {
+  require(qtype == XM_F64, XM_EINVAL, "FP64 vectors are multiplied with the FP64 Q");
+  dispatch_r<double, double, double>(p, p->Q64.ptr, Yt, r, out, s);
+}
+
+template <>
+void spmm_yt<float>(const xm_problem* p, xm_dtype qtype, const float* Yt, int r, float* out, hipStream_t s) {
+  if (qtype == XM_F32) {
+    require(p->Q32.ptr != nullptr, XM_EINVAL, "the FP32 copy of Q was not kept (XM_KEEP_F32)");
+    dispatch_r<float, float, float>(p, p->Q32.ptr, Yt, r, out, s);
+  } else if (qtype == XM_BF16) {
+    require(p->Q16.ptr != nullptr, XM_EINVAL, "the BF16 copy of Q was not kept (XM_KEEP_BF16)");
+    dispatch_r<uint16_t, float, float>(p, p->Q16.ptr, Yt, r, out, s);
+  } else {
+    throw Error(XM_EINVAL, "FP32 vectors are multiplied with the FP32 or BF16 Q");
+  }
+}
+
+template <typename Ts, typename Td>
+void transpose_rows(const Ts* in, int rows, int cols, Td* out, hipStream_t s) {
+  const int64_t m = static_cast<int64_t>(rows) * cols;
+  if (m == 0) return;
+  hipLaunchKernelGGL((transpose_rows_kernel<Ts, Td>), dim3(cdiv(m, kB)), dim3(kB), 0, s, in, rows, cols, out);
+  XM_LAUNCH_CHECK("transpose_rows_kernel");
+}
+
+template void transpose_rows<double, double>(const double*, int, int, double*, hipStream_t);
+template void transpose_rows<double, float>(const double*, int, int, float*, hipStream_t);
+template void transpose_rows<float, double>(const float*, int, int, double*, hipStream_t);
+template void transpose_rows<float, float>(const float*, int, int, float*, hipStream_t);
+
+}  // namespace xm

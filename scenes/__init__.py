@@ -105,16 +105,21 @@ def _distinct_choice(rng: np.random.Generator, cand: np.ndarray, L: np.ndarray) 
     return picked[mask]
 
 
-def _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=0.0, bbox=None):
-    """u = d_i (R_cfg[i] (x_k - c_i) + eps); a fraction of rows replaced by random points."""
+def _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=0.0, bbox=None, local=None):
+    """u = d_i (R_cfg[i] (x_k - c_i) + eps); a fraction of rows replaced by random points.
+
+    Outlier points are uniform in ``bbox`` (lo, hi) when given, else uniform in
+    the cube of half-side ``local`` centred at the true landmark."""
     n = fr.shape[0]
     pts = x[lm]
     if outlier_frac > 0.0:
         bad = rng.random(n) < outlier_frac
-        lo, hi = bbox
-        z = rng.uniform(lo, hi, size=(int(bad.sum()), 3))
         pts = pts.copy()
-        pts[bad] = z
+        if bbox is not None:
+            lo, hi = bbox
+            pts[bad] = rng.uniform(lo, hi, size=(int(bad.sum()), 3))
+        else:
+            pts[bad] = pts[bad] + rng.uniform(-local, local, size=(int(bad.sum()), 3))
     cam = np.einsum("nij,nj->ni", R_cfg[fr], pts - c[fr])
     if sigma > 0:
         cam = cam + sigma * rng.standard_normal((n, 3))
@@ -242,10 +247,10 @@ def _sequential(seed, N=2000, M=400_000, window=10, sigma=0.01):
 
 
 def _large(seed, N=10155, M=2_000_000, k=50, clusters=20, sigma=0.02, outlier=0.05,
-           chunk=250_000):
+           chunk=250_000, box=15.0, outlier_model="local", local=3.0):
     from scipy.spatial import cKDTree
     rng = np.random.Generator(np.random.PCG64(seed))
-    mu = rng.uniform(-40.0, 40.0, size=(clusters, 3))  # choice: cluster centres U[-40,40]^3
+    mu = rng.uniform(-box, box, size=(clusters, 3))   # choice: cluster centres U[-15,15]^3
     lab = rng.integers(0, clusters, size=N)
     c = mu[lab] + 6.0 * rng.standard_normal((N, 3))    # choice: N(mu, 6^2 I)
     R_cfg = haar_rotations(rng, N)
@@ -296,7 +301,10 @@ def _large(seed, N=10155, M=2_000_000, k=50, clusters=20, sigma=0.02, outlier=0.
         lm = np.concatenate([lm, np.array(extra_lm, dtype=np.int64)])
     Mtot = x.shape[0]
     lo, hi = c.min(0) - 3.0, c.max(0) + 3.0
-    u = _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=outlier, bbox=(lo, hi))
+    if outlier_model == "box":
+        u = _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=outlier, bbox=(lo, hi))
+    else:
+        u = _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=outlier, local=local)
     return _finish("large", N, Mtot, fr, lm, u, np.ones(fr.shape[0]), _ground_truth(R_cfg, c, d, x))
 
 

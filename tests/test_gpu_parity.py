@@ -1,0 +1,269 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle."""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import certificate as oce
+from oracle import data_matrix as odm
+from oracle import manifold as omf
+from oracle import rounding as ord_
+from oracle import staircase as ost
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _xm():
+    import paper_2502_04640_amd as xm
+    xm.load_library()
+    return xm
+
+
+def _dev(sc, f32=False):
+    fl = torch.float32 if f32 else torch.float64
+    return (torch.from_numpy(sc.frame).cuda(), torch.from_numpy(sc.landmark).cuda(),
+            torch.from_numpy(sc.u).to(fl).cuda(), torch.from_numpy(sc.w).to(fl).cuda())
+
+
+def _build(sc, keep=("f32",), f32=False):
+    xm = _xm()
+    fr, lm, u, w = _dev(sc, f32)
+    return xm.build_Q(sc.N, sc.M, fr, lm, u, w, keep=keep)
+
+
+def _oracle_Q(sc):
+    return odm.q_block_elimination(sc.N, sc.M, sc.frame, sc.landmark, sc.u, sc.w)
+
+
+def _rot_err(Ra, Rb):
+    d = np.linalg.norm(Ra - Rb, axis=(1, 2))
+    return float(np.max(2 * np.arcsin(np.minimum(1.0, d / (2 * np.sqrt(2))))))
+
+
+def _gap(a, b):
+    return abs(a - b) / (1 + abs(a) + abs(b))
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+# ---------------------------------------------------------------------------
+def test_build_q_tiny_matches_oracle():
+    _say("case: build_Q tiny seed 0")
+    sc = scenes.make_scene("tiny", 0)
+    P = _build(sc)
+    Q = P.Q_rows(0, 3 * sc.N).cpu().numpy()
+    Qo = _oracle_Q(sc)
+    assert np.abs(Q - Qo).max() <= 1e-10 * np.abs(Qo).max()
+    info = P.info()
+    assert info["N"] == sc.N and info["n_obs"] == sc.n_obs
+    assert abs(info["qbar"] - np.trace(Qo) / (3 * sc.N)) <= 1e-10 * info["qbar"]
+
+
+def test_build_q_bitwise_deterministic_and_order_free():
+    _say("case: build_Q determinism diff-like N=60")
+    sc = scenes.random_scene(60, 3000, L=5, sigma=0.02, seed=3, weights=(0.5, 1.5))
+    Q1 = _build(sc).Q_rows(0, 3 * sc.N).cpu().numpy()
+    Q2 = _build(sc).Q_rows(0, 3 * sc.N).cpu().numpy()
+    assert np.array_equal(Q1, Q2)
+    Q3 = _build(sc.shuffled(7)).Q_rows(0, 3 * sc.N).cpu().numpy()
+    assert np.abs(Q3 - Q1).max() <= 1e-11 * np.abs(Q1).max()
+    assert np.array_equal(Q1, Q1.T)
+
+
+def test_build_q_fp32_inputs_and_weights():
+    _say("case: build_Q FP32 u and w")
+    sc = scenes.random_scene(40, 1500, L=4, sigma=0.01, seed=4, weights=(0.5, 1.5))
+    P = _build(sc, f32=True)
+    u32 = sc.u.astype(np.float32).astype(np.float64)
+    w32 = sc.w.astype(np.float32).astype(np.float64)
+    Qo = odm.q_block_elimination(sc.N, sc.M, sc.frame, sc.landmark, u32, w32)
+    Q = P.Q_rows(0, 3 * sc.N).cpu().numpy()
+    assert np.abs(Q - Qo).max() <= 1e-10 * np.abs(Qo).max()
+
+
+def test_build_q_ragged_landmarks_and_single_observations():
+    _say("case: build_Q ragged tracks, singletons, gaps in landmark ids")
+    rng = np.random.default_rng(5)
+    sc = scenes.random_scene(30, 800, L=3, sigma=0.02, seed=5)
+    # drop a random subset of observations so tracks have length 1..3, and
+    # leave landmark ids unused
+    keep = rng.random(sc.n_obs) > 0.25
+    fr, lm, u, w = sc.frame[keep], sc.landmark[keep], sc.u[keep], sc.w[keep]
+    M = int(lm.max()) + 10
+    Qo = odm.q_block_elimination(sc.N, M, fr, lm, u, w)
+    sc2 = scenes.Scene(sc.N, M, fr, lm, u, w, {}, "ragged")
+    Q = _build(sc2).Q_rows(0, 3 * sc.N).cpu().numpy()
+    assert np.abs(Q - Qo).max() <= 1e-10 * np.abs(Qo).max()
+
+
+def test_build_q_errors():
+    _say("case: build_Q error paths")
+    xm = _xm()
+    sc = scenes.make_scene("tiny", 0)
+    fr, lm, u, w = _dev(sc)
+    bad = fr.clone(); bad[3] = sc.N
+    with pytest.raises(xm.XMError, match="XM_EINVAL"):
+        xm.build_Q(sc.N, sc.M, bad, lm, u, w)
+    ub = u.clone(); ub[5, 1] = float("nan")
+    with pytest.raises(xm.XMError, match="XM_EINVAL"):
+        xm.build_Q(sc.N, sc.M, fr, lm, ub, w)
+    wb = w.clone(); wb[2] = 0.0
+    with pytest.raises(xm.XMError, match="XM_EINVAL"):
+        xm.build_Q(sc.N, sc.M, fr, lm, u, wb)
+    # frame N-1 never observed -> XM_EGRAPH
+    with pytest.raises(xm.XMError, match="XM_EGRAPH"):
+        xm.build_Q(sc.N + 1, sc.M, fr, lm, u, w)
+    # two disconnected halves -> XM_EGRAPH
+    a = scenes.random_scene(6, 50, L=3, sigma=0.01, seed=1)
+    fr2 = np.r_[a.frame, a.frame + 6].astype(np.int32)
+    lm2 = np.r_[a.landmark, a.landmark + 50].astype(np.int32)
+    u2 = np.r_[a.u, a.u]
+    w2 = np.r_[a.w, a.w]
+    with pytest.raises(xm.XMError, match="XM_EGRAPH"):
+        xm.build_Q(12, 100, torch.from_numpy(fr2).cuda(), torch.from_numpy(lm2).cuda(),
+                   torch.from_numpy(u2).cuda(), torch.from_numpy(w2).cuda())
+
+
+@pytest.mark.parametrize("r", [1, 3, 5, 8])
+def test_spmm_parity(r):
+    _say(f"case: spmm r={r}")
+    sc = scenes.random_scene(70, 3000, L=4, sigma=0.02, seed=6)
+    P = _build(sc, keep=("f32", "bf16"))
+    Qo = _oracle_Q(sc)
+    rng = np.random.default_rng(r)
+    Y = rng.standard_normal((r, 3 * sc.N))
+    ref = Y @ Qo
+    Yd = torch.from_numpy(Y).cuda()
+    out64 = P.spmm(Yd, "f64").cpu().numpy()
+    scale = np.abs(Y).max() * np.abs(Qo).sum(0).max()
+    assert np.abs(out64 - ref).max() <= 1e-13 * scale
+    out32 = P.spmm(Yd, "f32").cpu().numpy()
+    assert np.abs(out32 - ref).max() <= 3e-6 * scale
+    out16 = P.spmm(Yd, "bf16").cpu().numpy()
+    assert np.abs(out16 - ref).max() <= 1e-2 * scale
+
+
+def _oracle_solution(sc, Q):
+    R, s, info = ost.staircase(Q, grad_tol=1e-11, tau=1e-7)
+    Rh, sh = ord_.round_solution(omf.to_U(R, s))
+    return R, s, info, Rh, sh
+
+
+@pytest.mark.parametrize("start", ["paper", "lifted"])
+@pytest.mark.parametrize("compute,rot_tol,gap_tol", [("f64", 1e-6, 1e-8), ("f32", 1e-4, 1e-5)])
+def test_solve_tiny_matches_oracle(compute, rot_tol, gap_tol, start):
+    _say(f"case: solve tiny {compute} start={start}")
+    xm = _xm()
+    sc = scenes.make_scene("tiny", 0)
+    Qo = _oracle_Q(sc)
+    _, _, oinfo, Rh_o, sh_o = _oracle_solution(sc, Qo)
+    P = _build(sc)
+    kw = dict(r0=3, r_max=5, lift=0.0) if start == "paper" else {}
+    Y, info = P.solve(xm.SolveOptions(compute=compute, **kw))
+    assert info["certified"] == 1 and oinfo["certified"]
+    R, s, rho_hat = P.round(Y)
+    R, s = R.cpu().numpy(), s.cpu().numpy()
+    assert _rot_err(R, Rh_o) <= rot_tol
+    assert np.abs(s / sh_o - 1).max() <= rot_tol
+    assert _gap(info["cost"], oinfo["cost"]) <= gap_tol
+    Uo = ord_.rounded_U(Rh_o, sh_o)
+    assert _gap(rho_hat, float(np.sum(Uo * (Uo @ Qo)))) <= gap_tol
+
+
+def test_noise_free_recovers_ground_truth():
+    _say("case: noise-free tiny")
+    xm = _xm()
+    sc = scenes.make_scene("tiny", 3, sigma=0.0)
+    P = _build(sc)
+    Y, info = P.solve(xm.SolveOptions(compute="f64", grad_tol=1e-11, r0=3, lift=0.0))
+    assert info["certified"] == 1 and info["r"] == 3
+    R, s, rho_hat = P.round(Y)
+    assert _rot_err(R.cpu().numpy(), sc.gt["R"]) <= 1e-7
+    assert np.abs(s.cpu().numpy() - sc.gt["s"]).max() <= 1e-7
+    assert abs(rho_hat) <= 1e-8 * P.info()["qbar"]
+
+
+def test_certificate_matches_dense_eigenvalue():
+    _say("case: certificate vs dense eigh")
+    sc = scenes.make_scene("tiny", 1)
+    Qo = _oracle_Q(sc)
+    R, s, oinfo = ost.staircase(Qo, grad_tol=1e-11)
+    c_o = oce.certify(Qo, R, s, 1e-7)
+    U = omf.to_U(R, s)
+    P = _build(sc)
+    c = P.certify(torch.from_numpy(U).cuda(), tol=1e-7, max_iter=300)
+    qbar = c["qbar"]
+    assert c["certified"] == 1
+    assert abs(c["lambda_min"] - c_o["lambda_min"]) <= 1e-6 * qbar
+    # primal and dual are small differences of O(qbar |Y|^2) terms: FP64 noise ~1e-16 * 3N * qbar
+    assert _gap(c["primal"], c_o["primal"]) <= 1e-9
+    assert _gap(c["dual"], c_o["dual"]) <= 1e-9
+
+
+def test_round_matches_oracle_on_rank5_input():
+    # A rank-5 factor whose top-3 subspace carries rotation-like blocks (clear
+    # eigenvalue gap and an unambiguous determinant majority): rounding must
+    # pick that subspace through the r x r Gram and agree with the oracle.
+    _say("case: rounding rank 5")
+    sc = scenes.make_scene("tiny", 2)
+    gt = sc.gt
+    Ugt = (gt["s"][:, None, None] * gt["R"]).transpose(1, 0, 2).reshape(3, 3 * sc.N)
+    rng = np.random.default_rng(1)
+    O, _ = np.linalg.qr(rng.standard_normal((5, 5)))
+    U = O @ np.vstack([Ugt + 0.05 * rng.standard_normal(Ugt.shape), 0.3 * rng.standard_normal((2, 3 * sc.N))])
+    Rh_o, sh_o = ord_.round_solution(U)
+    P = _build(sc)
+    Rg, sg, _ = P.round(torch.from_numpy(U).cuda())
+    assert _rot_err(Rg.cpu().numpy(), Rh_o) <= 1e-9
+    assert np.abs(sg.cpu().numpy() - sh_o).max() <= 1e-9 * np.abs(sh_o).max()
+
+
+def test_escape_from_spurious_minimum():
+    _say("case: staircase escape from a rank-3 local minimum")
+    xm = _xm()
+    from oracle import rtr as ortr
+    sc = scenes.random_scene(8, 40, L=3, sigma=0.5, seed=0)
+    Qo = _oracle_Q(sc)
+    rng = np.random.default_rng(0)
+    R0 = omf.gram_schmidt(rng.standard_normal((sc.N, 3, 3)))
+    s0 = np.exp(rng.standard_normal(sc.N) * 0.3)
+    s0[0] = 1.0
+    R, s, info = ortr.rtr(Qo, R0, s0, grad_tol=1e-11)
+    c = oce.certify(Qo, R, s, 1e-8)
+    assert c["lambda_min"] < -1e-3 * c["qbar"]
+    _, _, ofin = ost.staircase(Qo, R0=R, s0=s, r_max=7, grad_tol=1e-11)
+    P = _build(sc)
+    Y, ginfo = P.solve(xm.SolveOptions(compute="f64", r_max=7, grad_tol=1e-11),
+                       Y0=torch.from_numpy(omf.to_U(R, s)).cuda())
+    assert ginfo["stair_steps"] >= 1
+    assert ginfo["certified"] == 1 and ofin["certified"]
+    assert ginfo["cost"] < info["cost"]
+    assert _gap(ginfo["cost"], ofin["cost"]) <= 1e-8
+
+
+@pytest.mark.parametrize("cfg", ["diff"])
+def test_medium_config_q_and_solve(cfg):
+    _say(f"case: {cfg} build + solve f64 and f32")
+    xm = _xm()
+    sc = scenes.make_scene(cfg, 0)
+    Qo = _oracle_Q(sc)
+    P = _build(sc, keep=("f32", "bf16"), f32=True) if cfg == "diff" else _build(sc)
+    if cfg == "diff":
+        u32 = sc.u.astype(np.float32).astype(np.float64)
+        w32 = sc.w.astype(np.float32).astype(np.float64)
+        Qo = odm.q_block_elimination(sc.N, sc.M, sc.frame, sc.landmark, u32, w32)
+    Q = P.Q_rows(0, 3 * sc.N).cpu().numpy()
+    assert np.abs(Q - Qo).max() <= 1e-10 * np.abs(Qo).max()
+    _, _, oinfo, Rh_o, sh_o = _oracle_solution(sc, Qo)
+    for compute, rot_tol, gap_tol in (("f64", 1e-6, 1e-8), ("f32", 1e-4, 1e-5)):
+        Y, info = P.solve(xm.SolveOptions(compute=compute))
+        _say(f"  {compute}: r={info['r']} cert={info['certified']} outer={info['outer_iters']} "
+             f"inner={info['inner_iters']} lanczos={info['lanczos_iters']} solve_ms={info['solve_ms']:.1f} "
+             f"cert_ms={info['cert_ms']:.1f}")
+        assert info["certified"] == 1
+        R, s, _ = P.round(Y)
+        assert _rot_err(R.cpu().numpy(), Rh_o) <= rot_tol
+        assert _gap(info["cost"], oinfo["cost"]) <= gap_tol

@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every entry point its header declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xm.h")
+LIB = os.path.join(ROOT, "paper_2502_04640_amd", "libxm.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xm_[A-Za-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_four_calls():
+    names = declared_functions()
+    for n in ("xm_build_Q", "xm_bm_solve", "xm_round", "xm_certify"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libxm.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libxm.so not built")
+def test_last_error_empty_and_default_opts():
+    lib = ctypes.CDLL(LIB)
+    lib.xm_last_error.restype = ctypes.c_char_p
+    assert lib.xm_last_error() == b""
+    from paper_2502_04640_amd.api import _SolveOpts
+    o = _SolveOpts()
+    lib.xm_default_opts(ctypes.byref(o))
+    assert (o.r0, o.r_max, o.compute, o.lift) == (5, 7, 0, 1.0)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libxm.so not built")
+def test_null_arguments_are_rejected_without_gpu():
+    # argument checks run before any HIP call
+    lib = ctypes.CDLL(LIB)
+    lib.xm_build_Q.restype = ctypes.c_int
+    lib.xm_last_error.restype = ctypes.c_char_p
+    out = ctypes.c_void_p(0)
+    code = lib.xm_build_Q(ctypes.c_int32(1), ctypes.c_int32(1), ctypes.c_int64(1), None, None, None, 0, None, 0,
+                          ctypes.c_uint32(0), None, ctypes.byref(out))
+    assert code == -1 and b"N must be" in lib.xm_last_error()
+    lib.xm_get_info.restype = ctypes.c_int
+    assert lib.xm_get_info(None, None) == -1
