@@ -148,17 +148,18 @@ typedef struct {
                           (<= 0: 1e-9 for XM_F64, 1e-6 otherwise) */
   double cert_tol;     /* certified iff lambda_min(Z) >= -cert_tol * qbar
                           (<= 0: 1e-7 for XM_F64, 1e-5 otherwise) */
-  int32_t max_outer;   /* trust-region iterations per rank (<= 0: 300) */
+  int32_t max_outer;   /* trust-region iterations per rank (<= 0: 1000) */
   int32_t max_inner;   /* truncated-CG iterations per outer step (<= 0: 3N*r) */
   double delta0;       /* initial trust radius (<= 0: sqrt(3N)/8) */
   int32_t lanczos_max; /* Lanczos iterations per certificate (<= 0: 400) */
   double lanczos_tol;  /* Ritz residual tolerance relative to qbar (<= 0: 1e-6) */
+  int32_t precondition;/* 1: per-frame diagonal preconditioner in truncated CG */
   int32_t verbose;     /* 1: one line per outer iteration on stderr */
 } xm_solve_opts;
 
 /* Fill `opts` with the defaults: compute = XM_F64, r0 = 5, r_max = 7,
- * lift = 1 (a lifted start; set r0 = 3, lift = 0 for the paper's U^0), every
- * other field 0 (= the documented default). */
+ * lift = 1 (a lifted start; set r0 = 3, lift = 0 for the paper's U^0),
+ * precondition = 1, every other field 0 (= the documented default). */
 void xm_default_opts(xm_solve_opts* opts);
 
 typedef struct {
@@ -228,6 +229,46 @@ xm_status xm_certify(xm_problem* p, const double* Y, int32_t r, double tol, int3
  */
 xm_status xm_round(xm_problem* p, const double* Y, int32_t r, double* R_out, double* s_out,
                    double* rho_hat, void* stream);
+
+/*
+ * Translations and landmarks of an anchored rank-3 solution (eq. tpstar):
+ * t[1:] = -A_tt[1:,1:]^{-1} A_rt[:,1:]^T U^T with t_0 = 0, and each landmark
+ * the weighted mean p_k = (1/W_k) sum_o w_o (U_i u_o + t_i), for
+ * U = [s_0 R_0, ..., s_{N-1} R_{N-1}].
+ * R  device [N][3][3] row-major rotations, s device [N] scales (frame 0: I, 1
+ *    as returned by xm_round)
+ * t  device [N][3] or NULL;  pts device [M][3] or NULL (landmarks with no
+ *    observation get 0).  Synchronises `stream`.
+ */
+xm_status xm_recover_tp(xm_problem* p, const double* R, const double* s, double* t, double* pts,
+                        void* stream);
+
+typedef struct {
+  int32_t cg_iters;    /* CG iterations of the Hessian solve */
+  double cg_residual;  /* final relative CG residual */
+  double cost;         /* f = tr(Q U^T U) at (R, s) */
+} xm_adjoint_info;
+
+/*
+ * Adjoint of the certified optimum with respect to the lifted keypoints u_o
+ * and the weights w_o.  For a scalar loss l(R, s, f*) with partials
+ * gR = dl/dR [N][3][3], gs = dl/ds [N] and gcost = dl/d(f*), writes
+ * gu = dl/du [n_obs][3] and gw = dl/dw [n_obs] in the caller's observation
+ * order.  The cost term uses the envelope theorem (d(f*) / du_o = 2 w_o U_i^T e_o,
+ * d(f*) / dw_o = |e_o|^2, e_o the residual of eq. sba at the optimum); the
+ * rotation/scale term solves H lam = grad l by CG on the Riemannian Hessian of
+ * the problem with frame 0 held fixed (FP64 products) and then
+ * dl/du_o = -2 w_o (U_i^T e^lam_o + Udot_i^T e_o), dl/dw_o = -2 <e_o, e^lam_o>,
+ * where Udot_k = lam_s,k R_k + s_k lam_R,k and e^lam the residual of that
+ * direction.  Valid at a tight certified optimum (rank-3, from xm_round).
+ * gR / gs may be NULL (no rotation/scale loss); gu, gw are device buffers of
+ * dtype g_dtype (XM_F64 or XM_F32).  cg_tol (<= 0: 1e-10) is relative to
+ * |grad l|; cg_max <= 0 means 4N.  For callers that differentiate through the
+ * solver (the torch autograd Function of the Python binding).
+ */
+xm_status xm_adjoint(xm_problem* p, const double* R, const double* s, const double* gR,
+                     const double* gs, double gcost, void* gu, void* gw, xm_dtype g_dtype,
+                     double cg_tol, int32_t cg_max, xm_adjoint_info* info, void* stream);
 
 /*
  * Measurement hooks for the Y Q product kernel (the HBM-bound kernel of the

@@ -105,6 +105,27 @@ def q_block_elimination(N, M, frame, landmark, u, w, return_parts=False):
     return Q
 
 
+def q_rows(N, M, frame, landmark, u, w, rows):
+    """Selected rows of Q, for scenes too large for the dense constructions.
+
+    Same block elimination as q_block_elimination, kept sparse: A_rr, A_rt
+    and A_tt from the paper's matrices, then
+    Q[rows, :] = A_rr[rows, :] - (A_tt[1:,1:]^{-1} A_rt[rows, 1:]^T)^T A_rt[:, 1:]^T
+    with one dense Cholesky of the grounded Laplacian (N - 1 squared)."""
+    Q1, Q2, Q3, V1, V2, V3 = paper_matrices(N, M, frame, landmark, u, w)
+    q3 = Q3.diagonal()
+    inv = sp.diags(np.where(q3 > 0, 1.0 / np.where(q3 > 0, q3, 1.0), 0.0))
+    rows = np.asarray(rows)
+    V2r = V2[rows]
+    A_rr_rows = (Q1[rows] - V2r @ inv @ V2.T).toarray()
+    A_rt = (V1 - V2 @ inv @ V3.T).tocsr()
+    A_tt = (Q2 - V3 @ inv @ V3.T).toarray()
+    cf = sla.cho_factor(A_tt[1:, 1:], lower=True)
+    B = A_rt[:, 1:]
+    X = sla.cho_solve(cf, B[rows].toarray().T)          # (N-1) x |rows|
+    return A_rr_rows - (B @ X).T
+
+
 def recover_tp(N, M, frame, landmark, u, w, Y):
     """[t; p] for a given U (r x 3N): eq. tpstar, solved blockwise.
 

@@ -88,13 +88,15 @@ def rtr(Q, R, s, grad_tol=1e-10, max_outer=500, max_inner=None, Delta_bar=None,
         mdec = -(mf.inner(s, gR, gs, eta[0], eta[1]) + 0.5 * mf.inner(s, eta[0], eta[1], Heta[0], Heta[1]))
         reg = max(1.0, abs(f)) * np.finfo(float).eps * 1e3
         rho = (f - fn + reg) / (mdec + reg)
-        if rho < 0.25:
+        # a trial point whose cost is not finite is a failed step: reject, shrink
+        finite = bool(np.isfinite(rho))
+        if not finite or rho < 0.25:
             Delta = Delta / 4.0
         elif rho > 0.75 and reason in ("boundary", "negative curvature"):
             Delta = min(2.0 * Delta, Delta_bar)
         if log is not None:
             log.append((k, f, gnorm, Delta, rho, reason, nin))
-        if mdec > 0 and rho > rho_prime:
+        if finite and mdec > 0 and rho > rho_prime:
             R, s, f = Rn, sn, fn
             gR, gs = mf.rgrad(Q, R, s)
             gnorm = np.sqrt(mf.inner(s, gR, gs, gR, gs))

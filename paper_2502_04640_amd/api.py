@@ -41,7 +41,7 @@ class _SolveOpts(ctypes.Structure):
                 ("compute", ctypes.c_int32),
                 ("grad_tol", ctypes.c_double), ("cert_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("max_inner", ctypes.c_int32), ("delta0", ctypes.c_double), ("lanczos_max", ctypes.c_int32),
-                ("lanczos_tol", ctypes.c_double), ("verbose", ctypes.c_int32)]
+                ("lanczos_tol", ctypes.c_double), ("precondition", ctypes.c_int32), ("verbose", ctypes.c_int32)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -56,6 +56,10 @@ class _Cert(ctypes.Structure):
     _fields_ = [("lambda_min", ctypes.c_double), ("ritz_residual", ctypes.c_double), ("primal", ctypes.c_double),
                 ("dual", ctypes.c_double), ("qbar", ctypes.c_double), ("grad_norm", ctypes.c_double),
                 ("certified", ctypes.c_int32), ("iters", ctypes.c_int32)]
+
+
+class _AdjInfo(ctypes.Structure):
+    _fields_ = [("cg_iters", ctypes.c_int32), ("cg_residual", ctypes.c_double), ("cost", ctypes.c_double)]
 
 
 class _SpmmStats(ctypes.Structure):
@@ -98,6 +102,10 @@ def load_library() -> ctypes.CDLL:
     lib.xm_certify.restype = ctypes.c_int
     lib.xm_round.argtypes = [P, V, I32, V, V, ctypes.POINTER(ctypes.c_double), V]
     lib.xm_round.restype = ctypes.c_int
+    lib.xm_recover_tp.argtypes = [P, V, V, V, V, V]
+    lib.xm_recover_tp.restype = ctypes.c_int
+    lib.xm_adjoint.argtypes = [P, V, V, V, V, D, V, V, ctypes.c_int, D, I32, ctypes.POINTER(_AdjInfo), V]
+    lib.xm_adjoint.restype = ctypes.c_int
     lib.xm_spmm_timing.argtypes = [P, I32]
     lib.xm_spmm_timing.restype = ctypes.c_int
     lib.xm_spmm_stats.argtypes = [P, ctypes.POINTER(_SpmmStats), I32]
@@ -143,6 +151,7 @@ class SolveOptions:
     delta0: float = 0.0
     lanczos_max: int = 0
     lanczos_tol: float = 0.0
+    precondition: bool = True
     verbose: bool = False
 
     def to_c(self) -> _SolveOpts:
@@ -152,6 +161,7 @@ class SolveOptions:
         o.grad_tol, o.cert_tol = self.grad_tol, self.cert_tol
         o.max_outer, o.max_inner, o.delta0 = self.max_outer, self.max_inner, self.delta0
         o.lanczos_max, o.lanczos_tol, o.verbose = self.lanczos_max, self.lanczos_tol, int(self.verbose)
+        o.precondition = int(self.precondition)
         return o
 
 
@@ -239,6 +249,60 @@ class Problem:
         _check(load_library().xm_round(self._h, _ptr(Y), Y.shape[0], _ptr(R), _ptr(s), ctypes.byref(rho),
                                        _stream()))
         return R, s, rho.value
+
+
+    def recover_tp(self, R: torch.Tensor, s: torch.Tensor):
+        """Translations [N,3] and landmarks [M,3] of an anchored rank-3 solution (eq. tpstar)."""
+        R = _dev_tensor(R, torch.float64, "R")
+        s = _dev_tensor(s, torch.float64, "s")
+        t = torch.empty((self.N, 3), dtype=torch.float64, device="cuda")
+        pts = torch.empty((self.M, 3), dtype=torch.float64, device="cuda")
+        _check(load_library().xm_recover_tp(self._h, _ptr(R), _ptr(s), _ptr(t), _ptr(pts), _stream()))
+        return t, pts
+
+    def adjoint(self, R, s, gR=None, gs=None, gcost: float = 0.0, dtype=torch.float64, cg_tol: float = 0.0,
+                cg_max: int = 0):
+        """Gradients (dl/du [n,3], dl/dw [n], info) of a loss l(R, s, f*) with the given partials."""
+        R = _dev_tensor(R, torch.float64, "R")
+        s = _dev_tensor(s, torch.float64, "s")
+        gR = None if gR is None else _dev_tensor(gR.to(torch.float64), torch.float64, "gR")
+        gs = None if gs is None else _dev_tensor(gs.to(torch.float64), torch.float64, "gs")
+        n = self.info()["n_obs"]
+        gu = torch.empty((n, 3), dtype=dtype, device="cuda")
+        gw = torch.empty(n, dtype=dtype, device="cuda")
+        gdt = XM_F64 if dtype == torch.float64 else XM_F32
+        inf = _AdjInfo()
+        _check(load_library().xm_adjoint(self._h, _ptr(R), _ptr(s), _ptr(gR), _ptr(gs), float(gcost), _ptr(gu),
+                                         _ptr(gw), gdt, cg_tol, cg_max, ctypes.byref(inf), _stream()))
+        return gu, gw, {f: getattr(inf, f) for f, _ in _AdjInfo._fields_}
+
+
+class XMSolve(torch.autograd.Function):
+    """(R [N,3,3], s [N], f*) = certified SBA optimum of (u, w); differentiable in u and w.
+
+    forward: xm_build_Q -> xm_bm_solve -> xm_round (f* is the cost of the
+    rounded, anchored solution); backward: xm_adjoint (envelope theorem for f*,
+    implicit-function theorem for R and s).  Valid at tight certified optima.
+    """
+
+    @staticmethod
+    def forward(ctx, u, w, frame, landmark, N, M, opts=None):
+        P = build_Q(N, M, frame, landmark, u, w, keep=("f32",) if (opts and opts.compute != "f64") else ())
+        Y, info = P.solve(opts or SolveOptions())
+        R, s, rho = P.round(Y)
+        ctx.problem = P
+        ctx.info = info
+        ctx.u_dtype, ctx.w_dtype = u.dtype, w.dtype
+        ctx.save_for_backward(R, s)
+        ctx.mark_non_differentiable(R.new_empty(0))
+        return R, s, torch.tensor(rho, dtype=torch.float64, device=R.device)
+
+    @staticmethod
+    def backward(ctx, gR, gs, gcost):
+        R, s = ctx.saved_tensors
+        gc = 0.0 if gcost is None else float(gcost)
+        gu, gw, _ = ctx.problem.adjoint(R, s, gR, gs, gc, dtype=torch.float64)
+        return gu.to(ctx.u_dtype), gw.to(ctx.w_dtype), None, None, None, None, None
 
 
 def build_Q(N: int, M: int, frame: torch.Tensor, landmark: torch.Tensor, u: torch.Tensor,

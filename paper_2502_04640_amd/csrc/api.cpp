@@ -119,6 +119,7 @@ void xm_default_opts(xm_solve_opts* o) {
   o->delta0 = 0.0;
   o->lanczos_max = 0;
   o->lanczos_tol = 0.0;
+  o->precondition = 1;
   o->verbose = 0;
 }
 
@@ -189,6 +190,30 @@ xm_status xm_spmm_stats(xm_problem* p, xm_spmm_counters* out, int32_t reset) {
     out->total_ms[e.dtype] += ms;
   }
   if (reset) p->events_used = 0;
+  return XM_OK;
+  XM_API_CATCH
+}
+
+xm_status xm_recover_tp(xm_problem* p, const double* R, const double* s, double* t, double* pts, void* stream) {
+  XM_API_TRY
+  if (!p) return fail(XM_EINVAL, "NULL argument");
+  xm::recover_tp(p, R, s, t, pts, as_stream(stream));
+  return XM_OK;
+  XM_API_CATCH
+}
+
+xm_status xm_adjoint(xm_problem* p, const double* R, const double* s, const double* gR, const double* gs,
+                     double gcost, void* gu, void* gw, xm_dtype g_dtype, double cg_tol, int32_t cg_max,
+                     xm_adjoint_info* info, void* stream) {
+  XM_API_TRY
+  if (!p) return fail(XM_EINVAL, "NULL argument");
+  const xm::AdjointResult r =
+      xm::adjoint(p, R, s, gR, gs, gcost, gu, gw, g_dtype, cg_tol, cg_max, as_stream(stream));
+  if (info) {
+    info->cg_iters = r.cg_iters;
+    info->cg_residual = r.cg_residual;
+    info->cost = r.cost;
+  }
   return XM_OK;
   XM_API_CATCH
 }

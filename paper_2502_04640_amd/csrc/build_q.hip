@@ -429,6 +429,14 @@ __global__ __launch_bounds__(kB) void trace_kernel(const double* __restrict__ Q,
   if (threadIdx.x == 0) out[0] = v[0];
 }
 
+// q_kk = tr(Q_kk) / 3 per frame (the preconditioner of the local solver)
+__global__ void diag_block_kernel(const double* __restrict__ Q, int32_t N, int32_t ld, double* __restrict__ q) {
+  const int k = blockIdx.x * kB + threadIdx.x;
+  if (k >= N) return;
+  const int64_t i = 3 * static_cast<int64_t>(k);
+  q[k] = (Q[i * ld + i] + Q[(i + 1) * ld + i + 1] + Q[(i + 2) * ld + i + 2]) / 3.0;
+}
+
 __global__ void to_f32_kernel(const double* __restrict__ in, int64_t n, float* out) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
   if (e < n) out[e] = static_cast<float>(in[e]);
@@ -638,6 +646,9 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
     XM_HIP(hipStreamSynchronize(s));
     P->qbar = htr / P->n3;
   }
+  P->qkk.alloc(N);
+  hipLaunchKernelGGL(diag_block_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, P->Q64.ptr, N, P->ld, P->qkk.ptr);
+  XM_LAUNCH_CHECK("diag_block_kernel");
   if (copies & XM_KEEP_F32) {
     P->Q32.alloc(qn);
     hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(qn, kB)), dim3(kB), 0, s, P->Q64.ptr, static_cast<int64_t>(qn),

@@ -13,19 +13,26 @@ double vec_dot(const T* a, const T* b, int64_t n, double* part, int blocks, hipS
 template <typename T>
 struct Manifold {
   int32_t N;
+  // optional per-frame preconditioner: qkk[k] = tr(Q_kk)/3 (NULL: none) and
+  // pscale = mean_k s_k^2 q_kk at the current point
+  const double* qkk = nullptr;
+  double pscale = 1.0;
   explicit Manifold(int32_t n) : N(n) {}
   unsigned blocks() const { return cdiv(N, 256); }
 
-  // G = Q Yt.  part: [blocks][3] = {cost, |grad|^2 (metric), |Y|_F^2}
+  // G = Q Yt.  part: [blocks][5] = {cost, |grad|^2 (metric), |Y|_F^2, sum s^2 q_kk,
+  //                                 pscale * <grad, P grad>}
   void grad(int r, const T* Rt, const T* s, const T* G, T* gR, T* gs, T* Sc, T* ec, double* part,
             hipStream_t st) const;
   // mode 0: d = -res; 1: d = -res + beta d; 2: d unchanged.  Ydot = ds R + s dR.
   void ydot(int r, const T* Rt, const T* s, const T* resR, const T* ress, T* dR, T* ds, double beta, int mode,
             T* Ydot, hipStream_t st) const;
-  // part: [blocks][4] = {<d,Hd>, <d,d>, <eta,d>, <eta,eta>}
+  // part: [blocks][4] = {<d,Hd>, <d,Md>, <eta,Md>, <eta,M eta>} (M: preconditioner, identity if none)
+  // anchor0: frame 0 held fixed (its rows of the output are zero)
   void hess(int r, const T* Rt, const T* s, const T* G, const T* Sc, const T* ec, const T* dR, const T* ds,
-            const T* Gd, const T* etaR, const T* etas, T* HR, T* Hs, double* part, hipStream_t st) const;
-  // part: [blocks][1] = {<res,res>} (mode 0)
+            const T* Gd, const T* etaR, const T* etas, T* HR, T* Hs, double* part, hipStream_t st,
+            bool anchor0 = false) const;
+  // part: [blocks][2] = {<res,res>, <res, P res>} (mode 0)
   void tcg_update(int r, const T* s, double alpha, int mode, const T* dR, const T* ds, const T* HdR, const T* Hds,
                   T* etaR, T* etas, T* HetaR, T* Hetas, T* resR, T* ress, double* part, hipStream_t st) const;
   void retract(int r, const T* Rt, const T* s, const T* etaR, const T* etas, T* Rt2, T* s2, T* Yt2,

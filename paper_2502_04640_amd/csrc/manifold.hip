@@ -95,6 +95,17 @@ __device__ __forceinline__ void sub_xs(Blk<T, R>& out, const Blk<T, R>& x, const
     }
 }
 
+// Per-frame preconditioner weight c_k = s_k^2 q_kk / pscale (q_kk = tr(Q_kk)/3;
+// pscale = mean over frames of s_k^2 q_kk), or 1 when qkk is NULL.  The
+// preconditioner M acts as c_k on the rotation part and 3 c_k on the scale
+// part of a tangent vector (the diagonal of the Hessian with Q_kk replaced by
+// q_kk I); P = M^{-1}.
+__device__ __forceinline__ double prec_weight(const double* qkk, double pscale, double s) {
+  return qkk ? s * s * qkk[0] / pscale : 1.0;
+}
+// factor of the scale part relative to the rotation part (1 without a preconditioner)
+__device__ __forceinline__ double prec_sfac(const double* qkk) { return qkk ? 3.0 : 1.0; }
+
 template <int NQ>
 __device__ __forceinline__ void write_partials(double (&v)[NQ], double* part) {
   __shared__ double lds[NQ * (kB / 64)];
@@ -107,9 +118,10 @@ __device__ __forceinline__ void write_partials(double (&v)[NQ], double* part) {
 template <typename T, int R>
 __global__ __launch_bounds__(kB) void grad_kernel(int32_t N, const T* __restrict__ Rt, const T* __restrict__ s,
                                                   const T* __restrict__ G, T* __restrict__ gR, T* __restrict__ gs,
-                                                  T* __restrict__ Sc, T* __restrict__ ec, double* part) {
+                                                  T* __restrict__ Sc, T* __restrict__ ec, const double* qkk,
+                                                  double* part) {
   const int k = blockIdx.x * kB + threadIdx.x;
-  double v[3] = {0.0, 0.0, 0.0};
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (k < N) {
     Blk<T, R> Rk, Gam;
     Rk.load(Rt, k);
@@ -144,8 +156,13 @@ __global__ __launch_bounds__(kB) void grad_kernel(int32_t N, const T* __restrict
     v[0] = 0.5 * static_cast<double>(sk) * e;
     v[1] = dotb(g, g) + ((k == 0) ? 0.0 : static_cast<double>(gsk) * gsk / (static_cast<double>(sk) * sk));
     v[2] = 3.0 * static_cast<double>(sk) * sk;
+    // unnormalised preconditioner sums: s^2 q_kk and <g, M^{-1} g> * pscale
+    const double w = prec_weight(qkk ? qkk + k : nullptr, 1.0, static_cast<double>(sk));
+    v[3] = w;
+    v[4] = dotb(g, g) / w +
+           ((k == 0) ? 0.0 : static_cast<double>(gsk) * gsk / (prec_sfac(qkk) * w * static_cast<double>(sk) * sk));
   }
-  write_partials<3>(v, part);
+  write_partials<5>(v, part);
 }
 
 // mode 0: delta = -res;  mode 1: delta = -res + beta * delta;  mode 2: delta as is.
@@ -154,7 +171,7 @@ template <typename T, int R>
 __global__ __launch_bounds__(kB) void ydot_kernel(int32_t N, const T* __restrict__ Rt, const T* __restrict__ s,
                                                   const T* __restrict__ resR, const T* __restrict__ ress,
                                                   T* __restrict__ dR, T* __restrict__ ds, double beta, int mode,
-                                                  T* __restrict__ Ydot) {
+                                                  const double* qkk, double pscale, T* __restrict__ Ydot) {
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= N) return;
   Blk<T, R> Rk, d;
@@ -164,8 +181,16 @@ __global__ __launch_bounds__(kB) void ydot_kernel(int32_t N, const T* __restrict
     d.load(dR, k);
     dsk = ds[k];
   } else {
+    // preconditioned residual z = P res
     Blk<T, R> r;
     r.load(resR, k);
+    const double c = prec_weight(qkk ? qkk + k : nullptr, pscale, static_cast<double>(s[k]));
+    const T ic = static_cast<T>(1.0 / c), ic3 = static_cast<T>(1.0 / (prec_sfac(qkk) * c));
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+      for (int a = 0; a < R; ++a) r.v[cc][a] *= ic;
+    const T rs = ress[k] * ic3;
     if (mode == 1) {
       d.load(dR, k);
       const T b = static_cast<T>(beta);
@@ -173,13 +198,13 @@ __global__ __launch_bounds__(kB) void ydot_kernel(int32_t N, const T* __restrict
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int a = 0; a < R; ++a) d.v[c][a] = -r.v[c][a] + b * d.v[c][a];
-      dsk = -ress[k] + b * ds[k];
+      dsk = -rs + b * ds[k];
     } else {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int a = 0; a < R; ++a) d.v[c][a] = -r.v[c][a];
-      dsk = -ress[k];
+      dsk = -rs;
     }
     d.store(dR, k);
     ds[k] = dsk;
@@ -199,10 +224,15 @@ __global__ __launch_bounds__(kB) void hess_kernel(int32_t N, const T* __restrict
                                                   const T* __restrict__ ec, const T* __restrict__ dR,
                                                   const T* __restrict__ ds, const T* __restrict__ Gd,
                                                   const T* __restrict__ etaR, const T* __restrict__ etas,
-                                                  T* __restrict__ HR, T* __restrict__ Hs, double* part) {
+                                                  T* __restrict__ HR, T* __restrict__ Hs, const double* qkk,
+                                                  double pscale, double* part, int anchor0) {
   const int k = blockIdx.x * kB + threadIdx.x;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  if (k < N) {
+  if (k == 0 && anchor0) {
+    // frame 0 held fixed (anchored chart): the Hessian is projected onto the other frames
+    for (int e = 0; e < 3 * R; ++e) HR[e] = T(0);
+    Hs[0] = T(0);
+  } else if (k < N) {
     Blk<T, R> Rk, Gam, Gdd, Rd, Z;
     Rk.load(Rt, k);
     Gam.load(G, k);
@@ -236,10 +266,12 @@ __global__ __launch_bounds__(kB) void hess_kernel(int32_t N, const T* __restrict
     Blk<T, R> eta;
     eta.load(etaR, k);
     const double es = etas[k];
+    // the trust region is measured in the preconditioner norm <a, M b>
+    const double c = prec_weight(qkk ? qkk + k : nullptr, pscale, sd), c3 = prec_sfac(qkk) * c * is2;
     v[0] = dotb(Rd, Z) + static_cast<double>(dsk) * hs * is2;                               // <d, Hd>
-    v[1] = dotb(Rd, Rd) + static_cast<double>(dsk) * static_cast<double>(dsk) * is2;        // <d, d>
-    v[2] = dotb(eta, Rd) + es * static_cast<double>(dsk) * is2;                             // <eta, d>
-    v[3] = dotb(eta, eta) + es * es * is2;                                                  // <eta, eta>
+    v[1] = c * dotb(Rd, Rd) + c3 * static_cast<double>(dsk) * static_cast<double>(dsk);     // <d, M d>
+    v[2] = c * dotb(eta, Rd) + c3 * es * static_cast<double>(dsk);                          // <eta, M d>
+    v[3] = c * dotb(eta, eta) + c3 * es * es;                                               // <eta, M eta>
   }
   write_partials<4>(v, part);
 }
@@ -252,9 +284,10 @@ __global__ __launch_bounds__(kB) void tcg_update_kernel(int32_t N, const T* __re
                                                         const T* __restrict__ HdR, const T* __restrict__ Hds,
                                                         T* __restrict__ etaR, T* __restrict__ etas,
                                                         T* __restrict__ HetaR, T* __restrict__ Hetas,
-                                                        T* __restrict__ resR, T* __restrict__ ress, double* part) {
+                                                        T* __restrict__ resR, T* __restrict__ ress, const double* qkk,
+                                                        double pscale, double* part) {
   const int k = blockIdx.x * kB + threadIdx.x;
-  double v[1] = {0.0};
+  double v[2] = {0.0, 0.0};
   if (k < N) {
     const T a = static_cast<T>(alpha);
     Blk<T, R> d, hd, e, he;
@@ -284,10 +317,13 @@ __global__ __launch_bounds__(kB) void tcg_update_kernel(int32_t N, const T* __re
       const T rs = ress[k] + a * Hds[k];
       ress[k] = rs;
       const double sd = static_cast<double>(s[k]);
-      v[0] = dotb(r, r) + ((k == 0) ? 0.0 : static_cast<double>(rs) * rs / (sd * sd));
+      const double rr = dotb(r, r), ss = (k == 0) ? 0.0 : static_cast<double>(rs) * rs / (sd * sd);
+      const double c = prec_weight(qkk ? qkk + k : nullptr, pscale, sd);
+      v[0] = rr + ss;                      // <res, res>
+      v[1] = rr / c + ss / (prec_sfac(qkk) * c);  // <res, P res>
     }
   }
-  write_partials<1>(v, part);
+  write_partials<2>(v, part);
 }
 
 // Gram-Schmidt of the three columns of an r x 3 block (positive-diagonal QR).
@@ -328,7 +364,9 @@ __global__ __launch_bounds__(kB) void retract_kernel(int32_t N, const T* __restr
   gram_schmidt(m);
   m.store(Rt2, k);
   const T sk = s[k];
-  const T sn = (k == 0) ? T(1) : sk * exp(etas[k] / sk);
+  // log-scale step, clamped so that an oversized trial step cannot overflow
+  const T x = fmin(fmax(etas[k] / sk, T(-30)), T(30));
+  const T sn = (k == 0) ? T(1) : sk * exp(x);
   s2[k] = sn;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -499,7 +537,7 @@ template <typename T>
 void Manifold<T>::grad(int r, const T* Rt, const T* s, const T* G, T* gR, T* gs, T* Sc, T* ec, double* part,
                        hipStream_t st) const {
   XM_DISPATCH_R(r, hipLaunchKernelGGL((grad_kernel<T, R>), dim3(blocks()), dim3(kB), 0, st, N, Rt, s, G, gR, gs,
-                                      Sc, ec, part));
+                                      Sc, ec, qkk, part));
   XM_LAUNCH_CHECK("grad_kernel");
 }
 
@@ -507,16 +545,16 @@ template <typename T>
 void Manifold<T>::ydot(int r, const T* Rt, const T* s, const T* resR, const T* ress, T* dR, T* ds, double beta,
                        int mode, T* Ydot, hipStream_t st) const {
   XM_DISPATCH_R(r, hipLaunchKernelGGL((ydot_kernel<T, R>), dim3(blocks()), dim3(kB), 0, st, N, Rt, s, resR, ress,
-                                      dR, ds, beta, mode, Ydot));
+                                      dR, ds, beta, mode, qkk, pscale, Ydot));
   XM_LAUNCH_CHECK("ydot_kernel");
 }
 
 template <typename T>
 void Manifold<T>::hess(int r, const T* Rt, const T* s, const T* G, const T* Sc, const T* ec, const T* dR,
                        const T* ds, const T* Gd, const T* etaR, const T* etas, T* HR, T* Hs, double* part,
-                       hipStream_t st) const {
+                       hipStream_t st, bool anchor0) const {
   XM_DISPATCH_R(r, hipLaunchKernelGGL((hess_kernel<T, R>), dim3(blocks()), dim3(kB), 0, st, N, Rt, s, G, Sc, ec,
-                                      dR, ds, Gd, etaR, etas, HR, Hs, part));
+                                      dR, ds, Gd, etaR, etas, HR, Hs, qkk, pscale, part, anchor0 ? 1 : 0));
   XM_LAUNCH_CHECK("hess_kernel");
 }
 
@@ -525,7 +563,8 @@ void Manifold<T>::tcg_update(int r, const T* s, double alpha, int mode, const T*
                              const T* Hds, T* etaR, T* etas, T* HetaR, T* Hetas, T* resR, T* ress, double* part,
                              hipStream_t st) const {
   XM_DISPATCH_R(r, hipLaunchKernelGGL((tcg_update_kernel<T, R>), dim3(blocks()), dim3(kB), 0, st, N, s, alpha,
-                                      mode, dR, ds, HdR, Hds, etaR, etas, HetaR, Hetas, resR, ress, part));
+                                      mode, dR, ds, HdR, Hds, etaR, etas, HetaR, Hetas, resR, ress, qkk, pscale,
+                                      part));
   XM_LAUNCH_CHECK("tcg_update_kernel");
 }
 

@@ -34,6 +34,9 @@ struct xm_problem {
   xm::DevBuf<double> Gm;
   int32_t ldg = 0;
 
+  // tr(Q_kk) / 3 per frame
+  xm::DevBuf<double> qkk;
+
   // split-row partial sums of the Y Q product (grown on demand)
   xm::DevBuf<char> spmm_scratch;
 
@@ -82,6 +85,15 @@ xm_status bm_solve(xm_problem* p, const xm_solve_opts& o, const double* Y0, int 
 // round.hip
 void round_yt(xm_problem* p, const double* Y, int r, double* R_out, double* s_out, double* rho_hat,
               hipStream_t s);
+
+// adjoint.hip
+struct AdjointResult {
+  int cg_iters = 0;
+  double cg_residual = 0.0, cost = 0.0;
+};
+void recover_tp(xm_problem* p, const double* R, const double* s, double* t_out, double* p_out, hipStream_t st);
+AdjointResult adjoint(xm_problem* p, const double* R, const double* s, const double* gR, const double* gs,
+                      double gcost, void* gu, void* gw, xm_dtype gdt, double cg_tol, int cg_max, hipStream_t st);
 
 // Host sum of per-block partials [blocks][nq] (fixed order) after a stream sync.
 void read_partials(const double* dev, int blocks, int nq, double* out, hipStream_t s);

@@ -40,8 +40,9 @@ __global__ __launch_bounds__(kB) void gram_mfma_kernel(const double* __restrict_
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, acc, 0, 0, 0);
   }
   double* out = part + static_cast<int64_t>(wave) * 256;
+  // v_mfma_f64_16x16x4f64 returns D[(lane / 16) + 4 q][lane % 16] in register q
 #pragma unroll
-  for (int q = 0; q < 4; ++q) out[(4 * (lane >> 4) + q) * 16 + (lane & 15)] = acc[q];
+  for (int q = 0; q < 4; ++q) out[((lane >> 4) + 4 * q) * 16 + (lane & 15)] = acc[q];
 }
 
 template <int NN>

@@ -2,6 +2,13 @@
 // / truncated-CG local optimiser (Absil et al. 2008; Boumal 2023), driven from
 // the host, all vector work in the kernels of manifold.hip / spmm.hip.
 //
+// tCG is preconditioned (option, on by default) by the per-frame scalar
+// M_k = s_k^2 tr(Q_kk)/3 (normalised to mean 1; 3 M_k on the scale part),
+// the diagonal of the Hessian with each 3x3 diagonal block of Q replaced by a
+// multiple of I: it equalises the curvature of frames whose scales and
+// observation counts differ by orders of magnitude; the trust region is then
+// measured in the M-norm (Steihaug-Toint with a preconditioner).
+//
 // Parameters the paper leaves open (textbook defaults): tCG stops at
 // |r| <= |r0| min(|r0|^theta, kappa), kappa = 0.1, theta = 1; steps are
 // accepted when rho > 0.1; the radius is quartered when rho < 1/4 and doubled
@@ -49,23 +56,26 @@ template <typename T>
 RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_solve_opts& o, double grad_tol,
            hipStream_t st) {
   const int N = p->N;
-  const Manifold<T> mf(N);
+  Manifold<T> mf(N);
+  if (o.precondition) mf.qkk = p->qkk.ptr;
   const int nb = static_cast<int>(mf.blocks());
   const double qbar = p->qbar;
   const double Dbar = std::sqrt(3.0 * N);
   double Delta = (o.delta0 > 0) ? o.delta0 : Dbar / 8.0;
-  const int max_outer = (o.max_outer > 0) ? o.max_outer : 300;
+  const int max_outer = (o.max_outer > 0) ? o.max_outer : 1000;
   const int max_inner = (o.max_inner > 0) ? o.max_inner : std::min(3 * N * r, 2000);
   const double kappa = 0.1, theta = 1.0, rho_prime = 0.1;
   RtrOut out;
-  double sums[4];
+  double sums[5];
 
   mf.scale(r, V.Rt.ptr, V.s.ptr, V.Yt.ptr, st);
   spmm_yt<T>(p, qg, V.Yt.ptr, r, V.G.ptr, st);
   ++out.spmm;
   mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
-  read_partials(V.part.ptr, nb, 3, sums, st);
+  read_partials(V.part.ptr, nb, 5, sums, st);
   double f = sums[0], gg = sums[1], gnorm = std::sqrt(sums[1]), ynorm = std::sqrt(sums[2]);
+  // preconditioner scale at the current point and <g, P g>
+  double pscale = sums[3] / N, gpg = sums[4] * pscale;
   const size_t nvr = static_cast<size_t>(3) * N * r;
   int k = 0;
   for (k = 0; k < max_outer; ++k) {
@@ -80,8 +90,9 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
     XM_HIP(hipMemsetAsync(V.Hetas.ptr, 0, N * sizeof(T), st));
     XM_HIP(hipMemcpyAsync(V.resR.ptr, V.gR.ptr, nvr * sizeof(T), hipMemcpyDeviceToDevice, st));
     XM_HIP(hipMemcpyAsync(V.ress.ptr, V.gs.ptr, N * sizeof(T), hipMemcpyDeviceToDevice, st));
-    double r_r = gg;
-    const double norm_r0 = std::sqrt(r_r);
+    mf.pscale = pscale;
+    double z_r = gpg;  // <res, P res>
+    const double norm_r0 = std::sqrt(gg);
     int mode = 0;
     double beta = 0.0;
     bool boundary = false;
@@ -94,7 +105,7 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
               V.etas.ptr, V.HdR.ptr, V.Hds.ptr, V.part.ptr, st);
       read_partials(V.part.ptr, nb, 4, sums, st);
       const double d_Hd = sums[0], d_Pd = sums[1], e_Pd = sums[2], e_Pe = sums[3];
-      const double alpha = r_r / d_Hd;
+      const double alpha = z_r / d_Hd;
       const double e_Pe_new = e_Pe + 2.0 * alpha * e_Pd + alpha * alpha * d_Pd;
       if (d_Hd <= 0.0 || e_Pe_new >= Delta * Delta) {
         const double tau = (-e_Pd + std::sqrt(e_Pd * e_Pd + d_Pd * (Delta * Delta - e_Pe))) / d_Pd;
@@ -105,11 +116,11 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
       }
       mf.tcg_update(r, V.s.ptr, alpha, 0, V.dR.ptr, V.ds.ptr, V.HdR.ptr, V.Hds.ptr, V.etaR.ptr, V.etas.ptr,
                     V.HetaR.ptr, V.Hetas.ptr, V.resR.ptr, V.ress.ptr, V.part.ptr, st);
-      read_partials(V.part.ptr, nb, 1, sums, st);
-      const double r_r_new = sums[0];
+      read_partials(V.part.ptr, nb, 2, sums, st);
+      const double r_r_new = sums[0], z_r_new = sums[1];
       if (std::sqrt(r_r_new) <= norm_r0 * std::min(std::pow(norm_r0, theta), kappa)) break;
-      beta = r_r_new / r_r;
-      r_r = r_r_new;
+      beta = z_r_new / z_r;
+      z_r = z_r_new;
       mode = 1;
     }
     out.inner += std::min(j, max_inner);
@@ -124,9 +135,12 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
     const double df = sums[2];
     const double reg = std::max(1.0, std::fabs(f)) * 1e3 * 2.220446049250313e-16;
     const double rho = (-df + reg) / (mdec + reg);
-    if (rho < 0.25) Delta *= 0.25;
+    // a candidate whose cost is not finite (a scale step that overflowed) is
+    // rejected and the radius cut, like any poor model agreement
+    const bool finite = std::isfinite(rho);
+    if (!finite || rho < 0.25) Delta *= 0.25;
     else if (rho > 0.75 && boundary) Delta = std::min(2.0 * Delta, Dbar);
-    const bool accept = mdec > 0.0 && rho > rho_prime;
+    const bool accept = finite && mdec > 0.0 && rho > rho_prime;
     if (o.verbose)
       std::fprintf(stderr, "[xm] r=%d it=%d f=%.12e |g|=%.3e Delta=%.3e rho=%.3f inner=%d %s%s\n", r, k, f, gnorm,
                    Delta, rho, std::min(j, max_inner), boundary ? "boundary" : "interior", accept ? "" : " rejected");
@@ -136,11 +150,13 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
       std::swap(V.Yt.ptr, V.Yt2.ptr);
       std::swap(V.G.ptr, V.G2.ptr);
       mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
-      read_partials(V.part.ptr, nb, 3, sums, st);
+      read_partials(V.part.ptr, nb, 5, sums, st);
       f = sums[0];
       gg = sums[1];
       gnorm = std::sqrt(gg);
       ynorm = std::sqrt(sums[2]);
+      pscale = sums[3] / N;
+      gpg = sums[4] * pscale;
     }
   }
   if (!out.converged && gnorm <= grad_tol * qbar * ynorm) out.converged = true;
@@ -163,8 +179,8 @@ Check fp64_check(xm_problem* p, const double* Yt64, int r, hipStream_t st) {
   mf.split(r, Yt64, V.Rt.ptr, V.s.ptr, V.Yt.ptr, st);
   spmm_yt<double>(p, XM_F64, V.Yt.ptr, r, V.G.ptr, st);
   mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
-  double sums[3];
-  read_partials(V.part.ptr, static_cast<int>(mf.blocks()), 3, sums, st);
+  double sums[5];
+  read_partials(V.part.ptr, static_cast<int>(mf.blocks()), 5, sums, st);
   return {sums[0], std::sqrt(sums[1])};
 }
 

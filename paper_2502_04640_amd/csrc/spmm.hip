@@ -15,8 +15,22 @@
 namespace xm {
 namespace {
 
+// Launch shape (tuned on MI355X; see the design notes for the sweep):
+//   kTargetBlocks  workgroups the row slabs aim for,
+//   kMaxRows       rows of a slab (bounds the LDS staging of Yt),
+//   kUnroll        rows in flight per thread.
+#ifndef XM_SPMM_TARGET
+#define XM_SPMM_TARGET 2048
+#endif
+#ifndef XM_SPMM_MAXROWS
+#define XM_SPMM_MAXROWS 512
+#endif
+#ifndef XM_SPMM_UNROLL
+#define XM_SPMM_UNROLL 8
+#endif
 constexpr int kB = 256;
-constexpr int kMaxRows = 512;
+constexpr int kMaxRows = XM_SPMM_MAXROWS;
+constexpr int kTargetBlocks = XM_SPMM_TARGET;
 
 template <typename TQ>
 struct QVec;
@@ -76,7 +90,7 @@ __global__ __launch_bounds__(kB) void spmm_split_kernel(const TQ* __restrict__ Q
     for (int a = 0; a < R; ++a) acc[v][a] = TA(0);
   if (j < ld && nrows > 0) {
     const TQ* q = Q + static_cast<int64_t>(i0) * ld + j;
-#pragma unroll 8
+#pragma unroll XM_SPMM_UNROLL
     for (int i = 0; i < nrows; ++i) {
       TA qv[V];
       QVec<TQ>::load(q + static_cast<int64_t>(i) * ld, qv);
@@ -124,7 +138,7 @@ struct Split {
 Split choose_split(int32_t n3, int32_t ld, int V) {
   Split sp;
   sp.col_blocks = cdiv(ld, static_cast<size_t>(kB) * V);
-  const int target = 2048;
+  const int target = kTargetBlocks;
   int splits = static_cast<int>((target + sp.col_blocks - 1) / sp.col_blocks);
   splits = std::max(1, std::min(splits, static_cast<int>(cdiv(n3, 32))));
   int rows = static_cast<int>(cdiv(n3, splits));

@@ -267,3 +267,31 @@ def test_medium_config_q_and_solve(cfg):
         R, s, _ = P.round(Y)
         assert _rot_err(R.cpu().numpy(), Rh_o) <= rot_tol
         assert _gap(info["cost"], oinfo["cost"]) <= gap_tol
+
+
+def test_large_workload_sampled_rows_and_certified_solves():
+    # the benchmark's workload and launch configuration (N=10155, ~8M obs):
+    # sampled rows of Q against the oracle, then the FP32 and FP64 solves are
+    # both certified and agree (rotations within 1e-4 rad, cost gap 1e-5)
+    _say("case: large workload N=10155 (sampled Q rows, FP32 and FP64 solves)")
+    xm = _xm()
+    sc = scenes.make_scene("large", 0)
+    P = _build(sc, keep=("f32",))
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(3 * sc.N, size=12, replace=False))
+    rows[0] = 0
+    Qo = odm.q_rows(sc.N, sc.M, sc.frame, sc.landmark, sc.u, sc.w, rows)
+    Qg = np.stack([P.Q_rows(int(r), 1).cpu().numpy()[0] for r in rows])
+    assert np.abs(Qg - Qo).max() <= 1e-9 * np.abs(Qo).max()
+    Y32, i32 = P.solve(xm.SolveOptions(compute="f32"))
+    _say(f"  f32: r={i32['r']} cert={i32['certified']} outer={i32['outer_iters']} inner={i32['inner_iters']} "
+         f"solve_ms={i32['solve_ms']:.0f} cert_ms={i32['cert_ms']:.0f}")
+    Y64, i64 = P.solve(xm.SolveOptions(compute="f64"))
+    _say(f"  f64: r={i64['r']} cert={i64['certified']} outer={i64['outer_iters']} inner={i64['inner_iters']} "
+         f"solve_ms={i64['solve_ms']:.0f} cert_ms={i64['cert_ms']:.0f}")
+    assert i32["certified"] == 1 and i64["certified"] == 1
+    R32, s32, rho32 = P.round(Y32)
+    R64, s64, rho64 = P.round(Y64)
+    assert _rot_err(R32.cpu().numpy(), R64.cpu().numpy()) <= 1e-4
+    assert _gap(i32["cost"], i64["cost"]) <= 1e-5
+    assert _gap(i64["primal"], i64["dual"]) <= 1e-6

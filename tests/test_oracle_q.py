@@ -105,3 +105,11 @@ def test_single_observation_landmark_contributes_nothing():
     w = np.r_[sc.w, 1.7]
     Q1 = dm.q_block_elimination(sc.N, sc.M + 1, fr, lm, u, w)
     assert np.abs(Q1 - Q0).max() <= 1e-12 * np.abs(Q0).max()
+
+
+def test_q_rows_equals_full_construction():
+    sc = scenes.random_scene(9, 120, L=4, sigma=0.03, seed=12, weights=(0.5, 1.5))
+    Q = dm.q_block_elimination(*_args(sc))
+    rows = np.array([0, 4, 13, 26])
+    Qr = dm.q_rows(*_args(sc), rows)
+    assert np.abs(Qr - Q[rows]).max() <= 1e-12 * np.abs(Q).max()
