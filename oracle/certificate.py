@@ -16,6 +16,16 @@ tolerance, certified <=> lambda_min >= -tau * qbar, qbar = tr(Q)/3N; the
 minimum eigenvalue is taken on the orthogonal complement of the rows of U
 (Z U^T = 0 puts those directions at zero); the escape vector is normalised
 to unit length with its largest-magnitude entry positive.
+
+Block-Jacobi scaled form (what the GPU's Lanczos measures): with
+D = blkdiag(Q_kk), Zs = D^{-1/2} Z D^{-1/2} is congruent to Z, so by
+Sylvester's law of inertia both have the same number of negative
+eigenvalues.  min_eig_scaled takes the smallest eigenvalue ls of Zs on the
+orthogonal complement of D^{1/2} rows(U) (the D-orthogonal complement of
+rows(U) in the coordinates of Z); for v in that complement
+v^T Z v >= ls v^T D v, which gives the lower bound
+lambda_bound = ls * (d_min if ls >= 0 else d_max) over unit v, d_min, d_max
+the extreme eigenvalues of the Q_kk.
 """
 from __future__ import annotations
 
@@ -64,6 +74,42 @@ def min_eig(Z, U):
     return float(lam[0]), v, full
 
 
+def block_sqrt(Q):
+    """Q_kk^{1/2}, Q_kk^{-1/2} per frame and (d_min, d_max) over all blocks (eigh)."""
+    N = Q.shape[0] // 3
+    Dh = np.empty((N, 3, 3))
+    Dm = np.empty((N, 3, 3))
+    lo, hi = np.inf, -np.inf
+    for k in range(N):
+        B = Q[3 * k:3 * k + 3, 3 * k:3 * k + 3]
+        lam, V = np.linalg.eigh(0.5 * (B + B.T))
+        lam = np.maximum(lam, 1e-12 * lam[-1])
+        Dh[k] = (V * np.sqrt(lam)) @ V.T
+        Dm[k] = (V / np.sqrt(lam)) @ V.T
+        lo, hi = min(lo, lam[0]), max(hi, lam[-1])
+    return Dh, Dm, float(lo), float(hi)
+
+
+def _blkdiag(B):
+    N = B.shape[0]
+    M = np.zeros((3 * N, 3 * N))
+    for k in range(N):
+        M[3 * k:3 * k + 3, 3 * k:3 * k + 3] = B[k]
+    return M
+
+
+def min_eig_scaled(Q, Z, U):
+    """Smallest eigenvalue of Zs = D^{-1/2} Z D^{-1/2} on the orthogonal
+    complement of D^{1/2} rows(U), D = blkdiag(Q_kk), and the lower bound on
+    v^T Z v (unit v, D-orthogonal to rows(U)) it implies.  Dense."""
+    Dh, Dm, dmin, dmax = block_sqrt(Q)
+    Dmh = _blkdiag(Dm)
+    Zs = Dmh @ Z @ Dmh
+    lam, _, _ = min_eig(0.5 * (Zs + Zs.T), U @ _blkdiag(Dh))
+    bound = lam * (dmin if lam >= 0 else dmax)
+    return lam, bound, dmin, dmax
+
+
 def certify(Q, R, s, tau):
     """Certificate at (R, s): dict with lambda_min (complement), lambda_min_full,
     primal tr(Q U^T U), dual tr(Lambda_0), certified flag and escape vector."""
@@ -71,12 +117,14 @@ def certify(Q, R, s, tau):
     Lam = dual_lambda(Q, U, s)
     Z = dual_matrix(Q, Lam)
     lam, v, full = min_eig(Z, U)
+    lam_s, bound, dmin, dmax = min_eig_scaled(Q, Z, U)
     N = R.shape[0]
     qbar = float(np.trace(Q)) / (3 * N)
     primal = float(np.sum(U * (U @ Q)))
     dual = float(np.trace(Lam[0]))
     return {"lambda_min": lam, "lambda_min_full": full, "v": v, "primal": primal,
-            "dual": dual, "certified": bool(lam >= -tau * qbar), "qbar": qbar, "Lambda": Lam}
+            "dual": dual, "certified": bool(lam >= -tau * qbar), "qbar": qbar, "Lambda": Lam,
+            "lambda_min_scaled": lam_s, "lambda_bound": bound, "dmin": dmin, "dmax": dmax}
 
 
 def suboptimality(rho_hat, rho_sdp):

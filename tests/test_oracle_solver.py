@@ -219,3 +219,52 @@ def test_suboptimality_tight_scene():
     eta = ce.suboptimality(rho_hat, info["cost"])
     assert info["certified"] and info["r"] == 3
     assert 0 <= eta + 1e-12 and eta <= 1e-10
+
+
+def _d_complement_gen_eig(Q, Z, U):
+    """min of v^T Z v / v^T D v over v D-orthogonal to rows(U), D = blkdiag(Q_kk),
+    as a generalized symmetric eigenproblem on an explicit basis (scipy)."""
+    import scipy.linalg as sla
+    N = Q.shape[0] // 3
+    D = np.zeros_like(Q)
+    for k in range(N):
+        D[3 * k:3 * k + 3, 3 * k:3 * k + 3] = Q[3 * k:3 * k + 3, 3 * k:3 * k + 3]
+    C = sla.null_space((D @ U.T).T)                  # basis of {v : U D v = 0}
+    return float(sla.eigh(C.T @ Z @ C, C.T @ D @ C, eigvals_only=True)[0]), D
+
+
+@pytest.mark.parametrize("case", ["certified", "spurious"])
+def test_scaled_certificate_inertia_and_bound(case):
+    # Sylvester's law of inertia: Zs = D^{-1/2} Z D^{-1/2} has the sign pattern
+    # of Z; its deflated minimum equals the generalized Rayleigh minimum of
+    # (Z, D) on the D-orthogonal complement of rows(U), and lambda_bound bounds
+    # v^T Z v for unit v there.
+    if case == "certified":
+        sc = scenes.make_scene("tiny", 1)
+        Q = _Q(sc)
+        R, s, _ = st.staircase(Q, grad_tol=1e-11)
+    else:
+        sc = scenes.random_scene(8, 40, L=3, sigma=0.5, seed=0)
+        Q = _Q(sc)
+        rng = np.random.default_rng(0)
+        R, s = mf.gram_schmidt(rng.standard_normal((sc.N, 3, 3))), np.exp(rng.standard_normal(sc.N) * 0.3)
+        s[0] = 1.0
+        R, s, _ = rtr.rtr(Q, R, s, grad_tol=1e-11)
+    c = ce.certify(Q, R, s, 1e-8)
+    U = mf.to_U(R, s)
+    Z = ce.dual_matrix(Q, c["Lambda"])
+    gen, D = _d_complement_gen_eig(Q, Z, U)
+    assert abs(c["lambda_min_scaled"] - gen) <= 1e-9 * max(1.0, abs(gen))
+    n_neg = lambda A: int(np.sum(np.linalg.eigvalsh(A) < -1e-9 * np.abs(A).max()))
+    Dm = np.linalg.inv(np.linalg.cholesky(D))
+    assert n_neg(Dm @ Z @ Dm.T) == n_neg(Z)
+    if case == "certified":
+        assert c["lambda_min_scaled"] >= -1e-9 and c["lambda_bound"] >= -1e-8 * c["qbar"]
+    else:
+        assert c["lambda_min"] < 0 and c["lambda_min_scaled"] < 0 and c["lambda_bound"] < 0
+    rng = np.random.default_rng(5)
+    P = np.eye(Q.shape[0]) - (D @ U.T) @ np.linalg.solve(U @ D @ D @ U.T, U @ D)
+    for _ in range(200):
+        v = P @ rng.standard_normal(Q.shape[0])
+        v /= np.linalg.norm(v)
+        assert v @ Z @ v >= c["lambda_bound"] - 1e-9 * c["qbar"]
