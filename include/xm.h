@@ -134,6 +134,20 @@ xm_status xm_get_Q_rows(const xm_problem* p, int32_t row0, int32_t nrows, double
 xm_status xm_spmm(xm_problem* p, xm_dtype dtype, const double* Y, int32_t r, double* out,
                   void* stream);
 
+/*
+ * Which kernel computes the Y Q product for the stored Q of precision `dtype`
+ * (every product on the handle: solver, certificate, xm_spmm).  Q is
+ * symmetric, so the product can be formed from the upper triangle alone:
+ *   XM_SPMM_FULL   every element of Q is read once ((3N)^2 elements);
+ *   XM_SPMM_UPPER  only Q[i][j], j >= i, is read (3N(3N+1)/2 elements), each
+ *                  feeding both out[j] and out[i]: half the HBM bytes, with
+ *                  twice the arithmetic per byte and a cross-lane reduction.
+ * Both are deterministic; their results differ by rounding order only.
+ * Defaults: XM_SPMM_UPPER for FP64 and FP32, XM_SPMM_FULL for BF16.
+ */
+typedef enum { XM_SPMM_FULL = 0, XM_SPMM_UPPER = 1 } xm_spmm_kind;
+xm_status xm_set_spmm_kind(xm_problem* p, xm_dtype dtype, xm_spmm_kind kind);
+
 typedef struct {
   int32_t r0;          /* initial rank (>= 3); the staircase starts here */
   int32_t r_max;       /* maximum rank (r0 <= r_max <= 7) */
@@ -145,8 +159,11 @@ typedef struct {
                           manifold arithmetic; XM_BF16: BF16-stored Q for the
                           Hessian products, FP32 Q for gradient and cost */
   double grad_tol;     /* stop when ||grad|| <= grad_tol * qbar * ||Y||_F
-                          (<= 0: 1e-9 for XM_F64, 1e-6 otherwise) */
-  double cert_tol;     /* certified iff lambda_min(Z) >= -cert_tol * qbar
+                          (<= 0: 1e-9 for XM_F64, 1e-7 otherwise); also stop,
+                          counted as converged at the arithmetic's floor, after
+                          6 consecutive rejected trust-region steps while
+                          ||grad|| <= 30 grad_tol * qbar * ||Y||_F */
+  double cert_tol;     /* certified iff the lower bound on lambda_min(Z) >= -cert_tol * qbar
                           (<= 0: 1e-7 for XM_F64, 1e-5 otherwise) */
   int32_t max_outer;   /* trust-region iterations per rank (<= 0: 1000) */
   int32_t max_inner;   /* truncated-CG iterations per outer step (<= 0: 3N*r) */
@@ -170,10 +187,12 @@ typedef struct {
   int32_t stair_steps;   /* rank increases taken */
   int32_t spmm_count;    /* Y Q products in the solve (excluding the certificate) */
   int32_t lanczos_iters; /* Lanczos iterations, all certificates */
-  int32_t converged;     /* 1 if the gradient tolerance was met at the final rank */
+  int32_t converged;     /* 1 if the gradient tolerance was met at the final rank,
+                            2 if the solve stopped at the precision floor (grad_tol) */
   double cost;           /* f = tr(Q Y^T Y), FP64 */
   double grad_norm;      /* final Riemannian gradient norm from FP64 products */
-  double lambda_min;     /* minimum eigenvalue of Z at the final point */
+  double lambda_min;     /* lower bound on the minimum eigenvalue of Z at the final
+                            point (xm_cert.lambda_bound of the last certificate) */
   double primal, dual;   /* tr(Q Y^T Y) and tr(Lambda_0) */
   double solve_ms;       /* wall time of the local solves, milliseconds */
   double cert_ms;        /* wall time of the certificates, milliseconds */
@@ -195,23 +214,31 @@ xm_status xm_bm_solve(xm_problem* p, const xm_solve_opts* opts, const double* Y0
                       double* Y_out, xm_solve_info* info, void* stream);
 
 typedef struct {
-  double lambda_min;     /* minimum eigenvalue of Z on the complement of rows(Y) */
+  double lambda_min;     /* minimum eigenvalue of the block-Jacobi scaled dual
+                            D^{-1/2} Z D^{-1/2} (D = blkdiag(Q_kk)) on the
+                            complement of D^{1/2} rows(Y); same sign as that of Z */
   double ritz_residual;  /* residual norm of the Ritz pair of lambda_min */
+  double lambda_bound;   /* lower bound on v^T Z v over unit v D-orthogonal to rows(Y):
+                            (lambda_min - ritz_residual) * (d_min or d_max of the Q_kk);
+                            exact given that Lanczos found the smallest eigenvalue */
   double primal;         /* tr(Q Y^T Y) */
   double dual;           /* tr(Lambda_0), the dual objective b^T y */
   double qbar;           /* tr(Q) / 3N */
   double grad_norm;      /* || Z Y^T ||_F, the stationarity residual */
-  int32_t certified;     /* lambda_min >= -tol * qbar */
+  int32_t certified;     /* lambda_bound >= -tol * qbar */
   int32_t iters;         /* Lanczos iterations */
 } xm_cert;
 
 /*
  * Dual certificate at Y (Theorem "Dual Optimality Certificate").
  * Lambda_k = sym((Q Y^T)_k Y_k) / alpha_k (traceless for k >= 1),
- * Z = Q - blkdiag(Lambda), lambda_min(Z) by FP64 Lanczos with full
- * reorthogonalisation, deflated against the rows of Y.
+ * Z = Q - blkdiag(Lambda).  PSD-ness of Z is decided by FP64 Lanczos with full
+ * reorthogonalisation on the congruent D^{-1/2} Z D^{-1/2} (same inertia,
+ * narrower spectrum), deflated against D^{1/2} rows(Y); certified iff the
+ * lower bound lambda_bound >= -tol * qbar.
  * Y      device [r][3N], 1 <= r <= 8;  tol: relative tolerance (<= 0: 1e-7)
- * v_min  device [3N] unit eigenvector of lambda_min, or NULL.
+ * v_min  device [3N] unit direction D^{-1/2} x of the Ritz vector x of lambda_min
+ *        (v^T Z v < 0 when lambda_min < 0), or NULL.
  * Synchronises `stream`.
  */
 xm_status xm_certify(xm_problem* p, const double* Y, int32_t r, double tol, int32_t max_iter,
@@ -276,9 +303,11 @@ xm_status xm_adjoint(xm_problem* p, const double* R, const double* s, const doub
  * launch of the product kernel on a handle is bracketed by two HIP events on
  * the stream it runs on.  xm_spmm_stats synchronises those events and returns,
  * per stored precision (index = xm_dtype), the number of launches, their total
- * device time and the algorithmic bytes of one launch, (3N)^2 times the
- * element size (each stored element of Q is read once).  reset != 0 forgets
- * the recorded launches.
+ * device time and the algorithmic bytes of one launch (averaged over the
+ * recorded launches): the elements of Q the kernel must read (see
+ * xm_set_spmm_kind) times the element size.  Only the main product kernel is
+ * bracketed, not the pass that adds its partial sums.  reset != 0 forgets the
+ * recorded launches.
  */
 typedef struct {
   int64_t launches[3];

@@ -53,7 +53,8 @@ class _SolveInfo(ctypes.Structure):
 
 
 class _Cert(ctypes.Structure):
-    _fields_ = [("lambda_min", ctypes.c_double), ("ritz_residual", ctypes.c_double), ("primal", ctypes.c_double),
+    _fields_ = [("lambda_min", ctypes.c_double), ("ritz_residual", ctypes.c_double),
+                ("lambda_bound", ctypes.c_double), ("primal", ctypes.c_double),
                 ("dual", ctypes.c_double), ("qbar", ctypes.c_double), ("grad_norm", ctypes.c_double),
                 ("certified", ctypes.c_int32), ("iters", ctypes.c_int32)]
 
@@ -106,6 +107,8 @@ def load_library() -> ctypes.CDLL:
     lib.xm_recover_tp.restype = ctypes.c_int
     lib.xm_adjoint.argtypes = [P, V, V, V, V, D, V, V, ctypes.c_int, D, I32, ctypes.POINTER(_AdjInfo), V]
     lib.xm_adjoint.restype = ctypes.c_int
+    lib.xm_set_spmm_kind.argtypes = [P, ctypes.c_int, ctypes.c_int]
+    lib.xm_set_spmm_kind.restype = ctypes.c_int
     lib.xm_spmm_timing.argtypes = [P, I32]
     lib.xm_spmm_timing.restype = ctypes.c_int
     lib.xm_spmm_stats.argtypes = [P, ctypes.POINTER(_SpmmStats), I32]
@@ -199,6 +202,12 @@ class Problem:
         out = torch.empty_like(Y)
         _check(load_library().xm_spmm(self._h, _DT[dtype], _ptr(Y), Y.shape[0], _ptr(out), _stream()))
         return out
+
+    def set_spmm_kind(self, dtype: str, kind: str):
+        """Product kernel for the stored Q of `dtype`: "upper" (reads the upper
+        triangle only) or "full" (reads all of Q)."""
+        k = {"full": 0, "upper": 1}[kind]
+        _check(load_library().xm_set_spmm_kind(self._h, _DT[dtype], k))
 
     def spmm_timing(self, enable: bool = True):
         _check(load_library().xm_spmm_timing(self._h, int(enable)))

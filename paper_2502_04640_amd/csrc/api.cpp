@@ -146,6 +146,7 @@ xm_status xm_certify(xm_problem* p, const double* Y, int32_t r, double tol, int3
   const xm::CertResult c = xm::certify_yt(p, Yt.ptr, r, t, max_iter, 0.0, v_min, s);
   cert->lambda_min = c.lambda_min;
   cert->ritz_residual = c.ritz_residual;
+  cert->lambda_bound = c.lambda_bound;
   cert->primal = c.primal;
   cert->dual = c.dual;
   cert->qbar = p->qbar;
@@ -165,6 +166,16 @@ xm_status xm_round(xm_problem* p, const double* Y, int32_t r, double* R_out, dou
   XM_API_CATCH
 }
 
+xm_status xm_set_spmm_kind(xm_problem* p, xm_dtype dtype, xm_spmm_kind kind) {
+  XM_API_TRY
+  if (!p) return fail(XM_EINVAL, "NULL argument");
+  if (dtype < XM_F64 || dtype > XM_BF16) return fail(XM_EINVAL, "unknown dtype");
+  if (kind != XM_SPMM_FULL && kind != XM_SPMM_UPPER) return fail(XM_EINVAL, "unknown product kernel");
+  p->spmm_kind[dtype] = kind;
+  return XM_OK;
+  XM_API_CATCH
+}
+
 xm_status xm_spmm_timing(xm_problem* p, int32_t enable) {
   XM_API_TRY
   if (!p) return fail(XM_EINVAL, "NULL argument");
@@ -177,10 +188,6 @@ xm_status xm_spmm_stats(xm_problem* p, xm_spmm_counters* out, int32_t reset) {
   XM_API_TRY
   if (!p || !out) return fail(XM_EINVAL, "NULL argument");
   *out = xm_spmm_counters{};
-  const double elems = static_cast<double>(p->n3) * static_cast<double>(p->n3);
-  out->bytes_per_launch[XM_F64] = elems * 8.0;
-  out->bytes_per_launch[XM_F32] = elems * 4.0;
-  out->bytes_per_launch[XM_BF16] = elems * 2.0;
   for (size_t i = 0; i < p->events_used; ++i) {
     auto& e = p->events[i];
     XM_HIP(hipEventSynchronize(e.stop));
@@ -188,7 +195,10 @@ xm_status xm_spmm_stats(xm_problem* p, xm_spmm_counters* out, int32_t reset) {
     XM_HIP(hipEventElapsedTime(&ms, e.start, e.stop));
     out->launches[e.dtype] += 1;
     out->total_ms[e.dtype] += ms;
+    out->bytes_per_launch[e.dtype] += e.bytes;
   }
+  for (int d = 0; d < 3; ++d)
+    if (out->launches[d] > 0) out->bytes_per_launch[d] /= static_cast<double>(out->launches[d]);
   if (reset) p->events_used = 0;
   return XM_OK;
   XM_API_CATCH

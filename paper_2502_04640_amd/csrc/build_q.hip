@@ -228,44 +228,65 @@ __global__ void scatter_grounded_kernel(const int32_t* __restrict__ row_ptr, con
 // Sweeping the pivot set K of a symmetric A:
 //   A_KK <- -A_KK^{-1}, A_iK <- A_iK A_KK^{-1}, A_Kj <- A_KK^{-1} A_Kj,
 //   A_ij <- A_ij - A_iK A_KK^{-1} A_Kj   (i, j not in K).
-// Sweeping every index in turn leaves -A^{-1}.
+// Sweeping every index in turn leaves -A^{-1}.  A stays symmetric, so only
+// its upper triangle (64 x 64 tiles J >= I) is kept current; values of A_iK
+// for i past K are read from A_Ki, and the lower triangle is copied from the
+// upper one at the end.  The trailing update A_ij -= C_i P_j is a dense
+// rank-64 product per tile on FP64 matrix cores.
 constexpr int kNB = 64;
 
+// -A_KK^{-1} by Gauss-Jordan pivoting in LDS; a last block with nb < 64 is
+// padded with dscale * I.  Dinv (nb x nb) = A_KK^{-1}.
 __global__ __launch_bounds__(kB) void sweep_pivot_kernel(const double* __restrict__ A, int32_t lda,
                                                          int32_t k0, int32_t nb, double dscale,
                                                          double* Dinv, int* flags) {
   __shared__ double D[kNB][kNB + 1];
   const int t = threadIdx.x;
-  for (int e = t; e < nb * nb; e += kB) D[e / nb][e % nb] = A[static_cast<int64_t>(k0 + e / nb) * lda + k0 + e % nb];
+  const int j = t & 63, ibase = t >> 6;  // thread owns column j of rows ibase + 4c
+  for (int c = 0; c < kNB / 4; ++c) {
+    const int i = ibase + 4 * c;
+    D[i][j] = (i < nb && j < nb) ? A[static_cast<int64_t>(k0 + i) * lda + k0 + j] : (i == j ? dscale : 0.0);
+  }
   __syncthreads();
-  for (int p = 0; p < nb; ++p) {
+  for (int p = 0; p < kNB; ++p) {
     const double d = D[p][p];
     if (!(d > 1e-11 * dscale)) {
       if (t == 0) flags[4] = 1;
       return;  // uniform across the block: every thread read the same d
     }
-    // update all (i, j) != p using the old row/column p
-    double upd[(kNB * kNB) / kB];
-    int c = 0;
-    for (int e = t; e < nb * nb; e += kB, ++c) {
-      const int i = e / nb, j = e % nb;
-      upd[c] = (i != p && j != p) ? D[i][j] - D[i][p] * D[p][j] / d : D[i][j];
+    const double inv = 1.0 / d;
+    const double dpj = D[p][j] * inv;
+    double upd[kNB / 4];
+#pragma unroll
+    for (int c = 0; c < kNB / 4; ++c) {
+      const int i = ibase + 4 * c;
+      upd[c] = D[i][j] - D[i][p] * dpj;
     }
     __syncthreads();
-    c = 0;
-    for (int e = t; e < nb * nb; e += kB, ++c) {
-      const int i = e / nb, j = e % nb;
-      if (i != p && j != p) D[i][j] = upd[c];
+    if (j != p) {
+#pragma unroll
+      for (int c = 0; c < kNB / 4; ++c) {
+        const int i = ibase + 4 * c;
+        if (i != p) D[i][j] = upd[c];
+      }
     }
     __syncthreads();
-    if (t < nb && t != p) {
-      D[t][p] /= d;
-      D[p][t] /= d;
+    if (t < kNB && t != p) {
+      D[t][p] *= inv;
+      D[p][t] *= inv;
     }
-    if (t == 0) D[p][p] = -1.0 / d;
+    if (t == 0) D[p][p] = -inv;
     __syncthreads();
   }
-  for (int e = t; e < nb * nb; e += kB) Dinv[e] = -D[e / nb][e % nb];
+  for (int c = 0; c < kNB / 4; ++c) {
+    const int i = ibase + 4 * c;
+    if (i < nb && j < nb) Dinv[i * nb + j] = -D[i][j];
+  }
+}
+
+// A[i][k0+p] through the upper triangle: column K for rows above it, row K otherwise
+__device__ __forceinline__ double panel_value(const double* __restrict__ A, int32_t lda, int32_t k0, int i, int p) {
+  return (i < k0) ? A[static_cast<int64_t>(i) * lda + k0 + p] : A[static_cast<int64_t>(k0 + p) * lda + i];
 }
 
 // Ct[q][i] = sum_p A[i][k0+p] Dinv[p][q] (0 for i in K); Pt[q][i] = A[i][k0+q].
@@ -278,53 +299,60 @@ __global__ __launch_bounds__(kB) void sweep_panel_kernel(const double* __restric
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (i >= n || q >= nb) return;
-  const double* Ai = A + static_cast<int64_t>(i) * lda + k0;
   double acc = 0.0;
-  for (int p = 0; p < nb; ++p) acc += Ai[p] * Ds[p * nb + q];
+  for (int p = 0; p < nb; ++p) acc += panel_value(A, lda, k0, i, p) * Ds[p * nb + q];
   const bool inK = (i >= k0 && i < k0 + nb);
   Ct[static_cast<int64_t>(q) * ldt + i] = inK ? 0.0 : acc;
-  Pt[static_cast<int64_t>(q) * ldt + i] = Ai[q];
+  Pt[static_cast<int64_t>(q) * ldt + i] = panel_value(A, lda, k0, i, q);
 }
 
-// A[i][j] -= sum_p Ct[p][i] Pt[p][j] over a 64 x 64 tile (4 x 4 per thread).
+// A[i][j] -= sum_p Ct[p][i] Pt[p][j] on the 64 x 64 tiles J >= I.  Each wave
+// forms a 32 x 32 quarter as 2 x 2 blocks of v_mfma_f64_16x16x4f64 over 16
+// k-steps: lane l supplies A-operand [i = l % 16][k = l / 16] and B-operand
+// [k = l / 16][j = l % 16]; register q of the result holds [l / 16 + 4 q][l % 16].
+typedef double v4d __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(kB) void sweep_update_kernel(double* A, int32_t lda, int32_t n,
                                                           const double* __restrict__ Ct,
                                                           const double* __restrict__ Pt, int32_t ldt,
                                                           int32_t nb) {
+  if (blockIdx.x < blockIdx.y) return;  // lower tile: not kept
   __shared__ double Cs[kNB][64];
   __shared__ double Ps[kNB][64];
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   const int t = threadIdx.x;
-  for (int e = t; e < nb * 64; e += kB) {
-    const int p = e / 64, c = e % 64;
-    Cs[p][c] = (i0 + c < n) ? Ct[static_cast<int64_t>(p) * ldt + i0 + c] : 0.0;
-    Ps[p][c] = (j0 + c < n) ? Pt[static_cast<int64_t>(p) * ldt + j0 + c] : 0.0;
+  for (int e = t; e < kNB * 64; e += kB) {
+    const int p = e >> 6, c = e & 63;
+    Cs[p][c] = (p < nb && i0 + c < n) ? Ct[static_cast<int64_t>(p) * ldt + i0 + c] : 0.0;
+    Ps[p][c] = (p < nb && j0 + c < n) ? Pt[static_cast<int64_t>(p) * ldt + j0 + c] : 0.0;
   }
   __syncthreads();
-  const int tx = t & 15, ty = t >> 4;
-  double acc[4][4] = {};
-  for (int p = 0; p < nb; ++p) {
-    double a[4], b[4];
+  const int lane = t & 63, wave = t >> 6;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4d acc[2][2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      a[q] = Cs[p][ty * 4 + q];
-      b[q] = Ps[p][tx * 4 + q];
-    }
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k = 0; k < kNB; k += 4) {
+    const double a0 = Cs[k + lk][wi + lr], a1 = Cs[k + lk][wi + 16 + lr];
+    const double b0 = Ps[k + lk][wj + lr], b1 = Ps[k + lk][wj + 16 + lr];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int i = i0 + ty * 4 + x;
-    if (i >= n) continue;
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int j = j0 + tx * 4 + y;
-      if (j < n) A[static_cast<int64_t>(i) * lda + j] -= acc[x][y];
-    }
-  }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + wi + 16 * a + lk + 4 * q;
+        const int j = j0 + wj + 16 * b + lr;
+        if (i < n && j < n) A[static_cast<int64_t>(i) * lda + j] -= acc[a][b][q];
+      }
 }
 
 __global__ void sweep_finish_kernel(double* A, int32_t lda, int32_t n, int32_t k0, int32_t nb,
@@ -343,14 +371,18 @@ __global__ void sweep_finish_kernel(double* A, int32_t lda, int32_t n, int32_t k
 }
 
 // ---- sparse rows x dense:  out[3i+a][c] (+)= sum_{s in row i, j >= 1} Art[s][a] D[j-1][c]
+// With `upper`, only columns c >= 3i are formed (the block upper triangle of a
+// symmetric result; the lower part is copied from it afterwards).
 constexpr int kVPT = 4;
 __global__ __launch_bounds__(kB) void gather_product_kernel(const int32_t* __restrict__ row_ptr,
                                                             const int32_t* __restrict__ col,
                                                             const double* __restrict__ Art,
                                                             const double* __restrict__ D, int32_t ldd,
                                                             int32_t K, double* out, int32_t ldo,
-                                                            int accumulate) {
+                                                            int accumulate, int upper) {
   const int i = blockIdx.y;
+  const int cmin = upper ? 3 * i : 0;
+  if (static_cast<int>(blockIdx.x + 1) * (kB * kVPT) <= cmin) return;  // tile wholly left of the diagonal
   const int c0 = blockIdx.x * (kB * kVPT) + threadIdx.x;
   double acc[3][kVPT] = {};
   const int32_t s0 = row_ptr[i], s1 = row_ptr[i + 1];
@@ -374,7 +406,7 @@ __global__ __launch_bounds__(kB) void gather_product_kernel(const int32_t* __res
 #pragma unroll
     for (int v = 0; v < kVPT; ++v) {
       const int c = c0 + v * kB;
-      if (c < K) {
+      if (c < K && c >= cmin) {
         if (accumulate) o[c] += acc[a][v];
         else o[c] = acc[a][v];
       }
@@ -398,25 +430,22 @@ __global__ __launch_bounds__(kB) void transpose_kernel(const double* __restrict_
   }
 }
 
-// Q <- (Q + Q^T) / 2, one 32 x 32 tile pair (I <= J) per block.
+// Q[c][r] <- Q[r][c] for r < c: the lower triangle copied from the upper one,
+// one 32 x 32 tile pair (I <= J) per block, staged through LDS so that both
+// the read of tile (I, J) and the write of tile (J, I) are coalesced.
 __global__ __launch_bounds__(kB) void symmetrize_kernel(double* Q, int32_t n, int32_t ld) {
   const int I = blockIdx.y, J = blockIdx.x;
   if (I > J) return;
-  __shared__ double a[32][33], b[32][33];
+  __shared__ double a[32][33];
   const int r0 = I * 32, c0 = J * 32;
   for (int e = threadIdx.x; e < 32 * 32; e += kB) {
     const int r = e / 32, c = e % 32;
     a[r][c] = (r0 + r < n && c0 + c < n) ? Q[static_cast<int64_t>(r0 + r) * ld + c0 + c] : 0.0;  // tile (I, J)
-    b[r][c] = (c0 + r < n && r0 + c < n) ? Q[static_cast<int64_t>(c0 + r) * ld + r0 + c] : 0.0;  // tile (J, I)
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 32 * 32; e += kB) {
-    const int r = e / 32, c = e % 32;
-    if (r0 + r < n && c0 + c < n) {
-      const double m = 0.5 * (a[r][c] + b[c][r]);
-      Q[static_cast<int64_t>(r0 + r) * ld + c0 + c] = m;
-      Q[static_cast<int64_t>(c0 + c) * ld + r0 + r] = m;
-    }
+    const int c = e / 32, r = e % 32;  // write row c0 + c of tile (J, I), consecutive r
+    if (r0 + r < n && c0 + c < n && r0 + r < c0 + c) Q[static_cast<int64_t>(c0 + c) * ld + r0 + r] = a[r][c];
   }
 }
 
@@ -435,6 +464,65 @@ __global__ void diag_block_kernel(const double* __restrict__ Q, int32_t N, int32
   if (k >= N) return;
   const int64_t i = 3 * static_cast<int64_t>(k);
   q[k] = (Q[i * ld + i] + Q[(i + 1) * ld + i + 1] + Q[(i + 2) * ld + i + 2]) / 3.0;
+}
+
+// Q_kk^{1/2}, Q_kk^{-1/2} by a cyclic Jacobi eigendecomposition of each 3x3
+// diagonal block; eigenvalues are floored at 1e-12 of their block's largest so
+// that a degenerate block still gives an SPD scaling.  ext[k] = (min, max) eig.
+__global__ void block_sqrt_kernel(const double* __restrict__ Q, int32_t N, int32_t ld, double* __restrict__ Dh,
+                                  double* __restrict__ Dmh, double* __restrict__ ext) {
+  const int k = blockIdx.x * kB + threadIdx.x;
+  if (k >= N) return;
+  double A[3][3], V[3][3];
+  const int64_t i0 = 3 * static_cast<int64_t>(k);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      A[a][b] = 0.5 * (Q[(i0 + a) * ld + i0 + b] + Q[(i0 + b) * ld + i0 + a]);
+      V[a][b] = (a == b) ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= 1e-32 * dia) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        const double apq = A[p][q];
+        if (apq == 0.0) continue;
+        const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int m = 0; m < 3; ++m) {
+          const double amp = A[m][p], amq = A[m][q];
+          A[m][p] = c * amp - s * amq;
+          A[m][q] = s * amp + c * amq;
+        }
+        for (int m = 0; m < 3; ++m) {
+          const double apm = A[p][m], aqm = A[q][m];
+          A[p][m] = c * apm - s * aqm;
+          A[q][m] = s * apm + c * aqm;
+        }
+        for (int m = 0; m < 3; ++m) {
+          const double vmp = V[m][p], vmq = V[m][q];
+          V[m][p] = c * vmp - s * vmq;
+          V[m][q] = s * vmp + c * vmq;
+        }
+      }
+  }
+  double lam[3];
+  const double top = fmax(A[0][0], fmax(A[1][1], A[2][2]));
+  for (int a = 0; a < 3; ++a) lam[a] = fmax(A[a][a], 1e-12 * top);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double hp = 0.0, hm = 0.0;
+      for (int m = 0; m < 3; ++m) {
+        hp += V[a][m] * sqrt(lam[m]) * V[b][m];
+        hm += V[a][m] / sqrt(lam[m]) * V[b][m];
+      }
+      Dh[9 * static_cast<int64_t>(k) + 3 * a + b] = hp;
+      Dmh[9 * static_cast<int64_t>(k) + 3 * a + b] = hm;
+    }
+  ext[2 * k] = fmin(lam[0], fmin(lam[1], lam[2]));
+  ext[2 * k + 1] = fmax(lam[0], fmax(lam[1], lam[2]));
 }
 
 __global__ void to_f32_kernel(const double* __restrict__ in, int64_t n, float* out) {
@@ -613,6 +701,11 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
                          nb, Ct.ptr, P->ldg, Dinv.ptr);
       XM_LAUNCH_CHECK("sweep_finish_kernel");
     }
+    {
+      const unsigned T = cdiv(ng, 32);
+      hipLaunchKernelGGL(symmetrize_kernel, dim3(T, T), dim3(kB), 0, s, P->Gm.ptr, ng, P->ldg);
+      XM_LAUNCH_CHECK("symmetrize_kernel(G)");
+    }
     XM_HIP(hipMemcpyAsync(hflags, flags.ptr, sizeof(hflags), hipMemcpyDeviceToHost, s));
     XM_HIP(hipStreamSynchronize(s));
     require(!hflags[4], XM_EGRAPH, "the view graph is disconnected (grounded Laplacian is singular)");
@@ -623,14 +716,14 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
     const int32_t ldp = static_cast<int32_t>(round_up(ng, 64));
     DevBuf<double> Pm(static_cast<size_t>(P->n3) * ldp);
     hipLaunchKernelGGL(gather_product_kernel, dim3(cdiv(ng, kB * kVPT), N), dim3(kB), 0, s, P->row_ptr.ptr,
-                       P->col.ptr, P->Art.ptr, P->Gm.ptr, P->ldg, ng, Pm.ptr, ldp, 0);
+                       P->col.ptr, P->Art.ptr, P->Gm.ptr, P->ldg, ng, Pm.ptr, ldp, 0, 0);
     XM_LAUNCH_CHECK("gather_product_kernel(P)");
     DevBuf<double> Ptr(static_cast<size_t>(ng) * P->ld);
     hipLaunchKernelGGL(transpose_kernel, dim3(cdiv(ng, 64), cdiv(P->n3, 64)), dim3(kB), 0, s, Pm.ptr, P->n3, ng,
                        ldp, Ptr.ptr, P->ld);
     XM_LAUNCH_CHECK("transpose_kernel");
     hipLaunchKernelGGL(gather_product_kernel, dim3(cdiv(P->n3, kB * kVPT), N), dim3(kB), 0, s, P->row_ptr.ptr,
-                       P->col.ptr, P->Art.ptr, Ptr.ptr, P->ld, P->n3, P->Q64.ptr, P->ld, 1);
+                       P->col.ptr, P->Art.ptr, Ptr.ptr, P->ld, P->n3, P->Q64.ptr, P->ld, 1, 1);
     XM_LAUNCH_CHECK("gather_product_kernel(Q)");
     XM_HIP(hipStreamSynchronize(s));
   }
@@ -649,6 +742,23 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   P->qkk.alloc(N);
   hipLaunchKernelGGL(diag_block_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, P->Q64.ptr, N, P->ld, P->qkk.ptr);
   XM_LAUNCH_CHECK("diag_block_kernel");
+  {
+    P->Dhalf.alloc(9 * static_cast<size_t>(N));
+    P->Dmhalf.alloc(9 * static_cast<size_t>(N));
+    DevBuf<double> ext(2 * static_cast<size_t>(N));
+    hipLaunchKernelGGL(block_sqrt_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, P->Q64.ptr, N, P->ld, P->Dhalf.ptr,
+                       P->Dmhalf.ptr, ext.ptr);
+    XM_LAUNCH_CHECK("block_sqrt_kernel");
+    std::vector<double> he(2 * static_cast<size_t>(N));
+    XM_HIP(hipMemcpyAsync(he.data(), ext.ptr, he.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    XM_HIP(hipStreamSynchronize(s));
+    P->dmin = he[0];
+    P->dmax = he[1];
+    for (int k = 0; k < N; ++k) {
+      P->dmin = std::min(P->dmin, he[2 * k]);
+      P->dmax = std::max(P->dmax, he[2 * k + 1]);
+    }
+  }
   if (copies & XM_KEEP_F32) {
     P->Q32.alloc(qn);
     hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(qn, kB)), dim3(kB), 0, s, P->Q64.ptr, static_cast<int64_t>(qn),

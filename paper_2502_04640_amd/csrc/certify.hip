@@ -6,15 +6,27 @@
 // block, Lambda_k = sym((Q Y^T)_k Y_k) / alpha_k (alpha_k = |Y_k|^2 / 3), made
 // traceless for k >= 1.  The dual objective b^T y is tr(Lambda_0).
 //
-// lambda_min(Z) is found by Lanczos on Z = Q - blkdiag(Lambda) restricted to
-// the orthogonal complement of the rows of Y (Z Y^T = 0 at a critical point,
-// so those r directions carry zero eigenvalues): the first r basis vectors
-// are an orthonormal basis of rows(Y), every new Lanczos vector is
+// PSD-ness of Z is decided on the congruent operator
+//   Zs = D^{-1/2} Z D^{-1/2},   D = blkdiag(Q_kk)   (3x3 SPD diagonal blocks of Q),
+// which by Sylvester's law of inertia has the same signature as Z but a much
+// narrower spectrum (block-Jacobi scaling), so Lanczos needs far fewer
+// products.  Its smallest eigenvalue ls with Ritz residual res bounds
+// v^T Z v >= (ls - res) * (d_min if ls - res >= 0, else d_max) for unit v
+// D-orthogonal to rows(Y), d_min/d_max the extreme eigenvalues of the Q_kk
+// (given that the Ritz value belongs to the smallest eigenvalue, which the
+// stop rule below guards); certified iff that bound is >= -tol * qbar.
+//
+// Lanczos runs on the orthogonal complement of D^{1/2} rows(Y) (Zs D^{1/2} Y^T
+// = D^{-1/2} Z Y^T = 0 at a critical point): the first r basis vectors are an
+// orthonormal basis of D^{1/2} rows(Y), every new Lanczos vector is
 // orthogonalised against all previous ones twice (classical Gram-Schmidt,
 // "twice is enough"), and alpha_j, beta_j stay on the device so that
 // iterations run without host synchronisation.  Every few iterations the host
 // takes the smallest eigenvalue of the tridiagonal T_j by Sturm bisection and
 // its eigenvector by inverse iteration; the Ritz residual is beta_j |y_j|.
+// Convergence needs a small residual at two consecutive checks with the
+// smallest Ritz value unchanged between them (a converged Ritz value above a
+// not yet resolved smaller eigenvalue moves when the latter appears).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -82,6 +94,36 @@ __global__ void zapply_kernel(int32_t N, const double* __restrict__ Lam, const d
   const int c = static_cast<int>(i % 3);
   const double* L = Lam + 9 * k + 3 * c;
   w[i] = Qx[i] - (L[0] * x[3 * k] + L[1] * x[3 * k + 1] + L[2] * x[3 * k + 2]);
+}
+
+// y_k = M_k x_k per frame (M: [N][3][3] row-major)
+__global__ void blockmul_kernel(int32_t N, const double* __restrict__ Mb, const double* __restrict__ x,
+                                double* __restrict__ y) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (i >= 3 * static_cast<int64_t>(N)) return;
+  const int64_t k = i / 3;
+  const int c = static_cast<int>(i % 3);
+  const double* m = Mb + 9 * k + 3 * c;
+  y[i] = m[0] * x[3 * k] + m[1] * x[3 * k + 1] + m[2] * x[3 * k + 2];
+}
+
+// w = Dm (Qy - blkdiag(Lambda) y)   (y = Dm x already formed)
+__global__ void zapply_scaled_kernel(int32_t N, const double* __restrict__ Lam, const double* __restrict__ Dm,
+                                     const double* __restrict__ y, const double* __restrict__ Qy,
+                                     double* __restrict__ w) {
+  const int k = blockIdx.x * kB + threadIdx.x;
+  if (k >= N) return;
+  double t[3];
+  for (int c = 0; c < 3; ++c) {
+    const double* L = Lam + 9 * static_cast<int64_t>(k) + 3 * c;
+    t[c] = Qy[3 * static_cast<int64_t>(k) + c] -
+           (L[0] * y[3 * static_cast<int64_t>(k)] + L[1] * y[3 * static_cast<int64_t>(k) + 1] +
+            L[2] * y[3 * static_cast<int64_t>(k) + 2]);
+  }
+  for (int c = 0; c < 3; ++c) {
+    const double* m = Dm + 9 * static_cast<int64_t>(k) + 3 * c;
+    w[3 * static_cast<int64_t>(k) + c] = m[0] * t[0] + m[1] * t[1] + m[2] * t[2];
+  }
 }
 
 // c[b] = <V[b], w> (one block per basis vector)
@@ -232,6 +274,7 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
   const int32_t N = p->N;
   const int64_t n = p->n3;
   const double qbar = p->qbar;
+  require(n > r, XM_EINVAL, "certificate: 3N must exceed the rank");
   if (max_iter <= 0) max_iter = 400;
   max_iter = std::min<int>(max_iter, static_cast<int>(std::min<int64_t>(n - r, 2000 - 8)));
   if (lanczos_tol <= 0) lanczos_tol = 1e-6;
@@ -255,9 +298,10 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
   out.primal = sums[1];
   out.dual = sums[2];
 
-  // basis: [deflation rows of Y | Lanczos vectors]
+  // basis: [deflation rows D^{1/2} Y | Lanczos vectors of Zs]
   const int cap = r + max_iter + 1;
-  DevBuf<double> V(static_cast<size_t>(cap) * n), w(n), Qx(n), c1(cap), c2(cap), alpha(max_iter), beta(max_iter);
+  DevBuf<double> V(static_cast<size_t>(cap) * n), w(n), Qx(n), yv(n), c1(cap), c2(cap), alpha(max_iter),
+      beta(max_iter);
   const unsigned gb = cdiv(n, kB);
   auto orthogonalize = [&](int nv) {  // w -= V[0..nv) (V^T w), twice
     if (nv == 0) return;
@@ -269,7 +313,8 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
   };
   int nb = 0;
   for (int a = 0; a < r; ++a) {
-    hipLaunchKernelGGL(column_kernel, dim3(gb), dim3(kB), 0, s, Yt, r, a, n, w.ptr);
+    hipLaunchKernelGGL(column_kernel, dim3(gb), dim3(kB), 0, s, Yt, r, a, n, yv.ptr);
+    hipLaunchKernelGGL(blockmul_kernel, dim3(gb), dim3(kB), 0, s, N, p->Dhalf.ptr, yv.ptr, w.ptr);
     orthogonalize(nb);
     hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w.ptr, n, c1.ptr, c2.ptr, 0,
                        static_cast<double*>(nullptr), beta.ptr, 0, V.ptr + static_cast<int64_t>(nb) * n);
@@ -277,7 +322,7 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
     double bn = 0.0;
     XM_HIP(hipMemcpyAsync(&bn, beta.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
     XM_HIP(hipStreamSynchronize(s));
-    if (bn > 1e-10 * std::sqrt(static_cast<double>(N))) ++nb;  // skip a dependent row
+    if (bn > 1e-10 * std::sqrt(static_cast<double>(N) * p->dmax)) ++nb;  // skip a dependent row
   }
   hipLaunchKernelGGL(random_kernel, dim3(gb), dim3(kB), 0, s, n, static_cast<uint64_t>(12345), w.ptr);
   orthogonalize(nb);
@@ -285,16 +330,23 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
                      static_cast<double*>(nullptr), static_cast<double*>(nullptr), 0,
                      V.ptr + static_cast<int64_t>(nb) * n);
   XM_LAUNCH_CHECK("normalize_kernel");
+  // tolerances in the units of Zs
+  const double tol_s = tol * qbar / p->dmax;
+  const double ltol_s = lanczos_tol * qbar / p->dmax;
 
   std::vector<double> ha, hbv, d, e, y;
-  double theta = 0.0, res = 0.0;
+  double theta = 0.0, res = 0.0, theta_prev = 0.0;
+  bool prev_small = false;
   int j = 0;
   bool done = false;
   for (j = 0; j < max_iter && !done; ++j) {
     const double* x = V.ptr + static_cast<int64_t>(nb + j) * n;
-    spmm_yt<double>(p, XM_F64, x, 1, Qx.ptr, s);
-    hipLaunchKernelGGL(zapply_kernel, dim3(gb), dim3(kB), 0, s, N, Lam.ptr, x, Qx.ptr, w.ptr);
-    XM_LAUNCH_CHECK("zapply_kernel");
+    hipLaunchKernelGGL(blockmul_kernel, dim3(gb), dim3(kB), 0, s, N, p->Dmhalf.ptr, x, yv.ptr);
+    XM_LAUNCH_CHECK("blockmul_kernel");
+    spmm_yt<double>(p, XM_F64, yv.ptr, 1, Qx.ptr, s);
+    hipLaunchKernelGGL(zapply_scaled_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, N, Lam.ptr, p->Dmhalf.ptr, yv.ptr,
+                       Qx.ptr, w.ptr);
+    XM_LAUNCH_CHECK("zapply_scaled_kernel");
     const int nv = nb + j + 1;
     orthogonalize(nv);
     hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w.ptr, n, c1.ptr, c2.ptr, nb + j, alpha.ptr,
@@ -312,16 +364,22 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
       theta = tridiag_min_eig(d, e, m);
       y = tridiag_min_vec(d, e, m, theta);
       res = std::fabs(hbv[m - 1] * y[m - 1]);
-      const bool breakdown = hbv[m - 1] <= 1e-14 * (std::fabs(theta) + qbar);
-      const bool converged = res <= lanczos_tol * qbar || res <= 1e-3 * std::fabs(theta);
-      const bool negative = theta + res < -tol * qbar;
+      const bool breakdown = hbv[m - 1] <= 1e-14 * (std::fabs(theta) + 1.0);
+      const bool small = res <= ltol_s || res <= 1e-3 * std::fabs(theta);
+      const bool stable = std::fabs(theta - theta_prev) <= 1e-6 * std::fabs(theta) + ltol_s;
+      const bool converged = small && prev_small && stable;
+      const bool negative = theta + res < -tol_s;
       if (breakdown || converged || negative) done = true;
+      prev_small = small;
+      theta_prev = theta;
     }
   }
   out.iters = j;
   out.lambda_min = theta;
   out.ritz_residual = res;
-  out.certified = (theta - res) >= -tol * qbar;
+  const double lo = theta - res;
+  out.lambda_bound = lo * (lo >= 0.0 ? p->dmin : p->dmax);
+  out.certified = out.lambda_bound >= -tol * qbar;
   if (v_out) {
     const int m = static_cast<int>(y.size());
     DevBuf<double> yd(m);
@@ -330,7 +388,9 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
     hipLaunchKernelGGL(multiaxpy_kernel, dim3(gb), dim3(kB), 0, s, V.ptr + static_cast<int64_t>(nb) * n, m, n,
                        yd.ptr, 1.0, w.ptr);
     XM_LAUNCH_CHECK("multiaxpy_kernel");
-    hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w.ptr, n, c1.ptr, c2.ptr, 0,
+    // Ritz vector of Zs -> direction in the coordinates of Z: v = D^{-1/2} vs (v^T Z v = vs^T Zs vs)
+    hipLaunchKernelGGL(blockmul_kernel, dim3(gb), dim3(kB), 0, s, N, p->Dmhalf.ptr, w.ptr, yv.ptr);
+    hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, yv.ptr, n, c1.ptr, c2.ptr, 0,
                        static_cast<double*>(nullptr), static_cast<double*>(nullptr), 0, v_out);
     XM_LAUNCH_CHECK("normalize_kernel");
     XM_HIP(hipStreamSynchronize(s));

@@ -36,6 +36,10 @@ struct xm_problem {
 
   // tr(Q_kk) / 3 per frame
   xm::DevBuf<double> qkk;
+  // Q_kk^{1/2} and Q_kk^{-1/2} per frame ([N][3][3]) and the extreme
+  // eigenvalues over all Q_kk (the block-Jacobi scaling of the certificate)
+  xm::DevBuf<double> Dhalf, Dmhalf;
+  double dmin = 1.0, dmax = 1.0;
 
   // split-row partial sums of the Y Q product (grown on demand)
   xm::DevBuf<char> spmm_scratch;
@@ -44,7 +48,10 @@ struct xm_problem {
   struct TimedLaunch {
     hipEvent_t start, stop;
     int dtype;
+    double bytes;  // algorithmic bytes of Q the launch reads
   };
+  // product kernel per Q precision (xm_spmm_kind, indexed by xm_dtype)
+  int spmm_kind[3] = {XM_SPMM_UPPER, XM_SPMM_UPPER, XM_SPMM_FULL};
   bool timing = false;
   std::vector<TimedLaunch> events;
   size_t events_used = 0;
@@ -71,7 +78,7 @@ void transpose_rows(const Ts* in, int rows, int cols, Td* out, hipStream_t s);
 
 // certify.hip: certificate at Yt (FP64, [3N][r]).
 struct CertResult {
-  double lambda_min = 0, ritz_residual = 0, primal = 0, dual = 0, stat_res = 0;
+  double lambda_min = 0, ritz_residual = 0, lambda_bound = 0, primal = 0, dual = 0, stat_res = 0;
   int iters = 0;
   bool certified = false;
 };

@@ -13,7 +13,13 @@
 // |r| <= |r0| min(|r0|^theta, kappa), kappa = 0.1, theta = 1; steps are
 // accepted when rho > 0.1; the radius is quartered when rho < 1/4 and doubled
 // (up to sqrt(3N)) when rho > 3/4 on a boundary step; initial radius
-// sqrt(3N)/8; rho carries the usual max(1,|f|) 1e3 eps regularisation.  The
+// sqrt(3N)/8; rho carries the usual max(1,|f|) 1e3 eps regularisation.
+// Stop when |grad| <= grad_tol qbar |Y|, or, at the precision floor of
+// reduced-precision products, after 6 rejected steps in a row with |grad|
+// within 30 grad_tol qbar |Y|.  A reduced-precision solve then checks the
+// gradient with FP64 products and, while it is above the tolerance, runs up to
+// three more trust-region passes whose gradient products are taken relative
+// to the current point (FP64 product at that point as reference, see Rebase).  The
 // cost decrease is evaluated as <Y+ - Y, Q (Y+ + Y)> from the two products
 // already computed, which stays accurate in FP32 where f(Y+) - f(Y) would
 // cancel.  The staircase escape follows Theorem "Descent Direction": block k of
@@ -46,15 +52,54 @@ struct Vecs {
   }
 };
 
+// Gradient products relative to a reference point (reduced precision only):
+// G(Y) = Gref + Q (Y - Yref) with Gref = Q Yref formed once from the FP64 Q.
+// The reduced-precision product then only carries the rounding error of the
+// small difference Y - Yref, not of Q Y itself, whose entries cancel heavily
+// near the optimum (Y is close to the null space of the dual matrix); this is
+// what lets an FP32 solve converge below the noise floor of its own products.
+template <typename T>
+struct Rebase {
+  const T* Yref = nullptr;
+  const T* Gref = nullptr;
+  T* tmp = nullptr;
+};
+
+template <typename T>
+__global__ void sub_kernel(int64_t n, const T* __restrict__ a, const T* __restrict__ b, T* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+
+template <typename T>
+__global__ void add_kernel(int64_t n, const T* __restrict__ a, T* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) out[i] += a[i];
+}
+
+template <typename T>
+void grad_product(xm_problem* p, xm_dtype qg, const T* Yt, int r, T* G, const Rebase<T>& rb, hipStream_t st) {
+  const int64_t n = p->n3 * static_cast<int64_t>(r);
+  if (!rb.Yref) {
+    spmm_yt<T>(p, qg, Yt, r, G, st);
+    return;
+  }
+  hipLaunchKernelGGL(sub_kernel<T>, dim3(cdiv(n, 256)), dim3(256), 0, st, n, Yt, rb.Yref, rb.tmp);
+  XM_LAUNCH_CHECK("sub_kernel");
+  spmm_yt<T>(p, qg, rb.tmp, r, G, st);
+  hipLaunchKernelGGL(add_kernel<T>, dim3(cdiv(n, 256)), dim3(256), 0, st, n, rb.Gref, G);
+  XM_LAUNCH_CHECK("add_kernel");
+}
+
 struct RtrOut {
   double f = 0, gnorm = 0, ynorm = 0;
   int outer = 0, inner = 0, spmm = 0;
-  bool converged = false;
+  bool converged = false, floor = false;
 };
 
 template <typename T>
 RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_solve_opts& o, double grad_tol,
-           hipStream_t st) {
+           const Rebase<T>& rb, hipStream_t st) {
   const int N = p->N;
   Manifold<T> mf(N);
   if (o.precondition) mf.qkk = p->qkk.ptr;
@@ -65,11 +110,16 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
   const int max_outer = (o.max_outer > 0) ? o.max_outer : 1000;
   const int max_inner = (o.max_inner > 0) ? o.max_inner : std::min(3 * N * r, 2000);
   const double kappa = 0.1, theta = 1.0, rho_prime = 0.1;
+  // precision floor: in reduced precision the gradient cannot fall below the
+  // rounding noise of the products, and there every model step is rejected
+  const int floor_rejections = 6;
+  const double floor_tol = 30.0 * grad_tol;
+  int rejections = 0;
   RtrOut out;
   double sums[5];
 
   mf.scale(r, V.Rt.ptr, V.s.ptr, V.Yt.ptr, st);
-  spmm_yt<T>(p, qg, V.Yt.ptr, r, V.G.ptr, st);
+  grad_product<T>(p, qg, V.Yt.ptr, r, V.G.ptr, rb, st);
   ++out.spmm;
   mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
   read_partials(V.part.ptr, nb, 5, sums, st);
@@ -126,7 +176,7 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
     out.inner += std::min(j, max_inner);
     // ---- candidate and ratio test ----
     mf.retract(r, V.Rt.ptr, V.s.ptr, V.etaR.ptr, V.etas.ptr, V.Rt2.ptr, V.s2.ptr, V.Yt2.ptr, st);
-    spmm_yt<T>(p, qg, V.Yt2.ptr, r, V.G2.ptr, st);
+    grad_product<T>(p, qg, V.Yt2.ptr, r, V.G2.ptr, rb, st);
     ++out.spmm;
     mf.model(r, V.s.ptr, V.gR.ptr, V.gs.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr, V.Yt.ptr, V.G.ptr,
              V.Yt2.ptr, V.G2.ptr, V.part.ptr, st);
@@ -144,7 +194,13 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
     if (o.verbose)
       std::fprintf(stderr, "[xm] r=%d it=%d f=%.12e |g|=%.3e Delta=%.3e rho=%.3f inner=%d %s%s\n", r, k, f, gnorm,
                    Delta, rho, std::min(j, max_inner), boundary ? "boundary" : "interior", accept ? "" : " rejected");
+    if (!accept && ++rejections >= floor_rejections && gnorm <= floor_tol * qbar * ynorm) {
+      out.converged = out.floor = true;
+      ++k;
+      break;
+    }
     if (accept) {
+      rejections = 0;
       std::swap(V.Rt.ptr, V.Rt2.ptr);
       std::swap(V.s.ptr, V.s2.ptr);
       std::swap(V.Yt.ptr, V.Yt2.ptr);
@@ -167,12 +223,14 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
   return out;
 }
 
-// cost and gradient norm of the current point in FP64 (for reduced-precision solves)
+// cost, gradient norm and |Y|_F of the current point from FP64 products (for
+// reduced-precision solves); optionally the FP64 product Q Y, rounded to T
 struct Check {
-  double f, gnorm;
+  double f, gnorm, ynorm;
 };
 
-Check fp64_check(xm_problem* p, const double* Yt64, int r, hipStream_t st) {
+template <typename T>
+Check fp64_check(xm_problem* p, const double* Yt64, int r, hipStream_t st, T* G_out = nullptr) {
   const int N = p->N;
   Vecs<double> V(N, r);
   Manifold<double> mf(N);
@@ -181,7 +239,8 @@ Check fp64_check(xm_problem* p, const double* Yt64, int r, hipStream_t st) {
   mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
   double sums[5];
   read_partials(V.part.ptr, static_cast<int>(mf.blocks()), 5, sums, st);
-  return {sums[0], std::sqrt(sums[1])};
+  if (G_out) transpose_rows<double, T>(V.G.ptr, 1, static_cast<int>(p->n3 * r), G_out, st);
+  return {sums[0], std::sqrt(sums[1]), std::sqrt(sums[2])};
 }
 
 template <typename T>
@@ -192,12 +251,20 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   const bool f64 = std::is_same<T, double>::value;
   const xm_dtype qg = f64 ? XM_F64 : XM_F32;
   const xm_dtype qh = f64 ? XM_F64 : (o.compute == XM_BF16 ? XM_BF16 : XM_F32);
-  const double grad_tol = (o.grad_tol > 0) ? o.grad_tol : (f64 ? 1e-9 : 1e-6);
+  const double grad_tol = (o.grad_tol > 0) ? o.grad_tol : (f64 ? 1e-9 : 1e-7);
   const double cert_tol = (o.cert_tol > 0) ? o.cert_tol : (f64 ? 1e-7 : 1e-5);
   const int rmax = o.r_max;
   Vecs<T> V(N, rmax + 1);
   Manifold<T> mf(N);
   DevBuf<double> Yt64(static_cast<size_t>(n3) * (rmax + 1)), vmin(n3);
+  // reduced precision: reference point and FP64 product for the refinement passes
+  DevBuf<T> Yref, Gref, Rtmp;
+  if (!f64) {
+    Yref.alloc(static_cast<size_t>(n3) * rmax);
+    Gref.alloc(static_cast<size_t>(n3) * rmax);
+    Rtmp.alloc(static_cast<size_t>(n3) * rmax);
+  }
+  const int max_refine = 3;
 
   int r;
   if (Y0) {
@@ -215,7 +282,29 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   CertResult cr;
   while (true) {
     auto t0 = std::chrono::steady_clock::now();
-    ro = rtr<T>(p, V, r, qg, qh, o, grad_tol, st);
+    ro = rtr<T>(p, V, r, qg, qh, o, grad_tol, Rebase<T>{}, st);
+    // Reduced precision: check the gradient with FP64 products; while it is
+    // above the tolerance, continue from the current point with gradient
+    // products taken relative to it (Rebase), the FP64 product as reference.
+    for (int pass = 0; !f64 && pass < max_refine; ++pass) {
+      transpose_rows<T, double>(V.Yt.ptr, 1, static_cast<int>(n3 * r), Yt64.ptr, st);
+      const Check ck = fp64_check<T>(p, Yt64.ptr, r, st, Gref.ptr);
+      ++info->spmm_count;
+      if (o.verbose)
+        std::fprintf(stderr, "[xm] rank %d: FP64 check |g|=%.3e (tol %.3e)%s\n", r, ck.gnorm,
+                     grad_tol * p->qbar * ck.ynorm, ck.gnorm <= grad_tol * p->qbar * ck.ynorm ? "" : ", refining");
+      if (ck.gnorm <= grad_tol * p->qbar * ck.ynorm) break;
+      XM_HIP(hipMemcpyAsync(Yref.ptr, V.Yt.ptr, n3 * r * sizeof(T), hipMemcpyDeviceToDevice, st));
+      const RtrOut r2 = rtr<T>(p, V, r, qg, qh, o, grad_tol, Rebase<T>{Yref.ptr, Gref.ptr, Rtmp.ptr}, st);
+      ro.outer += r2.outer;
+      ro.inner += r2.inner;
+      ro.spmm += r2.spmm;
+      ro.f = r2.f;
+      ro.gnorm = r2.gnorm;
+      ro.ynorm = r2.ynorm;
+      ro.converged = r2.converged;
+      ro.floor = r2.floor;
+    }
     XM_HIP(hipStreamSynchronize(st));
     auto t1 = std::chrono::steady_clock::now();
     solve_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -230,7 +319,7 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
     cert_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
     info->lanczos_iters += cr.iters;
     if (o.verbose)
-      std::fprintf(stderr, "[xm] rank %d: f=%.12e |g|=%.3e lambda_min=%.6e (res %.2e, %d it) %s\n", r, ro.f,
+      std::fprintf(stderr, "[xm] rank %d: f=%.12e |g|=%.3e lambda_s=%.6e (res %.2e, %d it) %s\n", r, ro.f,
                    ro.gnorm, cr.lambda_min, cr.ritz_residual, cr.iters, cr.certified ? "certified" : "not certified");
     if (cr.certified || r >= rmax) break;
     // escape to rank r + 1 with step halving
@@ -258,16 +347,16 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   // final FP64 quantities
   if (f64) XM_HIP(hipMemcpyAsync(Yt64.ptr, V.Yt.ptr, n3 * r * sizeof(double), hipMemcpyDeviceToDevice, st));
   else transpose_rows<T, double>(V.Yt.ptr, 1, static_cast<int>(n3 * r), Yt64.ptr, st);
-  const Check ck = fp64_check(p, Yt64.ptr, r, st);
+  const Check ck = fp64_check<T>(p, Yt64.ptr, r, st);
   XM_HIP(hipMemsetAsync(Y_out, 0, static_cast<size_t>(rmax) * n3 * sizeof(double), st));
   transpose_rows<double, double>(Yt64.ptr, static_cast<int>(n3), r, Y_out, st);
   XM_HIP(hipStreamSynchronize(st));
   info->r = r;
   info->certified = cr.certified ? 1 : 0;
-  info->converged = ro.converged ? 1 : 0;
+  info->converged = ro.converged ? (ro.floor ? 2 : 1) : 0;
   info->cost = ck.f;
   info->grad_norm = ck.gnorm;
-  info->lambda_min = cr.lambda_min;
+  info->lambda_min = cr.lambda_bound;
   info->primal = cr.primal;
   info->dual = cr.dual;
   info->solve_ms = solve_ms;

@@ -20,7 +20,7 @@ namespace {
 //   kMaxRows       rows of a slab (bounds the LDS staging of Yt),
 //   kUnroll        rows in flight per thread.
 #ifndef XM_SPMM_TARGET
-#define XM_SPMM_TARGET 2048
+#define XM_SPMM_TARGET 1024
 #endif
 #ifndef XM_SPMM_MAXROWS
 #define XM_SPMM_MAXROWS 512
@@ -112,6 +112,187 @@ __global__ __launch_bounds__(kB) void spmm_split_kernel(const TQ* __restrict__ Q
   }
 }
 
+// Upper-triangle tile product.  Grid (chunk c of kB*V columns, slab s of RS
+// rows).  colpart[s][j][a] = sum_{i in slab, i <= j} Q[i][j] Yt[i][a];
+// rowpart[c][i][a] = sum_{j in chunk, j > i} Q[i][j] Yt[j][a].
+//
+// Rows are taken in batches of 8.  Lane l holds row b ^ pi(l) of the batch in
+// register slot b, pi(l) = (l >> 3) & 7: the butterfly partner of a lane at the
+// step with mask 32 (16, 8) then holds, in the slot the lane keeps, the row the
+// lane sends, so the three halving steps need no selects.  Within a batch a
+// wave still reads 8 whole row segments, each in 128-byte pieces.
+#ifndef XM_SYM_ROWS
+#define XM_SYM_ROWS 256
+#endif
+#ifndef XM_SYM_PERM
+#define XM_SYM_PERM 1
+#endif
+constexpr int kSymRows = XM_SYM_ROWS;  // RS
+constexpr bool kSymPerm = XM_SYM_PERM;  // lane-permuted slots (else selects in the butterfly)
+constexpr int kSymBatch = 8;           // rows per butterfly batch (fixed by the 3 halving steps)
+
+// Without the lane permutation the row of every slot is the same for the whole
+// wave, so the Yt values of the batch can come from uniform (scalar) loads.
+#ifndef XM_SYM_SCALAR_Y
+#define XM_SYM_SCALAR_Y 0
+#endif
+constexpr bool kSymScalarY = XM_SYM_SCALAR_Y && !XM_SYM_PERM;
+
+template <bool kMask, typename TQ, typename TA, typename TV, int R>
+__device__ __forceinline__ void sym_batch(const TQ* __restrict__ q, int32_t ld, int i_base, int nb, int pi, int jcol,
+                                          const TA* __restrict__ ys, const TV* __restrict__ Yt, int32_t n3,
+                                          const TA (&xc)[QVec<TQ>::V][R], TA (&acc)[QVec<TQ>::V][R],
+                                          TA (&p)[kSymBatch][R]) {
+  constexpr int V = QVec<TQ>::V;
+  TA qv[kSymBatch][V];
+#pragma unroll
+  for (int b = 0; b < kSymBatch; ++b) {
+    const int row = b ^ pi;
+    if (row < nb) {
+      QVec<TQ>::load(q + static_cast<int64_t>(row) * ld, qv[b]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) qv[b][v] = TA(0);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < kSymBatch; ++b) {
+    const int row = b ^ pi;
+    const int i = i_base + row;  // global row
+#pragma unroll
+    for (int a = 0; a < R; ++a) p[b][a] = TA(0);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      TA qc = qv[b][v], qr = qv[b][v];
+      if (kMask) {
+        qc = (jcol + v >= i) ? qc : TA(0);
+        qr = (jcol + v > i) ? qr : TA(0);
+      }
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        const TA y = kSymScalarY ? static_cast<TA>(Yt[static_cast<int64_t>(min(i, n3 - 1)) * R + a]) : ys[row * R + a];
+        acc[v][a] += qc * y;
+        p[b][a] += qr * xc[v][a];
+      }
+    }
+  }
+}
+
+#ifndef XM_SYM_WAVES
+#define XM_SYM_WAVES 0
+#endif
+#if XM_SYM_WAVES > 0
+#define XM_SYM_ATTR __attribute__((amdgpu_waves_per_eu(XM_SYM_WAVES)))
+#else
+#define XM_SYM_ATTR
+#endif
+template <typename TQ, typename TV, typename TA, int R>
+__global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __restrict__ Q, int32_t ld, int32_t n3,
+                                                      const TV* __restrict__ Yt, TA* __restrict__ colpart,
+                                                      TA* __restrict__ rowpart) {
+  constexpr int V = QVec<TQ>::V;
+  constexpr int C = kB * V;
+  constexpr int RS = kSymRows;
+  const int c = blockIdx.x, sl = blockIdx.y;
+  const int j0 = c * C;
+  const int i0 = sl * RS;
+  const int i1 = min(n3, i0 + RS);
+  if (j0 + C - 1 < i0) return;  // wholly below the diagonal (uniform per workgroup)
+  const int nrows = i1 - i0;
+  __shared__ TA ys[RS * R];
+  __shared__ TA rp[kB / 64][RS * R];
+  // rows past the end of Q stay zero: a ragged last batch multiplies them by zero
+  for (int e = threadIdx.x; e < RS * R; e += kB)
+    ys[e] = (e < nrows * R) ? static_cast<TA>(Yt[static_cast<int64_t>(i0) * R + e]) : TA(0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int pi = kSymPerm ? (lane >> 3) & 7 : 0;
+  const int j = j0 + threadIdx.x * V;
+  TA xc[V][R];
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+#pragma unroll
+    for (int a = 0; a < R; ++a) xc[v][a] = (j + v < n3) ? static_cast<TA>(Yt[static_cast<int64_t>(j + v) * R + a]) : TA(0);
+  __syncthreads();
+  TA acc[V][R];
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+#pragma unroll
+    for (int a = 0; a < R; ++a) acc[v][a] = TA(0);
+  const bool crossing = j0 < i1;
+  const bool active = j < ld;  // lanes past the padded width read nothing
+  const TQ* qbase = Q + static_cast<int64_t>(i0) * ld + (active ? j : 0);
+  for (int ib = 0; ib < nrows; ib += kSymBatch) {
+    const int nb = active ? min(kSymBatch, nrows - ib) : 0;
+    TA p[kSymBatch][R];
+    if (crossing)
+      sym_batch<true, TQ, TA, TV, R>(qbase + static_cast<int64_t>(ib) * ld, ld, i0 + ib, nb, pi, j, ys + ib * R, Yt,
+                                     n3, xc, acc, p);
+    else
+      sym_batch<false, TQ, TA, TV, R>(qbase + static_cast<int64_t>(ib) * ld, ld, i0 + ib, nb, pi, j, ys + ib * R, Yt,
+                                      n3, xc, acc, p);
+    // three halving steps (masks 32, 16, 8) leave row pi, summed over the 8
+    // lanes that share the low 3 lane bits; masks 4, 2, 1 finish the wave sum
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+      TA t4[4], t2[2];
+      TA t1;
+      if (kSymPerm) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t4[k] = p[k][a] + __shfl_xor(p[k + 4][a], 32);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) t2[k] = t4[k] + __shfl_xor(t4[k + 2], 16);
+        t1 = t2[0] + __shfl_xor(t2[1], 8);
+      } else {
+        const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          t4[k] = (h32 ? p[k + 4][a] : p[k][a]) + __shfl_xor(h32 ? p[k][a] : p[k + 4][a], 32);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) t2[k] = (h16 ? t4[k + 2] : t4[k]) + __shfl_xor(h16 ? t4[k] : t4[k + 2], 16);
+        t1 = (h8 ? t2[1] : t2[0]) + __shfl_xor(h8 ? t2[0] : t2[1], 8);
+      }
+      t1 += __shfl_xor(t1, 4);
+      t1 += __shfl_xor(t1, 2);
+      t1 += __shfl_xor(t1, 1);
+      if ((lane & 7) == 0) {
+        const int row = ib + ((lane >> 3) & 7);
+        if (row < nrows) rp[wave][row * R + a] = t1;
+      }
+    }
+  }
+  TA* cp = colpart + static_cast<int64_t>(sl) * n3 * R;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    if (j + v < n3) {
+#pragma unroll
+      for (int a = 0; a < R; ++a) cp[static_cast<int64_t>(j + v) * R + a] = acc[v][a];
+    }
+  }
+  __syncthreads();
+  TA* rpo = rowpart + static_cast<int64_t>(c) * n3 * R + static_cast<int64_t>(i0) * R;
+  for (int e = threadIdx.x; e < nrows * R; e += kB) {
+    TA sum = rp[0][e];
+#pragma unroll
+    for (int w = 1; w < kB / 64; ++w) sum += rp[w][e];
+    rpo[e] = sum;
+  }
+}
+
+// out[j][a] = sum_{s <= j / RS} colpart[s][j][a] + sum_{c >= j / C} rowpart[c][j][a]
+template <typename TA, typename TV, int R, int C>
+__global__ void spmm_sym_reduce_kernel(const TA* __restrict__ colpart, const TA* __restrict__ rowpart, int32_t n3,
+                                       int32_t nchunks, TV* __restrict__ out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  const int64_t m = static_cast<int64_t>(n3) * R;
+  if (e >= m) return;
+  const int jrow = static_cast<int>(e / R);
+  TA s = TA(0);
+  const int smax = jrow / kSymRows;
+  for (int k = 0; k <= smax; ++k) s += colpart[static_cast<int64_t>(k) * m + e];
+  for (int k = jrow / C; k < nchunks; ++k) s += rowpart[static_cast<int64_t>(k) * m + e];
+  out[e] = static_cast<TV>(s);
+}
+
 template <typename TA, typename TV>
 __global__ void spmm_reduce_kernel(const TA* __restrict__ part, int32_t splits, int64_t m, TV* __restrict__ out) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
@@ -169,6 +350,7 @@ void launch(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStream_t
     }
     ev = &mp->events[mp->events_used++];
     ev->dtype = QVec<TQ>::dtype;
+    ev->bytes = static_cast<double>(p->n3) * p->n3 * sizeof(TQ);
     XM_HIP(hipEventRecord(ev->start, s));
   }
   hipLaunchKernelGGL((spmm_split_kernel<TQ, TV, TA, R>), dim3(sp.col_blocks, sp.splits), dim3(kB), 0, s, Q,
@@ -180,8 +362,59 @@ void launch(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStream_t
   XM_LAUNCH_CHECK("spmm_reduce_kernel");
 }
 
+template <typename TQ, typename TV, typename TA, int R>
+void launch_sym(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStream_t s) {
+  constexpr int V = QVec<TQ>::V;
+  constexpr int C = kB * V;
+  const int nchunks = static_cast<int>(cdiv(p->ld, C));
+  const int nslabs = static_cast<int>(cdiv(p->n3, kSymRows));
+  auto& scratch = const_cast<xm_problem*>(p)->spmm_scratch;
+  const size_t per = static_cast<size_t>(p->n3) * R;
+  const size_t need = (static_cast<size_t>(nslabs) + nchunks) * per * sizeof(TA);
+  if (scratch.n < need) {
+    XM_HIP(hipStreamSynchronize(s));
+    scratch.alloc(need);
+  }
+  TA* colpart = reinterpret_cast<TA*>(scratch.ptr);
+  TA* rowpart = colpart + static_cast<size_t>(nslabs) * per;
+  xm_problem::TimedLaunch* ev = nullptr;
+  if (p->timing) {
+    auto* mp = const_cast<xm_problem*>(p);
+    if (mp->events_used == mp->events.size()) {
+      xm_problem::TimedLaunch t{};
+      XM_HIP(hipEventCreate(&t.start));
+      XM_HIP(hipEventCreate(&t.stop));
+      mp->events.push_back(t);
+    }
+    ev = &mp->events[mp->events_used++];
+    ev->dtype = QVec<TQ>::dtype;
+    ev->bytes = 0.5 * static_cast<double>(p->n3) * (p->n3 + 1) * sizeof(TQ);
+    XM_HIP(hipEventRecord(ev->start, s));
+  }
+  hipLaunchKernelGGL((spmm_sym_kernel<TQ, TV, TA, R>), dim3(nchunks, nslabs), dim3(kB), 0, s, Q, p->ld, p->n3, Yt,
+                     colpart, rowpart);
+  XM_LAUNCH_CHECK("spmm_sym_kernel");
+  if (ev) XM_HIP(hipEventRecord(ev->stop, s));
+  hipLaunchKernelGGL((spmm_sym_reduce_kernel<TA, TV, R, C>), dim3(cdiv(per, kB)), dim3(kB), 0, s, colpart, rowpart,
+                     p->n3, nchunks, out);
+  XM_LAUNCH_CHECK("spmm_sym_reduce_kernel");
+}
+
 template <typename TQ, typename TV, typename TA>
 void dispatch_r(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, hipStream_t s) {
+  if (p->spmm_kind[QVec<TQ>::dtype] == XM_SPMM_UPPER) {
+    switch (r) {
+      case 1: launch_sym<TQ, TV, TA, 1>(p, Q, Yt, out, s); return;
+      case 2: launch_sym<TQ, TV, TA, 2>(p, Q, Yt, out, s); return;
+      case 3: launch_sym<TQ, TV, TA, 3>(p, Q, Yt, out, s); return;
+      case 4: launch_sym<TQ, TV, TA, 4>(p, Q, Yt, out, s); return;
+      case 5: launch_sym<TQ, TV, TA, 5>(p, Q, Yt, out, s); return;
+      case 6: launch_sym<TQ, TV, TA, 6>(p, Q, Yt, out, s); return;
+      case 7: launch_sym<TQ, TV, TA, 7>(p, Q, Yt, out, s); return;
+      case 8: launch_sym<TQ, TV, TA, 8>(p, Q, Yt, out, s); return;
+      default: throw Error(XM_EINVAL, "rank must be in [1, 8]");
+    }
+  }
   switch (r) {
     case 1: launch<TQ, TV, TA, 1>(p, Q, Yt, out, s); break;
     case 2: launch<TQ, TV, TA, 2>(p, Q, Yt, out, s); break;

@@ -146,6 +146,34 @@ def test_spmm_parity(r):
     assert np.abs(out16 - ref).max() <= 1e-2 * scale
 
 
+@pytest.fixture(scope="module")
+def tiled_problem():
+    # 3N = 2100: five 512-row slabs (the last one 52 rows), three FP32 column
+    # chunks of 1024 and five FP64 chunks of 512, each with a ragged tail
+    sc = scenes.random_scene(700, 12000, L=4, sigma=0.02, seed=17)
+    return sc, _oracle_Q(sc)
+
+
+@pytest.mark.parametrize("kind", ["upper", "full"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_spmm_kernels_across_tiles(tiled_problem, kind, dtype):
+    _say(f"case: spmm {kind} {dtype} 3N=2100")
+    sc, Qo = tiled_problem
+    P = _build(sc, keep=("f32", "bf16"))
+    P.set_spmm_kind(dtype, kind)
+    tol = {"f64": 1e-13, "f32": 3e-6, "bf16": 1e-2}[dtype]
+    for r in (1, 2, 5, 8):
+        rng = np.random.default_rng(100 + r)
+        Y = rng.standard_normal((r, 3 * sc.N))
+        ref = Y @ Qo
+        out = P.spmm(torch.from_numpy(Y).cuda(), dtype).cpu().numpy()
+        scale = np.abs(Y).max() * np.abs(Qo).sum(0).max()
+        assert np.abs(out - ref).max() <= tol * scale, (r, np.abs(out - ref).max() / scale)
+        # deterministic: a second product is bitwise identical
+        out2 = P.spmm(torch.from_numpy(Y).cuda(), dtype).cpu().numpy()
+        assert np.array_equal(out, out2)
+
+
 def _oracle_solution(sc, Q):
     R, s, info = ost.staircase(Q, grad_tol=1e-11, tau=1e-7)
     Rh, sh = ord_.round_solution(omf.to_U(R, s))
@@ -197,7 +225,9 @@ def test_certificate_matches_dense_eigenvalue():
     c = P.certify(torch.from_numpy(U).cuda(), tol=1e-7, max_iter=300)
     qbar = c["qbar"]
     assert c["certified"] == 1
-    assert abs(c["lambda_min"] - c_o["lambda_min"]) <= 1e-6 * qbar
+    # the Lanczos runs on the block-Jacobi scaled dual D^{-1/2} Z D^{-1/2}
+    assert abs(c["lambda_min"] - c_o["lambda_min_scaled"]) <= 1e-6 * max(1.0, abs(c_o["lambda_min_scaled"]))
+    assert abs(c["lambda_bound"] - c_o["lambda_bound"]) <= 1e-6 * c_o["dmax"]
     # primal and dual are small differences of O(qbar |Y|^2) terms: FP64 noise ~1e-16 * 3N * qbar
     assert _gap(c["primal"], c_o["primal"]) <= 1e-9
     assert _gap(c["dual"], c_o["dual"]) <= 1e-9
@@ -269,11 +299,48 @@ def test_medium_config_q_and_solve(cfg):
         assert _gap(info["cost"], oinfo["cost"]) <= gap_tol
 
 
+@pytest.mark.parametrize("cfg", ["unordered", "sequential"])
+def test_unordered_and_sequential_configs(cfg):
+    # the 1000-frame unordered and 2000-frame loop scenes: sampled rows of Q
+    # against the oracle; FP64, FP32 and BF16-stored-Q solves all certified;
+    # FP32 / BF16 rotations against the FP64 solve (itself pinned to the oracle
+    # on the smaller scenes) within the FP32 bars
+    _say(f"case: {cfg} config (sampled Q rows, FP64 / FP32 / BF16 certified solves)")
+    xm = _xm()
+    sc = scenes.make_scene(cfg, 0)
+    P = _build(sc, keep=("f32", "bf16"))
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(3 * sc.N, size=16, replace=False))
+    Qo = odm.q_rows(sc.N, sc.M, sc.frame, sc.landmark, sc.u, sc.w, rows)
+    Qg = np.stack([P.Q_rows(int(r), 1).cpu().numpy()[0] for r in rows])
+    assert np.abs(Qg - Qo).max() <= 1e-10 * np.abs(Qo).max()
+    Y64, i64 = P.solve(xm.SolveOptions(compute="f64"))
+    R64, s64, rho64 = P.round(Y64)
+    eta = (rho64 - i64["cost"]) / (1 + abs(rho64) + abs(i64["cost"]))
+    _say(f"  f64: r={i64['r']} cert={i64['certified']} outer={i64['outer_iters']} inner={i64['inner_iters']} "
+         f"lanczos={i64['lanczos_iters']} eta={eta:.2e}")
+    assert i64["certified"] == 1
+    assert eta <= 1e-8  # tight: the rounded solution attains the SDP cost
+    for compute in ("f32", "bf16"):
+        Y, info = P.solve(xm.SolveOptions(compute=compute))
+        R, s, rho = P.round(Y)
+        err = _rot_err(R.cpu().numpy(), R64.cpu().numpy())
+        _say(f"  {compute}: r={info['r']} cert={info['certified']} conv={info['converged']} "
+             f"outer={info['outer_iters']} inner={info['inner_iters']} rot_err={err:.2e} "
+             f"gap={_gap(info['cost'], i64['cost']):.2e}")
+        assert info["certified"] == 1
+        assert err <= 1e-4
+        assert np.abs(s.cpu().numpy() / s64.cpu().numpy() - 1).max() <= 1e-4
+        assert _gap(info["cost"], i64["cost"]) <= 1e-5
+
+
 def test_large_workload_sampled_rows_and_certified_solves():
-    # the benchmark's workload and launch configuration (N=10155, ~8M obs):
-    # sampled rows of Q against the oracle, then the FP32 and FP64 solves are
-    # both certified and agree (rotations within 1e-4 rad, cost gap 1e-5)
-    _say("case: large workload N=10155 (sampled Q rows, FP32 and FP64 solves)")
+    # the benchmark's workload and launch configuration (N=10155, ~8M obs, 5%
+    # outliers): sampled rows of Q against the oracle; the FP32 and FP64 solves
+    # are both certified and reach the same SDP cost.  With outliers the
+    # relaxation is not tight here (optimal rank 4), so rounded rotations are
+    # compared on the outlier-free twin below instead.
+    _say("case: large workload N=10155 (sampled Q rows, FP32 and FP64 certified solves)")
     xm = _xm()
     sc = scenes.make_scene("large", 0)
     P = _build(sc, keep=("f32",))
@@ -290,8 +357,24 @@ def test_large_workload_sampled_rows_and_certified_solves():
     _say(f"  f64: r={i64['r']} cert={i64['certified']} outer={i64['outer_iters']} inner={i64['inner_iters']} "
          f"solve_ms={i64['solve_ms']:.0f} cert_ms={i64['cert_ms']:.0f}")
     assert i32["certified"] == 1 and i64["certified"] == 1
-    R32, s32, rho32 = P.round(Y32)
-    R64, s64, rho64 = P.round(Y64)
-    assert _rot_err(R32.cpu().numpy(), R64.cpu().numpy()) <= 1e-4
     assert _gap(i32["cost"], i64["cost"]) <= 1e-5
     assert _gap(i64["primal"], i64["dual"]) <= 1e-6
+
+
+def test_large_tight_twin_rotations_fp32_vs_fp64():
+    # the same generator without outliers (tight: rank-3 optimum): the FP32 and
+    # FP64 certified solutions round to the same rotations (1e-4 rad) and scales
+    _say("case: large outlier-free twin N=10155, FP32 vs FP64 rotations")
+    xm = _xm()
+    sc = scenes.make_scene("large", 0, outlier=0.0)
+    P = _build(sc, keep=("f32",))
+    Y32, i32 = P.solve(xm.SolveOptions(compute="f32"))
+    Y64, i64 = P.solve(xm.SolveOptions(compute="f64"))
+    assert i32["certified"] == 1 and i64["certified"] == 1
+    R32, s32, rho32 = P.round(Y32)
+    R64, s64, rho64 = P.round(Y64)
+    _say(f"  rho32={rho32:.10e} rho64={rho64:.10e} cost64={i64['cost']:.10e}")
+    assert _gap(rho64, i64["cost"]) <= 1e-8          # tight: rounding loses nothing
+    assert _rot_err(R32.cpu().numpy(), R64.cpu().numpy()) <= 1e-4
+    assert np.abs(s32.cpu().numpy() / s64.cpu().numpy() - 1).max() <= 1e-4
+    assert _gap(rho32, rho64) <= 1e-5
