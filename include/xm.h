@@ -117,6 +117,23 @@ typedef struct {
 xm_status xm_get_info(const xm_problem* p, xm_problem_info* info);
 
 /*
+ * Device time of the main kernels of the handle's xm_build_Q (HIP events on
+ * the build stream around every launch): the Laplacian inversion's trailing
+ * update and the two sparse-dense products of the translation elimination.
+ * `bytes` and `flops` are algorithmic totals over all launches (unique HBM
+ * bytes the kernel must move; FP64 flops).  Up to `cap` entries are written to
+ * `out` (host); *count receives the number available.
+ */
+typedef struct {
+  char name[40];
+  int32_t launches;
+  double total_ms;
+  double bytes;
+  double flops;
+} xm_kernel_stat;
+xm_status xm_build_stats(const xm_problem* p, xm_kernel_stat* out, int32_t cap, int32_t* count);
+
+/*
  * Copy rows [row0, row0 + nrows) of the FP64 Q into `out` (device, row-major
  * [nrows][3N]).  For checks against a reference.  Synchronises `stream`.
  */
@@ -159,7 +176,7 @@ typedef struct {
                           manifold arithmetic; XM_BF16: BF16-stored Q for the
                           Hessian products, FP32 Q for gradient and cost */
   double grad_tol;     /* stop when ||grad|| <= grad_tol * qbar * ||Y||_F
-                          (<= 0: 1e-9 for XM_F64, 1e-7 otherwise); also stop,
+                          (<= 0: 1e-9 for XM_F64, 3e-7 otherwise); also stop,
                           counted as converged at the arithmetic's floor, after
                           6 consecutive rejected trust-region steps while
                           ||grad|| <= 30 grad_tol * qbar * ||Y||_F */

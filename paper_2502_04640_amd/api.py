@@ -52,6 +52,11 @@ class _SolveInfo(ctypes.Structure):
                 ("dual", ctypes.c_double), ("solve_ms", ctypes.c_double), ("cert_ms", ctypes.c_double)]
 
 
+class _KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
 class _Cert(ctypes.Structure):
     _fields_ = [("lambda_min", ctypes.c_double), ("ritz_residual", ctypes.c_double),
                 ("lambda_bound", ctypes.c_double), ("primal", ctypes.c_double),
@@ -107,6 +112,8 @@ def load_library() -> ctypes.CDLL:
     lib.xm_recover_tp.restype = ctypes.c_int
     lib.xm_adjoint.argtypes = [P, V, V, V, V, D, V, V, ctypes.c_int, D, I32, ctypes.POINTER(_AdjInfo), V]
     lib.xm_adjoint.restype = ctypes.c_int
+    lib.xm_build_stats.argtypes = [P, ctypes.POINTER(_KernelStat), I32, ctypes.POINTER(ctypes.c_int32)]
+    lib.xm_build_stats.restype = ctypes.c_int
     lib.xm_set_spmm_kind.argtypes = [P, ctypes.c_int, ctypes.c_int]
     lib.xm_set_spmm_kind.restype = ctypes.c_int
     lib.xm_spmm_timing.argtypes = [P, I32]
@@ -202,6 +209,14 @@ class Problem:
         out = torch.empty_like(Y)
         _check(load_library().xm_spmm(self._h, _DT[dtype], _ptr(Y), Y.shape[0], _ptr(out), _stream()))
         return out
+
+    def build_stats(self) -> dict:
+        """Device time and algorithmic bytes / flops of the main assembly kernels."""
+        arr = (_KernelStat * 8)()
+        n = ctypes.c_int32(0)
+        _check(load_library().xm_build_stats(self._h, arr, 8, ctypes.byref(n)))
+        return {arr[k].name.decode(): {"launches": arr[k].launches, "total_ms": arr[k].total_ms,
+                                       "bytes": arr[k].bytes, "flops": arr[k].flops} for k in range(min(n.value, 8))}
 
     def set_spmm_kind(self, dtype: str, kind: str):
         """Product kernel for the stored Q of `dtype`: "upper" (reads the upper

@@ -1,4 +1,5 @@
 // C ABI of libxm (declared and documented in include/xm.h).
+#include <cstdio>
 #include <string>
 
 #include "problem.h"
@@ -63,6 +64,23 @@ xm_status xm_get_info(const xm_problem* p, xm_problem_info* info) {
   info->copies = static_cast<int32_t>(p->copies);
   info->qbar = p->qbar;
   info->build_ms = p->build_ms;
+  g_err.clear();
+  return XM_OK;
+}
+
+xm_status xm_build_stats(const xm_problem* p, xm_kernel_stat* out, int32_t cap, int32_t* count) {
+  if (!p || !count || (cap > 0 && !out)) return fail(XM_EINVAL, "NULL argument");
+  const int n = static_cast<int>(p->build_stats.size());
+  *count = n;
+  for (int k = 0; k < n && k < cap; ++k) {
+    const auto& st = p->build_stats[k];
+    xm_kernel_stat& o = out[k];
+    std::snprintf(o.name, sizeof(o.name), "%s", st.name);
+    o.launches = st.launches;
+    o.total_ms = st.ms;
+    o.bytes = st.bytes;
+    o.flops = st.flops;
+  }
   g_err.clear();
   return XM_OK;
 }

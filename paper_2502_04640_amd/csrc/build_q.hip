@@ -380,10 +380,12 @@ __global__ __launch_bounds__(kB) void gather_product_kernel(const int32_t* __res
                                                             const double* __restrict__ D, int32_t ldd,
                                                             int32_t K, double* out, int32_t ldo,
                                                             int accumulate, int upper) {
-  const int i = blockIdx.y;
+  // grid: x = frame (fastest), y = column tile, so that the workgroups in flight
+  // share one column tile of D (N rows x 8 KB, resident in the last-level cache)
+  const int i = blockIdx.x;
   const int cmin = upper ? 3 * i : 0;
-  if (static_cast<int>(blockIdx.x + 1) * (kB * kVPT) <= cmin) return;  // tile wholly left of the diagonal
-  const int c0 = blockIdx.x * (kB * kVPT) + threadIdx.x;
+  if (static_cast<int>(blockIdx.y + 1) * (kB * kVPT) <= cmin) return;  // tile wholly left of the diagonal
+  const int c0 = blockIdx.y * (kB * kVPT) + threadIdx.x;
   double acc[3][kVPT] = {};
   const int32_t s0 = row_ptr[i], s1 = row_ptr[i + 1];
   for (int32_t s = s0; s < s1; ++s) {
@@ -539,6 +541,33 @@ __global__ void to_bf16_kernel(const double* __restrict__ in, int64_t n, uint16_
   out[e] = static_cast<uint16_t>((x + 0x7fffu + lsb) >> 16);
 }
 
+// HIP events around every launch of one kernel on a stream; total() waits
+// for the last one and returns the summed device time in milliseconds.
+struct LaunchTimer {
+  std::vector<hipEvent_t> ev;
+  void start(hipStream_t s) { ev.push_back(record(s)); }
+  void stop(hipStream_t s) { ev.push_back(record(s)); }
+  static hipEvent_t record(hipStream_t s) {
+    hipEvent_t e;
+    XM_HIP(hipEventCreate(&e));
+    XM_HIP(hipEventRecord(e, s));
+    return e;
+  }
+  double total() {
+    double ms = 0.0;
+    if (!ev.empty()) XM_HIP(hipEventSynchronize(ev.back()));
+    for (size_t k = 0; k + 1 < ev.size(); k += 2) {
+      float t = 0.f;
+      XM_HIP(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+      ms += t;
+    }
+    return ms;
+  }
+  ~LaunchTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 int bits_for(uint64_t v) {  // number of bits needed to represent values < v
   int b = 1;
   while (b < 64 && (uint64_t(1) << b) < v) ++b;
@@ -686,6 +715,7 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
     DevBuf<double> Dinv(kNB * kNB);
     DevBuf<double> Ct(static_cast<size_t>(kNB) * P->ldg), Pt(static_cast<size_t>(kNB) * P->ldg);
     const unsigned tiles = cdiv(ng, 64);
+    LaunchTimer t_sweep;
     for (int32_t k0 = 0; k0 < ng; k0 += kNB) {
       const int32_t nb = std::min(kNB, ng - k0);
       hipLaunchKernelGGL(sweep_pivot_kernel, dim3(1), dim3(kB), 0, s, P->Gm.ptr, P->ldg, k0, nb, dscale,
@@ -694,9 +724,11 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
       hipLaunchKernelGGL(sweep_panel_kernel, dim3(cdiv(ng, 64), cdiv(nb, 4)), dim3(kB), 0, s, P->Gm.ptr, P->ldg,
                          ng, k0, nb, Dinv.ptr, Ct.ptr, Pt.ptr, P->ldg);
       XM_LAUNCH_CHECK("sweep_panel_kernel");
+      t_sweep.start(s);
       hipLaunchKernelGGL(sweep_update_kernel, dim3(tiles, tiles), dim3(kB), 0, s, P->Gm.ptr, P->ldg, ng, Ct.ptr,
                          Pt.ptr, P->ldg, nb);
       XM_LAUNCH_CHECK("sweep_update_kernel");
+      t_sweep.stop(s);
       hipLaunchKernelGGL(sweep_finish_kernel, dim3(cdiv(ng, kB), nb), dim3(kB), 0, s, P->Gm.ptr, P->ldg, ng, k0,
                          nb, Ct.ptr, P->ldg, Dinv.ptr);
       XM_LAUNCH_CHECK("sweep_finish_kernel");
@@ -709,23 +741,39 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
     XM_HIP(hipMemcpyAsync(hflags, flags.ptr, sizeof(hflags), hipMemcpyDeviceToHost, s));
     XM_HIP(hipStreamSynchronize(s));
     require(!hflags[4], XM_EGRAPH, "the view graph is disconnected (grounded Laplacian is singular)");
+    // per step: the upper triangle of G read and written once, nb * ng^2 FMA-pairs over it
+    const double g2 = static_cast<double>(ng) * ng;
+    P->build_stats.push_back({"sweep_update_kernel", static_cast<int>(cdiv(ng, kNB)), t_sweep.total(),
+                              cdiv(ng, kNB) * 8.0 * g2, static_cast<double>(ng) * g2});
   }
 
   // P = A_rt[:,1:] (-G^{-1})   (3N x (N-1)), then Pt = P^T, then Q += A_rt[:,1:] Pt
   {
     const int32_t ldp = static_cast<int32_t>(round_up(ng, 64));
     DevBuf<double> Pm(static_cast<size_t>(P->n3) * ldp);
-    hipLaunchKernelGGL(gather_product_kernel, dim3(cdiv(ng, kB * kVPT), N), dim3(kB), 0, s, P->row_ptr.ptr,
+    LaunchTimer t_gather;
+    t_gather.start(s);
+    hipLaunchKernelGGL(gather_product_kernel, dim3(N, cdiv(ng, kB * kVPT)), dim3(kB), 0, s, P->row_ptr.ptr,
                        P->col.ptr, P->Art.ptr, P->Gm.ptr, P->ldg, ng, Pm.ptr, ldp, 0, 0);
     XM_LAUNCH_CHECK("gather_product_kernel(P)");
+    t_gather.stop(s);
     DevBuf<double> Ptr(static_cast<size_t>(ng) * P->ld);
     hipLaunchKernelGGL(transpose_kernel, dim3(cdiv(ng, 64), cdiv(P->n3, 64)), dim3(kB), 0, s, Pm.ptr, P->n3, ng,
                        ldp, Ptr.ptr, P->ld);
     XM_LAUNCH_CHECK("transpose_kernel");
-    hipLaunchKernelGGL(gather_product_kernel, dim3(cdiv(P->n3, kB * kVPT), N), dim3(kB), 0, s, P->row_ptr.ptr,
+    t_gather.start(s);
+    hipLaunchKernelGGL(gather_product_kernel, dim3(N, cdiv(P->n3, kB * kVPT)), dim3(kB), 0, s, P->row_ptr.ptr,
                        P->col.ptr, P->Art.ptr, Ptr.ptr, P->ld, P->n3, P->Q64.ptr, P->ld, 1, 1);
     XM_LAUNCH_CHECK("gather_product_kernel(Q)");
+    t_gather.stop(s);
     XM_HIP(hipStreamSynchronize(s));
+    // P pass: G^{-1} read once, P written once, 3 FMAs per (stored block, column);
+    // Q pass: P^T read once, the upper triangle of Q read and written once, half the columns
+    const double nnz_off = static_cast<double>(S);  // every stored block of A_rt (the few with j = 0 are skipped)
+    const double bytes = 8.0 * (static_cast<double>(ng) * ng + 3.0 * N * ng) +
+                         8.0 * (static_cast<double>(ng) * P->n3 + static_cast<double>(P->n3) * P->n3);
+    const double flops = 6.0 * nnz_off * ng + 6.0 * nnz_off * P->n3 * 0.5;
+    P->build_stats.push_back({"gather_product_kernel", 2, t_gather.total(), bytes, flops});
   }
   {
     const unsigned T = cdiv(P->n3, 32);

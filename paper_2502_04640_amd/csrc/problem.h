@@ -14,6 +14,13 @@ struct xm_problem {
   double qbar = 0.0;
   double build_ms = 0.0;
   int64_t nnzb = 0, n_pairs = 0;
+  // device time of the main assembly kernels of the build (xm_build_stats)
+  struct KernelStat {
+    const char* name;
+    int launches;
+    double ms, bytes, flops;
+  };
+  std::vector<KernelStat> build_stats;
 
   // Q, row-major [3N][ld], zero padding columns
   xm::DevBuf<double> Q64;

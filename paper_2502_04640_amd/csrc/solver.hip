@@ -93,7 +93,7 @@ void grad_product(xm_problem* p, xm_dtype qg, const T* Yt, int r, T* G, const Re
 
 struct RtrOut {
   double f = 0, gnorm = 0, ynorm = 0;
-  int outer = 0, inner = 0, spmm = 0;
+  int outer = 0, inner = 0, spmm = 0, accepted = 0;
   bool converged = false, floor = false;
 };
 
@@ -201,6 +201,7 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
     }
     if (accept) {
       rejections = 0;
+      ++out.accepted;
       std::swap(V.Rt.ptr, V.Rt2.ptr);
       std::swap(V.s.ptr, V.s2.ptr);
       std::swap(V.Yt.ptr, V.Yt2.ptr);
@@ -251,7 +252,7 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   const bool f64 = std::is_same<T, double>::value;
   const xm_dtype qg = f64 ? XM_F64 : XM_F32;
   const xm_dtype qh = f64 ? XM_F64 : (o.compute == XM_BF16 ? XM_BF16 : XM_F32);
-  const double grad_tol = (o.grad_tol > 0) ? o.grad_tol : (f64 ? 1e-9 : 1e-7);
+  const double grad_tol = (o.grad_tol > 0) ? o.grad_tol : (f64 ? 1e-9 : 3e-7);
   const double cert_tol = (o.cert_tol > 0) ? o.cert_tol : (f64 ? 1e-7 : 1e-5);
   const int rmax = o.r_max;
   Vecs<T> V(N, rmax + 1);
@@ -304,6 +305,7 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
       ro.ynorm = r2.ynorm;
       ro.converged = r2.converged;
       ro.floor = r2.floor;
+      if (r2.accepted == 0) break;  // the iterate's own rounding is the floor: no further progress
     }
     XM_HIP(hipStreamSynchronize(st));
     auto t1 = std::chrono::steady_clock::now();
