@@ -311,37 +311,59 @@ __global__ __launch_bounds__(kB) void sweep_panel_kernel(const double* __restric
 // k-steps: lane l supplies A-operand [i = l % 16][k = l / 16] and B-operand
 // [k = l / 16][j = l % 16]; register q of the result holds [l / 16 + 4 q][l % 16].
 typedef double v4d __attribute__((ext_vector_type(4)));
+// The tile of A is loaded into registers first, so its HBM latency overlaps the
+// panel staging and the matrix-core work; the panels go through LDS in
+// k-chunks of kSweepKC rows (smaller chunks: less LDS, more workgroups per CU).
+#ifndef XM_SWEEP_KC
+#define XM_SWEEP_KC 16
+#endif
+constexpr int kSweepKC = XM_SWEEP_KC;
 __global__ __launch_bounds__(kB) void sweep_update_kernel(double* A, int32_t lda, int32_t n,
                                                           const double* __restrict__ Ct,
                                                           const double* __restrict__ Pt, int32_t ldt,
                                                           int32_t nb) {
   if (blockIdx.x < blockIdx.y) return;  // lower tile: not kept
-  __shared__ double Cs[kNB][64];
-  __shared__ double Ps[kNB][64];
+  __shared__ double Cs[kSweepKC][64];
+  __shared__ double Ps[kSweepKC][64];
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   const int t = threadIdx.x;
-  for (int e = t; e < kNB * 64; e += kB) {
-    const int p = e >> 6, c = e & 63;
-    Cs[p][c] = (p < nb && i0 + c < n) ? Ct[static_cast<int64_t>(p) * ldt + i0 + c] : 0.0;
-    Ps[p][c] = (p < nb && j0 + c < n) ? Pt[static_cast<int64_t>(p) * ldt + j0 + c] : 0.0;
-  }
-  __syncthreads();
   const int lane = t & 63, wave = t >> 6;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
+  double g[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + wi + 16 * a + lk + 4 * q;
+        const int j = j0 + wj + 16 * b + lr;
+        g[a][b][q] = (i < n && j < n) ? A[static_cast<int64_t>(i) * lda + j] : 0.0;
+      }
   v4d acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int kc = 0; kc < kNB; kc += kSweepKC) {
+    if (kc > 0) __syncthreads();  // the previous chunk has been consumed
+    for (int e = t; e < kSweepKC * 64; e += kB) {
+      const int p = e >> 6, c = e & 63;
+      const int pp = kc + p;
+      Cs[p][c] = (pp < nb && i0 + c < n) ? Ct[static_cast<int64_t>(pp) * ldt + i0 + c] : 0.0;
+      Ps[p][c] = (pp < nb && j0 + c < n) ? Pt[static_cast<int64_t>(pp) * ldt + j0 + c] : 0.0;
+    }
+    __syncthreads();
 #pragma unroll 4
-  for (int k = 0; k < kNB; k += 4) {
-    const double a0 = Cs[k + lk][wi + lr], a1 = Cs[k + lk][wi + 16 + lr];
-    const double b0 = Ps[k + lk][wj + lr], b1 = Ps[k + lk][wj + 16 + lr];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    for (int k = 0; k < kSweepKC; k += 4) {
+      const double a0 = Cs[k + lk][wi + lr], a1 = Cs[k + lk][wi + 16 + lr];
+      const double b0 = Ps[k + lk][wj + lr], b1 = Ps[k + lk][wj + 16 + lr];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -351,7 +373,7 @@ __global__ __launch_bounds__(kB) void sweep_update_kernel(double* A, int32_t lda
       for (int q = 0; q < 4; ++q) {
         const int i = i0 + wi + 16 * a + lk + 4 * q;
         const int j = j0 + wj + 16 * b + lr;
-        if (i < n && j < n) A[static_cast<int64_t>(i) * lda + j] -= acc[a][b][q];
+        if (i < n && j < n) A[static_cast<int64_t>(i) * lda + j] = g[a][b][q] - acc[a][b][q];
       }
 }
 
@@ -381,36 +403,66 @@ __global__ __launch_bounds__(kB) void gather_product_kernel(const int32_t* __res
                                                             int32_t K, double* out, int32_t ldo,
                                                             int accumulate, int upper) {
   // grid: x = frame (fastest), y = column tile, so that the workgroups in flight
-  // share one column tile of D (N rows x 8 KB, resident in the last-level cache)
+  // share one column tile of D (N rows x 8 KB, resident in the last-level cache).
+  // Thread t owns the column pairs (c, c+1) and (c+512, c+513), c = tile + 2t;
+  // neighbours are taken 4 at a time so that 8 16-byte loads are in flight.
   const int i = blockIdx.x;
   const int cmin = upper ? 3 * i : 0;
   if (static_cast<int>(blockIdx.y + 1) * (kB * kVPT) <= cmin) return;  // tile wholly left of the diagonal
-  const int c0 = blockIdx.y * (kB * kVPT) + threadIdx.x;
-  double acc[3][kVPT] = {};
+  const int c0 = blockIdx.y * (kB * kVPT) + 2 * threadIdx.x;
+  const bool in0 = c0 < K, in1 = c0 + 2 * kB < K;  // pair in range (c < K, K <= ldd, ldd even)
+  double acc[3][4] = {};
   const int32_t s0 = row_ptr[i], s1 = row_ptr[i + 1];
-  for (int32_t s = s0; s < s1; ++s) {
+  int32_t s = s0;
+  for (; s + 4 <= s1; s += 4) {
+    double a[4][3];
+    double2 d0[4], d1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = col[s + u];
+      const double w = (j == 0) ? 0.0 : 1.0;  // column 0 of A_rt is the anchored frame: no term
+      a[u][0] = w * Art[3 * (s + u)];
+      a[u][1] = w * Art[3 * (s + u) + 1];
+      a[u][2] = w * Art[3 * (s + u) + 2];
+      const double* Dj = D + static_cast<int64_t>(j > 0 ? j - 1 : 0) * ldd;
+      d0[u] = in0 ? *reinterpret_cast<const double2*>(Dj + c0) : double2{0.0, 0.0};
+      d1[u] = in1 ? *reinterpret_cast<const double2*>(Dj + c0 + 2 * kB) : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        acc[q][0] += a[u][q] * d0[u].x;
+        acc[q][1] += a[u][q] * d0[u].y;
+        acc[q][2] += a[u][q] * d1[u].x;
+        acc[q][3] += a[u][q] * d1[u].y;
+      }
+  }
+  for (; s < s1; ++s) {
     const int j = col[s];
     if (j == 0) continue;
-    const double a0 = Art[3 * s], a1 = Art[3 * s + 1], a2 = Art[3 * s + 2];
     const double* Dj = D + static_cast<int64_t>(j - 1) * ldd;
+    const double2 e0 = in0 ? *reinterpret_cast<const double2*>(Dj + c0) : double2{0.0, 0.0};
+    const double2 e1 = in1 ? *reinterpret_cast<const double2*>(Dj + c0 + 2 * kB) : double2{0.0, 0.0};
 #pragma unroll
-    for (int v = 0; v < kVPT; ++v) {
-      const int c = c0 + v * kB;
-      const double d = (c < K) ? Dj[c] : 0.0;
-      acc[0][v] += a0 * d;
-      acc[1][v] += a1 * d;
-      acc[2][v] += a2 * d;
+    for (int q = 0; q < 3; ++q) {
+      const double aq = Art[3 * s + q];
+      acc[q][0] += aq * e0.x;
+      acc[q][1] += aq * e0.y;
+      acc[q][2] += aq * e1.x;
+      acc[q][3] += aq * e1.y;
     }
   }
+  const int cc[4] = {c0, c0 + 1, c0 + 2 * kB, c0 + 2 * kB + 1};
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double* o = out + static_cast<int64_t>(3 * i + a) * ldo;
+  for (int q = 0; q < 3; ++q) {
+    double* o = out + static_cast<int64_t>(3 * i + q) * ldo;
 #pragma unroll
-    for (int v = 0; v < kVPT; ++v) {
-      const int c = c0 + v * kB;
+    for (int v = 0; v < 4; ++v) {
+      const int c = cc[v];
       if (c < K && c >= cmin) {
-        if (accumulate) o[c] += acc[a][v];
-        else o[c] = acc[a][v];
+        if (accumulate) o[c] += acc[q][v];
+        else o[c] = acc[q][v];
       }
     }
   }
@@ -458,6 +510,21 @@ __global__ __launch_bounds__(kB) void trace_kernel(const double* __restrict__ Q,
   for (int i = threadIdx.x; i < n; i += kB) v[0] += Q[static_cast<int64_t>(i) * ld + i];
   block_sum<1>(v, lds);
   if (threadIdx.x == 0) out[0] = v[0];
+}
+
+// largest diagonal entry of a matrix (one block; scale of the pivot test)
+__global__ __launch_bounds__(kB) void diag_max_kernel(const double* __restrict__ A, int32_t n, int32_t ld,
+                                                      double* out) {
+  __shared__ double lds[kB];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += kB) m = fmax(m, A[static_cast<int64_t>(i) * ld + i]);
+  lds[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = lds[0];
 }
 
 // q_kk = tr(Q_kk) / 3 per frame (the preconditioner of the local solver)
@@ -705,13 +772,13 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
     // scale for the pivot test: largest diagonal of G
     double dscale = 0.0;
     {
-      // small host loop over the diagonal (N - 1 reads, once)
-      std::vector<double> hd(ng);
-      XM_HIP(hipMemcpy2DAsync(hd.data(), sizeof(double), P->Gm.ptr, (P->ldg + 1) * sizeof(double),
-                              sizeof(double), ng, hipMemcpyDeviceToHost, s));
+      DevBuf<double> dm(1);
+      hipLaunchKernelGGL(diag_max_kernel, dim3(1), dim3(kB), 0, s, P->Gm.ptr, ng, P->ldg, dm.ptr);
+      XM_LAUNCH_CHECK("diag_max_kernel");
+      XM_HIP(hipMemcpyAsync(&dscale, dm.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
       XM_HIP(hipStreamSynchronize(s));
-      for (double v : hd) dscale = std::max(dscale, v);
     }
+    require(dscale > 0.0, XM_EGRAPH, "the grounded Laplacian has no positive diagonal entry");
     DevBuf<double> Dinv(kNB * kNB);
     DevBuf<double> Ct(static_cast<size_t>(kNB) * P->ldg), Pt(static_cast<size_t>(kNB) * P->ldg);
     const unsigned tiles = cdiv(ng, 64);
@@ -751,7 +818,7 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   {
     const int32_t ldp = static_cast<int32_t>(round_up(ng, 64));
     DevBuf<double> Pm(static_cast<size_t>(P->n3) * ldp);
-    LaunchTimer t_gather;
+    LaunchTimer t_gather, t_gather_q;
     t_gather.start(s);
     hipLaunchKernelGGL(gather_product_kernel, dim3(N, cdiv(ng, kB * kVPT)), dim3(kB), 0, s, P->row_ptr.ptr,
                        P->col.ptr, P->Art.ptr, P->Gm.ptr, P->ldg, ng, Pm.ptr, ldp, 0, 0);
@@ -761,19 +828,20 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
     hipLaunchKernelGGL(transpose_kernel, dim3(cdiv(ng, 64), cdiv(P->n3, 64)), dim3(kB), 0, s, Pm.ptr, P->n3, ng,
                        ldp, Ptr.ptr, P->ld);
     XM_LAUNCH_CHECK("transpose_kernel");
-    t_gather.start(s);
+    t_gather_q.start(s);
     hipLaunchKernelGGL(gather_product_kernel, dim3(N, cdiv(P->n3, kB * kVPT)), dim3(kB), 0, s, P->row_ptr.ptr,
                        P->col.ptr, P->Art.ptr, Ptr.ptr, P->ld, P->n3, P->Q64.ptr, P->ld, 1, 1);
     XM_LAUNCH_CHECK("gather_product_kernel(Q)");
-    t_gather.stop(s);
+    t_gather_q.stop(s);
     XM_HIP(hipStreamSynchronize(s));
     // P pass: G^{-1} read once, P written once, 3 FMAs per (stored block, column);
     // Q pass: P^T read once, the upper triangle of Q read and written once, half the columns
     const double nnz_off = static_cast<double>(S);  // every stored block of A_rt (the few with j = 0 are skipped)
-    const double bytes = 8.0 * (static_cast<double>(ng) * ng + 3.0 * N * ng) +
-                         8.0 * (static_cast<double>(ng) * P->n3 + static_cast<double>(P->n3) * P->n3);
-    const double flops = 6.0 * nnz_off * ng + 6.0 * nnz_off * P->n3 * 0.5;
-    P->build_stats.push_back({"gather_product_kernel", 2, t_gather.total(), bytes, flops});
+    P->build_stats.push_back({"gather_product_kernel (P)", 1, t_gather.total(),
+                              8.0 * (static_cast<double>(ng) * ng + 3.0 * N * ng), 6.0 * nnz_off * ng});
+    P->build_stats.push_back({"gather_product_kernel (Q)", 1, t_gather_q.total(),
+                              8.0 * (static_cast<double>(ng) * P->n3 + static_cast<double>(P->n3) * P->n3),
+                              6.0 * nnz_off * P->n3 * 0.5});
   }
   {
     const unsigned T = cdiv(P->n3, 32);

@@ -17,9 +17,11 @@
 // Stop when |grad| <= grad_tol qbar |Y|, or, at the precision floor of
 // reduced-precision products, after 6 rejected steps in a row with |grad|
 // within 30 grad_tol qbar |Y|.  A reduced-precision solve then checks the
-// gradient with FP64 products and, while it is above the tolerance, runs up to
-// three more trust-region passes whose gradient products are taken relative
-// to the current point (FP64 product at that point as reference, see Rebase).  The
+// gradient with FP64 products and, while it is above grad_tol / 30, runs up to
+// two short trust-region passes (to that tolerance; truncated-CG steps of at
+// most 25 products) whose gradient products
+// are taken relative to the current point, with the FP64 product at that point
+// as reference (see Rebase).  The
 // cost decrease is evaluated as <Y+ - Y, Q (Y+ + Y)> from the two products
 // already computed, which stays accurate in FP32 where f(Y+) - f(Y) would
 // cancel.  The staircase escape follows Theorem "Descent Direction": block k of
@@ -53,16 +55,23 @@ struct Vecs {
 };
 
 // Gradient products relative to a reference point (reduced precision only):
-// G(Y) = Gref + Q (Y - Yref) with Gref = Q Yref formed once from the FP64 Q.
+// G(Y) = Gref + Q (Y - Yref) with Gref = Q Yref from the FP64 Q, kept in FP64.
 // The reduced-precision product then only carries the rounding error of the
 // small difference Y - Yref, not of Q Y itself, whose entries cancel heavily
-// near the optimum (Y is close to the null space of the dual matrix); this is
-// what lets an FP32 solve converge below the noise floor of its own products.
+// near the optimum (Y is close to the null space of the dual matrix).  G is
+// kept in FP64 (G64), and the Riemannian gradient and the cost change are
+// formed from it in FP64, so that the cancellation in the projection
+// E - R sym(R^T E) loses nothing either; the Hessian products use the rounded
+// copy.  This is what lets an FP32 solve converge below the rounding noise
+// of its own products.
 template <typename T>
 struct Rebase {
   const T* Yref = nullptr;
-  const T* Gref = nullptr;
+  const double* Gref = nullptr;  // Q Yref, FP64
   T* tmp = nullptr;
+  double* G64 = nullptr;         // G(Y) at the current point, FP64
+  double* G2_64 = nullptr;       // G(Y) at the candidate, FP64
+  bool on() const { return Yref != nullptr; }
 };
 
 template <typename T>
@@ -71,24 +80,30 @@ __global__ void sub_kernel(int64_t n, const T* __restrict__ a, const T* __restri
   if (i < n) out[i] = a[i] - b[i];
 }
 
+// G64 = Gref + G (FP64); G <- G64 rounded
 template <typename T>
-__global__ void add_kernel(int64_t n, const T* __restrict__ a, T* __restrict__ out) {
+__global__ void combine_kernel(int64_t n, const double* __restrict__ Gref, T* __restrict__ G,
+                               double* __restrict__ G64) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (i < n) out[i] += a[i];
+  if (i >= n) return;
+  const double g = Gref[i] + static_cast<double>(G[i]);
+  G64[i] = g;
+  G[i] = static_cast<T>(g);
 }
 
 template <typename T>
-void grad_product(xm_problem* p, xm_dtype qg, const T* Yt, int r, T* G, const Rebase<T>& rb, hipStream_t st) {
+void grad_product(xm_problem* p, xm_dtype qg, const T* Yt, int r, T* G, double* G64, const Rebase<T>& rb,
+                  hipStream_t st) {
   const int64_t n = p->n3 * static_cast<int64_t>(r);
-  if (!rb.Yref) {
+  if (!rb.on()) {
     spmm_yt<T>(p, qg, Yt, r, G, st);
     return;
   }
   hipLaunchKernelGGL(sub_kernel<T>, dim3(cdiv(n, 256)), dim3(256), 0, st, n, Yt, rb.Yref, rb.tmp);
   XM_LAUNCH_CHECK("sub_kernel");
   spmm_yt<T>(p, qg, rb.tmp, r, G, st);
-  hipLaunchKernelGGL(add_kernel<T>, dim3(cdiv(n, 256)), dim3(256), 0, st, n, rb.Gref, G);
-  XM_LAUNCH_CHECK("add_kernel");
+  hipLaunchKernelGGL(combine_kernel<T>, dim3(cdiv(n, 256)), dim3(256), 0, st, n, rb.Gref, G, G64);
+  XM_LAUNCH_CHECK("combine_kernel");
 }
 
 struct RtrOut {
@@ -119,9 +134,17 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
   double sums[5];
 
   mf.scale(r, V.Rt.ptr, V.s.ptr, V.Yt.ptr, st);
-  grad_product<T>(p, qg, V.Yt.ptr, r, V.G.ptr, rb, st);
+  double* G64 = rb.G64;
+  double* G2_64 = rb.G2_64;
+  auto form_grad = [&]() {
+    if (rb.on()) mf.grad(r, V.Rt.ptr, V.s.ptr, static_cast<const double*>(G64), V.gR.ptr, V.gs.ptr, V.Sc.ptr,
+                         V.ec.ptr, V.part.ptr, st);
+    else mf.grad(r, V.Rt.ptr, V.s.ptr, static_cast<const T*>(V.G.ptr), V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr,
+                 V.part.ptr, st);
+  };
+  grad_product<T>(p, qg, V.Yt.ptr, r, V.G.ptr, G64, rb, st);
   ++out.spmm;
-  mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
+  form_grad();
   read_partials(V.part.ptr, nb, 5, sums, st);
   double f = sums[0], gg = sums[1], gnorm = std::sqrt(sums[1]), ynorm = std::sqrt(sums[2]);
   // preconditioner scale at the current point and <g, P g>
@@ -176,10 +199,14 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
     out.inner += std::min(j, max_inner);
     // ---- candidate and ratio test ----
     mf.retract(r, V.Rt.ptr, V.s.ptr, V.etaR.ptr, V.etas.ptr, V.Rt2.ptr, V.s2.ptr, V.Yt2.ptr, st);
-    grad_product<T>(p, qg, V.Yt2.ptr, r, V.G2.ptr, rb, st);
+    grad_product<T>(p, qg, V.Yt2.ptr, r, V.G2.ptr, G2_64, rb, st);
     ++out.spmm;
-    mf.model(r, V.s.ptr, V.gR.ptr, V.gs.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr, V.Yt.ptr, V.G.ptr,
-             V.Yt2.ptr, V.G2.ptr, V.part.ptr, st);
+    if (rb.on())
+      mf.model(r, V.s.ptr, V.gR.ptr, V.gs.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr, V.Yt.ptr,
+               static_cast<const double*>(G64), V.Yt2.ptr, static_cast<const double*>(G2_64), true, V.part.ptr, st);
+    else
+      mf.model(r, V.s.ptr, V.gR.ptr, V.gs.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr, V.Yt.ptr,
+               static_cast<const T*>(V.G.ptr), V.Yt2.ptr, static_cast<const T*>(V.G2.ptr), false, V.part.ptr, st);
     read_partials(V.part.ptr, nb, 3, sums, st);
     const double mdec = -(sums[0] + 0.5 * sums[1]);
     const double df = sums[2];
@@ -190,7 +217,9 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
     const bool finite = std::isfinite(rho);
     if (!finite || rho < 0.25) Delta *= 0.25;
     else if (rho > 0.75 && boundary) Delta = std::min(2.0 * Delta, Dbar);
-    const bool accept = finite && mdec > 0.0 && rho > rho_prime;
+    // a step the (reduced-precision) model misjudges as an increase is still
+    // taken when the evaluated cost went down
+    const bool accept = finite && ((mdec > 0.0 && rho > rho_prime) || (mdec <= 0.0 && df < -reg));
     if (o.verbose)
       std::fprintf(stderr, "[xm] r=%d it=%d f=%.12e |g|=%.3e Delta=%.3e rho=%.3f inner=%d %s%s\n", r, k, f, gnorm,
                    Delta, rho, std::min(j, max_inner), boundary ? "boundary" : "interior", accept ? "" : " rejected");
@@ -206,7 +235,8 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
       std::swap(V.s.ptr, V.s2.ptr);
       std::swap(V.Yt.ptr, V.Yt2.ptr);
       std::swap(V.G.ptr, V.G2.ptr);
-      mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
+      std::swap(G64, G2_64);
+      form_grad();
       read_partials(V.part.ptr, nb, 5, sums, st);
       f = sums[0];
       gg = sums[1];
@@ -230,8 +260,7 @@ struct Check {
   double f, gnorm, ynorm;
 };
 
-template <typename T>
-Check fp64_check(xm_problem* p, const double* Yt64, int r, hipStream_t st, T* G_out = nullptr) {
+Check fp64_check(xm_problem* p, const double* Yt64, int r, hipStream_t st, double* G_out = nullptr) {
   const int N = p->N;
   Vecs<double> V(N, r);
   Manifold<double> mf(N);
@@ -240,7 +269,7 @@ Check fp64_check(xm_problem* p, const double* Yt64, int r, hipStream_t st, T* G_
   mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
   double sums[5];
   read_partials(V.part.ptr, static_cast<int>(mf.blocks()), 5, sums, st);
-  if (G_out) transpose_rows<double, T>(V.G.ptr, 1, static_cast<int>(p->n3 * r), G_out, st);
+  if (G_out) XM_HIP(hipMemcpyAsync(G_out, V.G.ptr, p->n3 * r * sizeof(double), hipMemcpyDeviceToDevice, st));
   return {sums[0], std::sqrt(sums[1]), std::sqrt(sums[2])};
 }
 
@@ -258,14 +287,20 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   Vecs<T> V(N, rmax + 1);
   Manifold<T> mf(N);
   DevBuf<double> Yt64(static_cast<size_t>(n3) * (rmax + 1)), vmin(n3);
-  // reduced precision: reference point and FP64 product for the refinement passes
-  DevBuf<T> Yref, Gref, Rtmp;
+  // reduced precision: reference point and FP64 products for the refinement passes
+  DevBuf<T> Yref, Rtmp;
+  DevBuf<double> Gref, G64a, G64b;
   if (!f64) {
     Yref.alloc(static_cast<size_t>(n3) * rmax);
-    Gref.alloc(static_cast<size_t>(n3) * rmax);
     Rtmp.alloc(static_cast<size_t>(n3) * rmax);
+    Gref.alloc(static_cast<size_t>(n3) * rmax);
+    G64a.alloc(static_cast<size_t>(n3) * rmax);
+    G64b.alloc(static_cast<size_t>(n3) * rmax);
   }
-  const int max_refine = 3;
+  // refinement target: the FP32 stage stops at grad_tol (its products' own
+  // rounding allows little more), the FP64-referenced passes go 30x further
+  const int max_refine = 2;
+  const double refine_tol = grad_tol / 30.0;
 
   int r;
   if (Y0) {
@@ -289,22 +324,30 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
     // products taken relative to it (Rebase), the FP64 product as reference.
     for (int pass = 0; !f64 && pass < max_refine; ++pass) {
       transpose_rows<T, double>(V.Yt.ptr, 1, static_cast<int>(n3 * r), Yt64.ptr, st);
-      const Check ck = fp64_check<T>(p, Yt64.ptr, r, st, Gref.ptr);
+      const Check ck = fp64_check(p, Yt64.ptr, r, st, Gref.ptr);
       ++info->spmm_count;
       if (o.verbose)
         std::fprintf(stderr, "[xm] rank %d: FP64 check |g|=%.3e (tol %.3e)%s\n", r, ck.gnorm,
-                     grad_tol * p->qbar * ck.ynorm, ck.gnorm <= grad_tol * p->qbar * ck.ynorm ? "" : ", refining");
-      if (ck.gnorm <= grad_tol * p->qbar * ck.ynorm) break;
+                     refine_tol * p->qbar * ck.ynorm, ck.gnorm <= refine_tol * p->qbar * ck.ynorm ? "" : ", refining");
+      if (ck.gnorm <= refine_tol * p->qbar * ck.ynorm) break;
       XM_HIP(hipMemcpyAsync(Yref.ptr, V.Yt.ptr, n3 * r * sizeof(T), hipMemcpyDeviceToDevice, st));
-      const RtrOut r2 = rtr<T>(p, V, r, qg, qh, o, grad_tol, Rebase<T>{Yref.ptr, Gref.ptr, Rtmp.ptr}, st);
+      // a refinement pass is a short polish from a converged point: at most 15
+      // steps, starting from a radius 64x below the default
+      xm_solve_opts oref = o;
+      oref.max_outer = (o.max_outer > 0) ? std::min(o.max_outer, 15) : 15;
+      if (oref.delta0 <= 0) oref.delta0 = std::sqrt(3.0 * N) / 8.0 / 64.0;
+      oref.max_inner = (o.max_inner > 0) ? std::min(o.max_inner, 25) : 25;  // truncated Newton steps
+      const RtrOut r2 = rtr<T>(p, V, r, qg, qh, oref, refine_tol,
+                               Rebase<T>{Yref.ptr, Gref.ptr, Rtmp.ptr, G64a.ptr, G64b.ptr}, st);
       ro.outer += r2.outer;
       ro.inner += r2.inner;
       ro.spmm += r2.spmm;
       ro.f = r2.f;
       ro.gnorm = r2.gnorm;
       ro.ynorm = r2.ynorm;
-      ro.converged = r2.converged;
-      ro.floor = r2.floor;
+      // convergence is judged at grad_tol: the refinement target is a bonus
+      if (r2.converged && !r2.floor) ro.floor = false;
+      ro.converged = ro.converged || r2.converged;
       if (r2.accepted == 0) break;  // the iterate's own rounding is the floor: no further progress
     }
     XM_HIP(hipStreamSynchronize(st));
@@ -349,7 +392,7 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   // final FP64 quantities
   if (f64) XM_HIP(hipMemcpyAsync(Yt64.ptr, V.Yt.ptr, n3 * r * sizeof(double), hipMemcpyDeviceToDevice, st));
   else transpose_rows<T, double>(V.Yt.ptr, 1, static_cast<int>(n3 * r), Yt64.ptr, st);
-  const Check ck = fp64_check<T>(p, Yt64.ptr, r, st);
+  const Check ck = fp64_check(p, Yt64.ptr, r, st);
   XM_HIP(hipMemsetAsync(Y_out, 0, static_cast<size_t>(rmax) * n3 * sizeof(double), st));
   transpose_rows<double, double>(Yt64.ptr, static_cast<int>(n3), r, Y_out, st);
   XM_HIP(hipStreamSynchronize(st));

@@ -279,18 +279,29 @@ __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __re
 }
 
 // out[j][a] = sum_{s <= j / RS} colpart[s][j][a] + sum_{c >= j / C} rowpart[c][j][a]
+// 64 outputs per workgroup, 4 threads per output (every 4th partial each),
+// the 4 sums added in a fixed order: deterministic.
 template <typename TA, typename TV, int R, int C>
-__global__ void spmm_sym_reduce_kernel(const TA* __restrict__ colpart, const TA* __restrict__ rowpart, int32_t n3,
-                                       int32_t nchunks, TV* __restrict__ out) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+__global__ __launch_bounds__(kB) void spmm_sym_reduce_kernel(const TA* __restrict__ colpart,
+                                                             const TA* __restrict__ rowpart, int32_t n3,
+                                                             int32_t nchunks, TV* __restrict__ out) {
+  __shared__ TA sums[4][64];
   const int64_t m = static_cast<int64_t>(n3) * R;
-  if (e >= m) return;
-  const int jrow = static_cast<int>(e / R);
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
   TA s = TA(0);
-  const int smax = jrow / kSymRows;
-  for (int k = 0; k <= smax; ++k) s += colpart[static_cast<int64_t>(k) * m + e];
-  for (int k = jrow / C; k < nchunks; ++k) s += rowpart[static_cast<int64_t>(k) * m + e];
-  out[e] = static_cast<TV>(s);
+  if (e < m) {
+    const int jrow = static_cast<int>(e / R);
+    const int smax = jrow / kSymRows;
+    for (int k = g; k <= smax; k += 4) s += colpart[static_cast<int64_t>(k) * m + e];
+    for (int k = jrow / C + g; k < nchunks; k += 4) s += rowpart[static_cast<int64_t>(k) * m + e];
+  }
+  sums[g][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (g == 0 && e < m) {
+    const int l = threadIdx.x;
+    out[e] = static_cast<TV>((sums[0][l] + sums[1][l]) + (sums[2][l] + sums[3][l]));
+  }
 }
 
 template <typename TA, typename TV>
@@ -395,7 +406,7 @@ void launch_sym(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStre
                      colpart, rowpart);
   XM_LAUNCH_CHECK("spmm_sym_kernel");
   if (ev) XM_HIP(hipEventRecord(ev->stop, s));
-  hipLaunchKernelGGL((spmm_sym_reduce_kernel<TA, TV, R, C>), dim3(cdiv(per, kB)), dim3(kB), 0, s, colpart, rowpart,
+  hipLaunchKernelGGL((spmm_sym_reduce_kernel<TA, TV, R, C>), dim3(cdiv(per, 64)), dim3(kB), 0, s, colpart, rowpart,
                      p->n3, nchunks, out);
   XM_LAUNCH_CHECK("spmm_sym_reduce_kernel");
 }
