@@ -30,6 +30,10 @@ if ROOT not in sys.path:
 METRIC = "time-to-certified-optimum (s) + BSR SpMM GB/s, FP32 vs FP64, N=10k frames"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6   # MI355X FP64, vector and matrix
+# HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain
+# copy kernel (profiles/hbm_traffic_spmm_sym_f32_large.md); valid for the large
+# workload and the kernel as it was profiled -- re-measure after changing it.
+PMC_TRAFFIC_BYTES = {("large", "spmm_sym_kernel (f32 Q)"): 1.981e9}
 
 
 def log(msg):
@@ -215,7 +219,8 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    roof.update({"traffic": None, "kernel": dom_name, "launches": dk["launches"],
+    roof.update({"traffic": PMC_TRAFFIC_BYTES.get((args.workload, dom_name)), "kernel": dom_name,
+                 "launches": dk["launches"],
                  "bytes_per_launch": bytes_l, "flops_per_launch": flops_l or None,
                  "avg_launch_ms": round(avg_ms, 4)})
     spmm_gbs = {k: (stats[k]["bytes_per_launch"] / (stats[k]["total_ms"] / stats[k]["launches"] * 1e-3) / 1e9
