@@ -181,9 +181,9 @@ typedef struct {
                           6 consecutive rejected trust-region steps while
                           ||grad|| <= 30 grad_tol * qbar * ||Y||_F.  XM_F32 /
                           XM_BF16 then check the gradient with FP64 products
-                          and refine toward grad_tol / 30 (at most 2 passes of
-                          at most 15 steps; gradient products taken relative to
-                          the current point with its FP64 product as reference) */
+                          and refine toward grad_tol / 30 (one pass of at most
+                          8 steps; gradient products taken relative to the
+                          current point with its FP64 product as reference) */
   double cert_tol;     /* certified iff the lower bound on lambda_min(Z) >= -cert_tol * qbar
                           (<= 0: 1e-7 for XM_F64, 1e-5 otherwise) */
   int32_t max_outer;   /* trust-region iterations per rank (<= 0: 1000) */

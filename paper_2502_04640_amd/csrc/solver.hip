@@ -17,9 +17,9 @@
 // Stop when |grad| <= grad_tol qbar |Y|, or, at the precision floor of
 // reduced-precision products, after 6 rejected steps in a row with |grad|
 // within 30 grad_tol qbar |Y|.  A reduced-precision solve then checks the
-// gradient with FP64 products and, while it is above grad_tol / 30, runs up to
-// two short trust-region passes (to that tolerance; truncated-CG steps of at
-// most 25 products) whose gradient products
+// gradient with FP64 products and, if it is above grad_tol / 30, runs one
+// short trust-region pass (at most 8 steps toward that tolerance; truncated-CG
+// steps of at most 25 products) whose gradient products
 // are taken relative to the current point, with the FP64 product at that point
 // as reference (see Rebase).  The
 // cost decrease is evaluated as <Y+ - Y, Q (Y+ + Y)> from the two products
@@ -299,7 +299,7 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   }
   // refinement target: the FP32 stage stops at grad_tol (its products' own
   // rounding allows little more), the FP64-referenced passes go 30x further
-  const int max_refine = 2;
+  const int max_refine = 1;
   const double refine_tol = grad_tol / 30.0;
 
   int r;
@@ -331,10 +331,10 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
                      refine_tol * p->qbar * ck.ynorm, ck.gnorm <= refine_tol * p->qbar * ck.ynorm ? "" : ", refining");
       if (ck.gnorm <= refine_tol * p->qbar * ck.ynorm) break;
       XM_HIP(hipMemcpyAsync(Yref.ptr, V.Yt.ptr, n3 * r * sizeof(T), hipMemcpyDeviceToDevice, st));
-      // a refinement pass is a short polish from a converged point: at most 15
+      // a refinement pass is a short polish from a converged point: at most 8
       // steps, starting from a radius 64x below the default
       xm_solve_opts oref = o;
-      oref.max_outer = (o.max_outer > 0) ? std::min(o.max_outer, 15) : 15;
+      oref.max_outer = (o.max_outer > 0) ? std::min(o.max_outer, 8) : 8;
       if (oref.delta0 <= 0) oref.delta0 = std::sqrt(3.0 * N) / 8.0 / 64.0;
       oref.max_inner = (o.max_inner > 0) ? std::min(o.max_inner, 25) : 25;  // truncated Newton steps
       const RtrOut r2 = rtr<T>(p, V, r, qg, qh, oref, refine_tol,
