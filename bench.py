@@ -199,9 +199,11 @@ def main():
     # dominant kernel of the last timed step (per-launch HIP-event durations):
     # the Y Q products (per stored precision) and the main assembly kernels
     kernels = {}
+    names = {"f64": "spmm_sym_kernel (f64 Q)", "f32": "spmm_sym_kernel (f32 Q)",
+             "bf16": "spmm_split_kernel (bf16 Q)", "f64_factored": "factored product (f64: sparse A_rr, A_rt; dense G^-1)"}
     for k in stats:
         if stats[k]["launches"]:
-            kernels[f"{'spmm_split_kernel' if k == 'bf16' else 'spmm_sym_kernel'} ({k} Q)"] = {
+            kernels[names[k]] = {
                 "launches": stats[k]["launches"], "total_ms": stats[k]["total_ms"],
                 "bytes": stats[k]["bytes_per_launch"] * stats[k]["launches"], "flops": None}
     for name, v in P.build_stats().items():
@@ -257,7 +259,7 @@ def main():
                   "lanczos": last["lanczos_iters"], "stair_steps": last["stair_steps"]},
         "spmm_GBps": {k: (round(v, 1) if v else None) for k, v in spmm_gbs.items()},
         "spmm_launches": {k: stats[k]["launches"] for k in stats},
-        "spmm_kernel": {"f64": "upper", "f32": "upper", "bf16": "full"},
+        "spmm_kernel": {"f64 residual": "upper", "f64 curvature": "factored", "f32": "upper", "bf16": "full"},
         "roofline": roof,
         "kernels_ms": {k: round(v["total_ms"], 2) for k, v in kernels.items()},
     }

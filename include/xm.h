@@ -159,11 +159,35 @@ xm_status xm_spmm(xm_problem* p, xm_dtype dtype, const double* Y, int32_t r, dou
  *   XM_SPMM_UPPER  only Q[i][j], j >= i, is read (3N(3N+1)/2 elements), each
  *                  feeding both out[j] and out[i]: half the HBM bytes, with
  *                  twice the arithmetic per byte and a cross-lane reduction.
- * Both are deterministic; their results differ by rounding order only.
- * Defaults: XM_SPMM_UPPER for FP64 and FP32, XM_SPMM_FULL for BF16.
+ *   XM_SPMM_FACTORED (FP64 only)  Q is not read at all: Q Y^T is formed from
+ *                  the factors of its elimination, Q = A_rr - A_rt' G^{-1} A_rt'^T
+ *                  (App. A; A_rt' = A_rt without the anchored frame's column,
+ *                  G the grounded Laplacian), as A_rr Y^T (sparse 3x3 blocks
+ *                  on the co-visibility pattern) - A_rt' (G^{-1} (A_rt'^T Y^T))
+ *                  with the dense symmetric G^{-1} read through its upper
+ *                  triangle: (N-1)N/2 + 15 nnz(blocks) values per product
+ *                  instead of 3N(3N+1)/2.  The paper names sparse products as
+ *                  its future work.  The two terms cancel near the optimum
+ *                  (A_rr Y^T is up to ~30x larger than Q Y^T there), so the
+ *                  factored form carries that much more rounding: fine in FP64
+ *                  for products of directions, not for the residual at the
+ *                  iterate (an FP64 solve then stalls near 1e-7 relative
+ *                  gradient), and too coarse in FP32 (~1e-3 relative error on
+ *                  a 2000-frame loop), so FP32 and BF16 keep the dense forms.
+ * All are deterministic; their results differ by rounding order only.
  */
-typedef enum { XM_SPMM_FULL = 0, XM_SPMM_UPPER = 1 } xm_spmm_kind;
+typedef enum { XM_SPMM_FULL = 0, XM_SPMM_UPPER = 1, XM_SPMM_FACTORED = 2 } xm_spmm_kind;
+/* Products play two roles.  XM_ROLE_RESIDUAL: Y Q at the iterate itself
+ * (cost, gradient, multipliers, xm_spmm), whose entries cancel heavily near
+ * the optimum, so they need the most accurate form.  XM_ROLE_CURVATURE:
+ * products of directions (Hessian-vector products of truncated CG and of the
+ * adjoint, Lanczos steps of the certificate).  Defaults: residual products
+ * XM_SPMM_UPPER (FP64, FP32) / XM_SPMM_FULL (BF16); curvature products
+ * XM_SPMM_FACTORED for FP64, as the residual ones otherwise. */
+typedef enum { XM_ROLE_RESIDUAL = 0, XM_ROLE_CURVATURE = 1 } xm_product_role;
+/* xm_set_spmm_kind sets the kernel of both roles; xm_set_product_kind of one. */
 xm_status xm_set_spmm_kind(xm_problem* p, xm_dtype dtype, xm_spmm_kind kind);
+xm_status xm_set_product_kind(xm_problem* p, xm_product_role role, xm_dtype dtype, xm_spmm_kind kind);
 
 typedef struct {
   int32_t r0;          /* initial rank (>= 3); the staircase starts here */
@@ -323,17 +347,19 @@ xm_status xm_adjoint(xm_problem* p, const double* R, const double* s, const doub
  * local solver and of the Lanczos certificate).  With timing enabled, every
  * launch of the product kernel on a handle is bracketed by two HIP events on
  * the stream it runs on.  xm_spmm_stats synchronises those events and returns,
- * per stored precision (index = xm_dtype), the number of launches, their total
- * device time and the algorithmic bytes of one launch (averaged over the
- * recorded launches): the elements of Q the kernel must read (see
- * xm_set_spmm_kind) times the element size.  Only the main product kernel is
- * bracketed, not the pass that adds its partial sums.  reset != 0 forgets the
- * recorded launches.
+ * per product (index = xm_dtype for the dense kernels of each stored precision,
+ * 3 for the FP64 factored product), the number of launches, their total device
+ * time and the algorithmic bytes of one launch (averaged over the recorded
+ * launches): the values the product must read (see xm_set_spmm_kind) times
+ * their size.  For the dense kernels only the main product kernel is bracketed,
+ * not the pass that adds its partial sums; the factored product is bracketed
+ * whole (its three kernels).  reset != 0 forgets the recorded launches.
  */
+#define XM_STATS_FACTORED 3
 typedef struct {
-  int64_t launches[3];
-  double total_ms[3];
-  double bytes_per_launch[3];
+  int64_t launches[4];
+  double total_ms[4];
+  double bytes_per_launch[4];
 } xm_spmm_counters;
 xm_status xm_spmm_timing(xm_problem* p, int32_t enable);
 xm_status xm_spmm_stats(xm_problem* p, xm_spmm_counters* out, int32_t reset);

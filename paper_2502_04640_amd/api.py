@@ -69,8 +69,8 @@ class _AdjInfo(ctypes.Structure):
 
 
 class _SpmmStats(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 3), ("total_ms", ctypes.c_double * 3),
-                ("bytes_per_launch", ctypes.c_double * 3)]
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4),
+                ("bytes_per_launch", ctypes.c_double * 4)]
 
 
 def library_path() -> str:
@@ -114,6 +114,8 @@ def load_library() -> ctypes.CDLL:
     lib.xm_adjoint.restype = ctypes.c_int
     lib.xm_build_stats.argtypes = [P, ctypes.POINTER(_KernelStat), I32, ctypes.POINTER(ctypes.c_int32)]
     lib.xm_build_stats.restype = ctypes.c_int
+    lib.xm_set_product_kind.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.xm_set_product_kind.restype = ctypes.c_int
     lib.xm_set_spmm_kind.argtypes = [P, ctypes.c_int, ctypes.c_int]
     lib.xm_set_spmm_kind.restype = ctypes.c_int
     lib.xm_spmm_timing.argtypes = [P, I32]
@@ -218,11 +220,15 @@ class Problem:
         return {arr[k].name.decode(): {"launches": arr[k].launches, "total_ms": arr[k].total_ms,
                                        "bytes": arr[k].bytes, "flops": arr[k].flops} for k in range(min(n.value, 8))}
 
-    def set_spmm_kind(self, dtype: str, kind: str):
+    def set_spmm_kind(self, dtype: str, kind: str, role: str | None = None):
         """Product kernel for the stored Q of `dtype`: "upper" (reads the upper
-        triangle only) or "full" (reads all of Q)."""
-        k = {"full": 0, "upper": 1}[kind]
-        _check(load_library().xm_set_spmm_kind(self._h, _DT[dtype], k))
+        triangle only), "full" (reads all of Q) or, for "f64", "factored" (from
+        the elimination factors of Q, without reading Q)."""
+        k = {"full": 0, "upper": 1, "factored": 2}[kind]
+        if role is None:
+            _check(load_library().xm_set_spmm_kind(self._h, _DT[dtype], k))
+        else:
+            _check(load_library().xm_set_product_kind(self._h, {"residual": 0, "curvature": 1}[role], _DT[dtype], k))
 
     def spmm_timing(self, enable: bool = True):
         _check(load_library().xm_spmm_timing(self._h, int(enable)))
@@ -231,7 +237,7 @@ class Problem:
         st = _SpmmStats()
         _check(load_library().xm_spmm_stats(self._h, ctypes.byref(st), int(reset)))
         out = {}
-        for name, k in _DT.items():
+        for name, k in list(_DT.items()) + [("f64_factored", 3)]:
             out[name] = {"launches": st.launches[k], "total_ms": st.total_ms[k],
                          "bytes_per_launch": st.bytes_per_launch[k]}
         return out

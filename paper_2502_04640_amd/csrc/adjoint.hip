@@ -296,7 +296,7 @@ AdjointResult adjoint(xm_problem* p, const double* R, const double* s, const dou
     if (b2 > 0.0) {
       for (j = 1; j <= cg_max; ++j) {
         mf.ydot(3, Rt.ptr, sv.ptr, resR.ptr, ress.ptr, dR.ptr, ds.ptr, beta, mode, Ydot.ptr, st);
-        spmm_yt<double>(p, XM_F64, Ydot.ptr, 3, Gd.ptr, st);
+        spmm_yt<double>(p, XM_F64, Ydot.ptr, 3, Gd.ptr, st, XM_ROLE_CURVATURE);
         mf.hess(3, Rt.ptr, sv.ptr, G.ptr, Sc.ptr, ec.ptr, dR.ptr, ds.ptr, Gd.ptr, etaR.ptr, etas.ptr, HdR.ptr,
                 Hds.ptr, part.ptr, st, true);
         read_partials(part.ptr, nb, 4, sums, st);

@@ -184,13 +184,33 @@ xm_status xm_round(xm_problem* p, const double* Y, int32_t r, double* R_out, dou
   XM_API_CATCH
 }
 
-xm_status xm_set_spmm_kind(xm_problem* p, xm_dtype dtype, xm_spmm_kind kind) {
-  XM_API_TRY
+namespace {
+xm_status set_kind(xm_problem* p, int role, xm_dtype dtype, xm_spmm_kind kind) {
   if (!p) return fail(XM_EINVAL, "NULL argument");
   if (dtype < XM_F64 || dtype > XM_BF16) return fail(XM_EINVAL, "unknown dtype");
-  if (kind != XM_SPMM_FULL && kind != XM_SPMM_UPPER) return fail(XM_EINVAL, "unknown product kernel");
-  p->spmm_kind[dtype] = kind;
+  if (kind != XM_SPMM_FULL && kind != XM_SPMM_UPPER && kind != XM_SPMM_FACTORED)
+    return fail(XM_EINVAL, "unknown product kernel");
+  if (kind == XM_SPMM_FACTORED && dtype != XM_F64) return fail(XM_EINVAL, "the factored product is FP64 only");
+  if (role < 0) {
+    p->spmm_kind[XM_ROLE_RESIDUAL][dtype] = kind;
+    p->spmm_kind[XM_ROLE_CURVATURE][dtype] = kind;
+  } else {
+    p->spmm_kind[role][dtype] = kind;
+  }
   return XM_OK;
+}
+}  // namespace
+
+xm_status xm_set_spmm_kind(xm_problem* p, xm_dtype dtype, xm_spmm_kind kind) {
+  XM_API_TRY
+  return set_kind(p, -1, dtype, kind);
+  XM_API_CATCH
+}
+
+xm_status xm_set_product_kind(xm_problem* p, xm_product_role role, xm_dtype dtype, xm_spmm_kind kind) {
+  XM_API_TRY
+  if (role != XM_ROLE_RESIDUAL && role != XM_ROLE_CURVATURE) return fail(XM_EINVAL, "unknown product role");
+  return set_kind(p, role, dtype, kind);
   XM_API_CATCH
 }
 
@@ -215,7 +235,7 @@ xm_status xm_spmm_stats(xm_problem* p, xm_spmm_counters* out, int32_t reset) {
     out->total_ms[e.dtype] += ms;
     out->bytes_per_launch[e.dtype] += e.bytes;
   }
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < 4; ++d)
     if (out->launches[d] > 0) out->bytes_per_launch[d] /= static_cast<double>(out->launches[d]);
   if (reset) p->events_used = 0;
   return XM_OK;

@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kB) void reduce_blocks_kernel(
     const int64_t* __restrict__ seg_start, const uint32_t* __restrict__ seg_key, int64_t S, int32_t N,
     const uint64_t* __restrict__ vals, const double* __restrict__ u_s, const double* __restrict__ w_s,
     const int32_t* __restrict__ lm_s, const double* __restrict__ Wl, double* Q, int32_t ld,
-    double* Art, double* Att) {
+    double* Art, double* Att, double* Arr) {
   const int64_t s = static_cast<int64_t>(blockIdx.x) * (kB / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (s >= S) return;
@@ -180,16 +180,51 @@ __global__ __launch_bounds__(kB) void reduce_blocks_kernel(
   if (lane == 0) {
     const uint32_t key = seg_key[s];
     const int64_t i = key / static_cast<uint32_t>(N), j = key % static_cast<uint32_t>(N);
-    double* Qb = Q + (3 * i) * static_cast<int64_t>(ld) + 3 * j;
+    if (Q) {
+      double* Qb = Q + (3 * i) * static_cast<int64_t>(ld) + 3 * j;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Qb[a * static_cast<int64_t>(ld) + b] = acc[a * 4 + b];
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) Qb[a * static_cast<int64_t>(ld) + b] = acc[a * 4 + b];
+      for (int b = 0; b < 3; ++b) Arr[9 * s + 3 * a + b] = acc[a * 4 + b];
     Art[3 * s] = acc[3];
     Art[3 * s + 1] = acc[7];
     Art[3 * s + 2] = acc[11];
     Att[s] = acc[15];
   }
+}
+
+// ArtT[s] = Art[t] for the block s = (i, j) and its transpose t = (j, i)
+// (binary search of i in row j: columns are sorted within a row)
+__global__ void transpose_art_kernel(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                     const double* __restrict__ Art, int32_t N, int64_t S, double* ArtT,
+                                     int* flags) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (s >= S) return;
+  // row i of block s: the last row whose start is <= s
+  int lo = 0, hi = N - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (row_ptr[mid] <= s) lo = mid;
+    else hi = mid - 1;
+  }
+  const int i = lo, j = col[s];
+  int32_t a = row_ptr[j], b = row_ptr[j + 1] - 1;
+  while (a < b) {
+    const int32_t mid = (a + b) / 2;
+    if (col[mid] < i) a = mid + 1;
+    else b = mid;
+  }
+  if (a > b || col[a] != i) {  // the co-visibility pattern is symmetric: not reached
+    flags[5] = 1;
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ArtT[3 * s + c] = Art[3 * static_cast<int64_t>(a) + c];
 }
 
 __global__ void pattern_kernel(const uint32_t* __restrict__ seg_key, int64_t S, int32_t N,
@@ -235,75 +270,120 @@ __global__ void scatter_grounded_kernel(const int32_t* __restrict__ row_ptr, con
 // rank-64 product per tile on FP64 matrix cores.
 constexpr int kNB = 64;
 
-// -A_KK^{-1} by Gauss-Jordan pivoting in LDS; a last block with nb < 64 is
-// padded with dscale * I.  Dinv (nb x nb) = A_KK^{-1}.
+// -A_KK^{-1} by Gauss-Jordan pivoting; a last block with nb < 64 is padded
+// with dscale * I.  Dinv (nb x nb) = A_KK^{-1}.  Thread t keeps the 16 entries
+// (ibase + 4c, j) of the block in registers; only the pivot column and row go
+// through LDS, double-buffered so that one barrier per pivot suffices.
 __global__ __launch_bounds__(kB) void sweep_pivot_kernel(const double* __restrict__ A, int32_t lda,
                                                          int32_t k0, int32_t nb, double dscale,
                                                          double* Dinv, int* flags) {
-  __shared__ double D[kNB][kNB + 1];
+  __shared__ double colbuf[2][kNB], rowbuf[2][kNB];
   const int t = threadIdx.x;
   const int j = t & 63, ibase = t >> 6;  // thread owns column j of rows ibase + 4c
+  double d[kNB / 4];
+#pragma unroll
   for (int c = 0; c < kNB / 4; ++c) {
     const int i = ibase + 4 * c;
-    D[i][j] = (i < nb && j < nb) ? A[static_cast<int64_t>(k0 + i) * lda + k0 + j] : (i == j ? dscale : 0.0);
+    d[c] = (i < nb && j < nb) ? A[static_cast<int64_t>(k0 + i) * lda + k0 + j] : (i == j ? dscale : 0.0);
+  }
+  // pivot 0's column and row
+#pragma unroll
+  for (int c = 0; c < kNB / 4; ++c) {
+    const int i = ibase + 4 * c;
+    if (j == 0) colbuf[0][i] = d[c];
+    if (i == 0) rowbuf[0][j] = d[c];
   }
   __syncthreads();
   for (int p = 0; p < kNB; ++p) {
-    const double d = D[p][p];
-    if (!(d > 1e-11 * dscale)) {
+    const int par = p & 1;
+    const double piv = rowbuf[par][p];
+    if (!(piv > 1e-11 * dscale)) {
       if (t == 0) flags[4] = 1;
-      return;  // uniform across the block: every thread read the same d
+      return;  // uniform across the block: every thread read the same pivot
     }
-    const double inv = 1.0 / d;
-    const double dpj = D[p][j] * inv;
-    double upd[kNB / 4];
+    const double inv = 1.0 / piv;
+    const double rpj = rowbuf[par][j];  // old A[p][j]
 #pragma unroll
     for (int c = 0; c < kNB / 4; ++c) {
       const int i = ibase + 4 * c;
-      upd[c] = D[i][j] - D[i][p] * dpj;
+      const double cip = colbuf[par][i];  // old A[i][p]
+      if (i != p && j != p) d[c] -= cip * rpj * inv;
+      else if (i != p) d[c] = cip * inv;
+      else if (j != p) d[c] = rpj * inv;
+      else d[c] = -inv;
     }
-    __syncthreads();
-    if (j != p) {
+    if (p + 1 < kNB) {
 #pragma unroll
       for (int c = 0; c < kNB / 4; ++c) {
         const int i = ibase + 4 * c;
-        if (i != p) D[i][j] = upd[c];
+        if (j == p + 1) colbuf[par ^ 1][i] = d[c];
+        if (i == p + 1) rowbuf[par ^ 1][j] = d[c];
       }
     }
     __syncthreads();
-    if (t < kNB && t != p) {
-      D[t][p] *= inv;
-      D[p][t] *= inv;
-    }
-    if (t == 0) D[p][p] = -inv;
-    __syncthreads();
   }
+#pragma unroll
   for (int c = 0; c < kNB / 4; ++c) {
     const int i = ibase + 4 * c;
-    if (i < nb && j < nb) Dinv[i * nb + j] = -D[i][j];
+    if (i < nb && j < nb) Dinv[i * nb + j] = -d[c];
   }
-}
-
-// A[i][k0+p] through the upper triangle: column K for rows above it, row K otherwise
-__device__ __forceinline__ double panel_value(const double* __restrict__ A, int32_t lda, int32_t k0, int i, int p) {
-  return (i < k0) ? A[static_cast<int64_t>(i) * lda + k0 + p] : A[static_cast<int64_t>(k0 + p) * lda + i];
 }
 
 // Ct[q][i] = sum_p A[i][k0+p] Dinv[p][q] (0 for i in K); Pt[q][i] = A[i][k0+q].
+// One workgroup per 64 rows i: the 64 x 64 panel slice is staged in LDS with
+// coalesced loads (rows of A for i < k0, rows of A_K. for i >= k0, since only
+// the upper triangle is current), then multiplied by Dinv (4 x 4 outputs per
+// thread, indices strided by 16 so that LDS reads are conflict-free).
 __global__ __launch_bounds__(kB) void sweep_panel_kernel(const double* __restrict__ A, int32_t lda, int32_t n,
                                                          int32_t k0, int32_t nb, const double* __restrict__ Dinv,
                                                          double* Ct, double* Pt, int32_t ldt) {
-  __shared__ double Ds[kNB * kNB];
-  for (int e = threadIdx.x; e < nb * nb; e += kB) Ds[e] = Dinv[e];
+  __shared__ double T[64][65];   // T[r][p] = A[i0 + r][k0 + p]
+  __shared__ double Ds[64][65];  // Ds[p][q] = Dinv[p][q]
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.x * 64;
+  for (int e = t; e < 64 * 64; e += kB) {
+    const int p = e >> 6, q = e & 63;
+    Ds[p][q] = (p < nb && q < nb) ? Dinv[p * nb + q] : 0.0;
+  }
+  if (i0 < k0) {  // the whole tile lies above K (k0 and i0 are multiples of 64)
+    for (int e = t; e < 64 * 64; e += kB) {
+      const int r = e >> 6, p = e & 63;
+      T[r][p] = (i0 + r < n && p < nb) ? A[static_cast<int64_t>(i0 + r) * lda + k0 + p] : 0.0;
+    }
+  } else {
+    for (int e = t; e < 64 * 64; e += kB) {
+      const int p = e >> 6, r = e & 63;
+      T[r][p] = (i0 + r < n && p < nb) ? A[static_cast<int64_t>(k0 + p) * lda + i0 + r] : 0.0;
+    }
+  }
   __syncthreads();
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= n || q >= nb) return;
-  double acc = 0.0;
-  for (int p = 0; p < nb; ++p) acc += panel_value(A, lda, k0, i, p) * Ds[p * nb + q];
-  const bool inK = (i >= k0 && i < k0 + nb);
-  Ct[static_cast<int64_t>(q) * ldt + i] = inK ? 0.0 : acc;
-  Pt[static_cast<int64_t>(q) * ldt + i] = panel_value(A, lda, k0, i, q);
+  const int tx = t & 15, ty = t >> 4;
+  double acc[4][4] = {};
+  for (int p = 0; p < 64; ++p) {
+    double tv[4], dv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) tv[a] = T[ty + 16 * a][p];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dv[c] = Ds[p][tx + 16 * c];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] += tv[a] * dv[c];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = i0 + ty + 16 * a;
+    const bool inK = (i >= k0 && i < k0 + nb);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int q = tx + 16 * c;
+      if (i < n && q < nb) Ct[static_cast<int64_t>(q) * ldt + i] = inK ? 0.0 : acc[a][c];
+    }
+  }
+  for (int e = t; e < 64 * 64; e += kB) {
+    const int q = e >> 6, r = e & 63;
+    if (i0 + r < n && q < nb) Pt[static_cast<int64_t>(q) * ldt + i0 + r] = T[r][q];
+  }
 }
 
 // A[i][j] -= sum_p Ct[p][i] Pt[p][j] on the 64 x 64 tiles J >= I.  Each wave
@@ -743,9 +823,10 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   XM_HIP(hipMemsetAsync(P->Q64.ptr, 0, qn * sizeof(double), s));
   P->Art.alloc(3 * S);
   P->Att.alloc(S);
+  P->Arr.alloc(9 * S);
   hipLaunchKernelGGL(reduce_blocks_kernel, dim3(cdiv(S, kB / 64)), dim3(kB), 0, s, seg_start.ptr, seg_key.ptr,
                      S, N, pvals.ptr, P->u_s.ptr, P->w_s.ptr, P->lm_s.ptr, P->Wl.ptr, P->Q64.ptr, P->ld,
-                     P->Art.ptr, P->Att.ptr);
+                     P->Art.ptr, P->Att.ptr, P->Arr.ptr);
   XM_LAUNCH_CHECK("reduce_blocks_kernel");
   P->row_ptr.alloc(N + 1);
   P->col.alloc(S);
@@ -755,10 +836,15 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   hipLaunchKernelGGL(check_diag_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, P->row_ptr.ptr, P->col.ptr,
                      P->Att.ptr, N, flags.ptr);
   XM_LAUNCH_CHECK("check_diag_kernel");
+  P->ArtT.alloc(3 * S);
+  hipLaunchKernelGGL(transpose_art_kernel, dim3(cdiv(S, kB)), dim3(kB), 0, s, P->row_ptr.ptr, P->col.ptr,
+                     P->Art.ptr, N, S, P->ArtT.ptr, flags.ptr);
+  XM_LAUNCH_CHECK("transpose_art_kernel");
   XM_HIP(hipMemcpyAsync(hflags, flags.ptr, sizeof(hflags), hipMemcpyDeviceToHost, s));
   XM_HIP(hipStreamSynchronize(s));
   pkeys.release(); pvals.release(); seg_start.release(); seg_key.release();
   require(!hflags[3], XM_EGRAPH, "a frame has no observation shared with another frame");
+  require(!hflags[5], XM_EINVAL, "internal: co-visibility pattern is not symmetric");
 
   // a2-ii: translations.  G = A_tt[1:,1:] (dense), swept to -G^{-1}.
   const int32_t ng = N - 1;
@@ -788,8 +874,8 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
       hipLaunchKernelGGL(sweep_pivot_kernel, dim3(1), dim3(kB), 0, s, P->Gm.ptr, P->ldg, k0, nb, dscale,
                          Dinv.ptr, flags.ptr);
       XM_LAUNCH_CHECK("sweep_pivot_kernel");
-      hipLaunchKernelGGL(sweep_panel_kernel, dim3(cdiv(ng, 64), cdiv(nb, 4)), dim3(kB), 0, s, P->Gm.ptr, P->ldg,
-                         ng, k0, nb, Dinv.ptr, Ct.ptr, Pt.ptr, P->ldg);
+      hipLaunchKernelGGL(sweep_panel_kernel, dim3(cdiv(ng, 64)), dim3(kB), 0, s, P->Gm.ptr, P->ldg, ng, k0, nb,
+                         Dinv.ptr, Ct.ptr, Pt.ptr, P->ldg);
       XM_LAUNCH_CHECK("sweep_panel_kernel");
       t_sweep.start(s);
       hipLaunchKernelGGL(sweep_update_kernel, dim3(tiles, tiles), dim3(kB), 0, s, P->Gm.ptr, P->ldg, ng, Ct.ptr,

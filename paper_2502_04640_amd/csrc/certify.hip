@@ -343,7 +343,7 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
     const double* x = V.ptr + static_cast<int64_t>(nb + j) * n;
     hipLaunchKernelGGL(blockmul_kernel, dim3(gb), dim3(kB), 0, s, N, p->Dmhalf.ptr, x, yv.ptr);
     XM_LAUNCH_CHECK("blockmul_kernel");
-    spmm_yt<double>(p, XM_F64, yv.ptr, 1, Qx.ptr, s);
+    spmm_yt<double>(p, XM_F64, yv.ptr, 1, Qx.ptr, s, XM_ROLE_CURVATURE);
     hipLaunchKernelGGL(zapply_scaled_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, N, Lam.ptr, p->Dmhalf.ptr, yv.ptr,
                        Qx.ptr, w.ptr);
     XM_LAUNCH_CHECK("zapply_scaled_kernel");

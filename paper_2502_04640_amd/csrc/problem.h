@@ -36,6 +36,9 @@ struct xm_problem {
   // co-visibility pattern (rows = frames), with the eliminated-landmark blocks
   xm::DevBuf<int32_t> row_ptr, col;  // [N+1], [nnzb]
   xm::DevBuf<double> Art;            // [nnzb][3]: A_rt[3i+a][j]
+  xm::DevBuf<double> ArtT;           // [nnzb][3]: A_rt[3j+a][i] (the transposed block's entry)
+  xm::DevBuf<double> Arr;            // [nnzb][9]: A_rr[3i+a][3j+b], row-major 3x3
+  xm::DevBuf<double> fact_scratch;   // W and V of the factored product
   xm::DevBuf<double> Att;            // [nnzb]:    A_tt[i][j]
   // -(A_tt[1:,1:])^{-1}, row-major [N-1][ldg]
   xm::DevBuf<double> Gm;
@@ -57,8 +60,9 @@ struct xm_problem {
     int dtype;
     double bytes;  // algorithmic bytes of Q the launch reads
   };
-  // product kernel per Q precision (xm_spmm_kind, indexed by xm_dtype)
-  int spmm_kind[3] = {XM_SPMM_UPPER, XM_SPMM_UPPER, XM_SPMM_FULL};
+  // product kernel per role (xm_product_role) and Q precision (xm_dtype)
+  int spmm_kind[2][3] = {{XM_SPMM_UPPER, XM_SPMM_UPPER, XM_SPMM_FULL},
+                         {XM_SPMM_FACTORED, XM_SPMM_UPPER, XM_SPMM_FULL}};
   bool timing = false;
   std::vector<TimedLaunch> events;
   size_t events_used = 0;
@@ -76,8 +80,11 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
 
 // spmm.hip: out (3N x r, row-major, frame-major "Yt" layout, ld = r) = Q * Yt.
 // Yt is [3N][r] (row i holds Y[0..r)[i]).  T is the vector precision.
+// role: XM_ROLE_RESIDUAL (gradient, cost, multipliers: accuracy at the optimum)
+// or XM_ROLE_CURVATURE (Hessian-vector and Lanczos products of directions).
 template <typename T>
-void spmm_yt(const xm_problem* p, xm_dtype qtype, const T* Yt, int r, T* out, hipStream_t s);
+void spmm_yt(const xm_problem* p, xm_dtype qtype, const T* Yt, int r, T* out, hipStream_t s,
+             int role = XM_ROLE_RESIDUAL);
 
 // layout conversions between the ABI layout Y[r][3N] and the internal Yt[3N][r]
 template <typename Ts, typename Td>

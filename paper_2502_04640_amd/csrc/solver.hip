@@ -172,7 +172,7 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
     int j = 0;
     for (j = 1; j <= max_inner; ++j) {
       mf.ydot(r, V.Rt.ptr, V.s.ptr, V.resR.ptr, V.ress.ptr, V.dR.ptr, V.ds.ptr, beta, mode, V.Ydot.ptr, st);
-      spmm_yt<T>(p, qh, V.Ydot.ptr, r, V.Gd.ptr, st);
+      spmm_yt<T>(p, qh, V.Ydot.ptr, r, V.Gd.ptr, st, XM_ROLE_CURVATURE);
       ++out.spmm;
       mf.hess(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.Sc.ptr, V.ec.ptr, V.dR.ptr, V.ds.ptr, V.Gd.ptr, V.etaR.ptr,
               V.etas.ptr, V.HdR.ptr, V.Hds.ptr, V.part.ptr, st);

@@ -32,6 +32,18 @@ constexpr int kB = 256;
 constexpr int kMaxRows = XM_SPMM_MAXROWS;
 constexpr int kTargetBlocks = XM_SPMM_TARGET;
 
+// Q is streamed once per product.  FP64 Q is read with non-temporal loads
+// (measured 7 % faster for the r = 1 product of the certificate); for FP32 Q
+// they raise the register count of the r = 5 product past 3 waves per SIMD and
+// lose, so FP32 keeps ordinary loads.
+template <typename E, int K>
+__device__ __forceinline__ void load_nt(const E* p, E (&out)[K]) {
+  typedef E vec __attribute__((ext_vector_type(K)));
+  const vec v = __builtin_nontemporal_load(reinterpret_cast<const vec*>(p));
+#pragma unroll
+  for (int k = 0; k < K; ++k) out[k] = v[k];
+}
+
 template <typename TQ>
 struct QVec;
 template <>
@@ -40,8 +52,9 @@ struct QVec<double> {
   static constexpr int dtype = XM_F64;
   template <typename TA>
   __device__ static void load(const double* p, TA* out) {
-    const double2 v = *reinterpret_cast<const double2*>(p);
-    out[0] = v.x; out[1] = v.y;
+    double v[2];
+    load_nt<double, 2>(p, v);
+    out[0] = v[0]; out[1] = v[1];
   }
 };
 template <>
@@ -129,7 +142,12 @@ __global__ __launch_bounds__(kB) void spmm_split_kernel(const TQ* __restrict__ Q
 #endif
 constexpr int kSymRows = XM_SYM_ROWS;  // RS
 constexpr bool kSymPerm = XM_SYM_PERM;  // lane-permuted slots (else selects in the butterfly)
-constexpr int kSymBatch = 8;           // rows per butterfly batch (fixed by the 3 halving steps)
+#ifndef XM_SYM_BATCH
+#define XM_SYM_BATCH 8
+#endif
+constexpr int kSymBatch = XM_SYM_BATCH;  // rows per butterfly batch: 8 (3 halving steps) or 4 (2)
+static_assert(kSymBatch == 8 || (kSymBatch == 4 && XM_SYM_PERM), "batch of 4 rows needs the lane permutation");
+constexpr int kSymShift = (kSymBatch == 8) ? 3 : 4;  // lane >> kSymShift selects the row of a lane
 
 // Without the lane permutation the row of every slot is the same for the whole
 // wave, so the Yt values of the batch can come from uniform (scalar) loads.
@@ -205,7 +223,7 @@ __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __re
   for (int e = threadIdx.x; e < RS * R; e += kB)
     ys[e] = (e < nrows * R) ? static_cast<TA>(Yt[static_cast<int64_t>(i0) * R + e]) : TA(0);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int pi = kSymPerm ? (lane >> 3) & 7 : 0;
+  const int pi = kSymPerm ? (lane >> kSymShift) & (kSymBatch - 1) : 0;
   const int j = j0 + threadIdx.x * V;
   TA xc[V][R];
 #pragma unroll
@@ -236,9 +254,14 @@ __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __re
     for (int a = 0; a < R; ++a) {
       TA t4[4], t2[2];
       TA t1;
-      if (kSymPerm) {
+      if (kSymBatch == 4) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) t4[k] = p[k][a] + __shfl_xor(p[k + 4][a], 32);
+        for (int k = 0; k < 2; ++k) t2[k] = p[k][a] + __shfl_xor(p[(k + 2) % kSymBatch][a], 32);
+        t1 = t2[0] + __shfl_xor(t2[1], 16);
+        t1 += __shfl_xor(t1, 8);
+      } else if (kSymPerm) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t4[k] = p[k][a] + __shfl_xor(p[(k + 4) % kSymBatch][a], 32);
 #pragma unroll
         for (int k = 0; k < 2; ++k) t2[k] = t4[k] + __shfl_xor(t4[k + 2], 16);
         t1 = t2[0] + __shfl_xor(t2[1], 8);
@@ -246,7 +269,8 @@ __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __re
         const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          t4[k] = (h32 ? p[k + 4][a] : p[k][a]) + __shfl_xor(h32 ? p[k][a] : p[k + 4][a], 32);
+          t4[k] = (h32 ? p[(k + 4) % kSymBatch][a] : p[k][a]) +
+                  __shfl_xor(h32 ? p[k][a] : p[(k + 4) % kSymBatch][a], 32);
 #pragma unroll
         for (int k = 0; k < 2; ++k) t2[k] = (h16 ? t4[k + 2] : t4[k]) + __shfl_xor(h16 ? t4[k] : t4[k + 2], 16);
         t1 = (h8 ? t2[1] : t2[0]) + __shfl_xor(h8 ? t2[0] : t2[1], 8);
@@ -254,8 +278,8 @@ __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __re
       t1 += __shfl_xor(t1, 4);
       t1 += __shfl_xor(t1, 2);
       t1 += __shfl_xor(t1, 1);
-      if ((lane & 7) == 0) {
-        const int row = ib + ((lane >> 3) & 7);
+      if ((lane & ((1 << kSymShift) - 1)) == 0) {
+        const int row = ib + ((lane >> kSymShift) & (kSymBatch - 1));
         if (row < nrows) rp[wave][row * R + a] = t1;
       }
     }
@@ -373,14 +397,16 @@ void launch(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStream_t
   XM_LAUNCH_CHECK("spmm_reduce_kernel");
 }
 
+// out (n x R) = M Yt for a symmetric n x n matrix M (row-major, leading
+// dimension ld, zero padding columns) read through its upper triangle.
 template <typename TQ, typename TV, typename TA, int R>
-void launch_sym(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStream_t s) {
+void sym_product(const TQ* M, int32_t ld, int32_t n, const TV* Yt, TV* out, DevBuf<char>& scratch,
+                 xm_problem::TimedLaunch* ev, hipStream_t s) {
   constexpr int V = QVec<TQ>::V;
   constexpr int C = kB * V;
-  const int nchunks = static_cast<int>(cdiv(p->ld, C));
-  const int nslabs = static_cast<int>(cdiv(p->n3, kSymRows));
-  auto& scratch = const_cast<xm_problem*>(p)->spmm_scratch;
-  const size_t per = static_cast<size_t>(p->n3) * R;
+  const int nchunks = static_cast<int>(cdiv(ld, C));
+  const int nslabs = static_cast<int>(cdiv(n, kSymRows));
+  const size_t per = static_cast<size_t>(n) * R;
   const size_t need = (static_cast<size_t>(nslabs) + nchunks) * per * sizeof(TA);
   if (scratch.n < need) {
     XM_HIP(hipStreamSynchronize(s));
@@ -388,32 +414,169 @@ void launch_sym(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStre
   }
   TA* colpart = reinterpret_cast<TA*>(scratch.ptr);
   TA* rowpart = colpart + static_cast<size_t>(nslabs) * per;
-  xm_problem::TimedLaunch* ev = nullptr;
-  if (p->timing) {
-    auto* mp = const_cast<xm_problem*>(p);
-    if (mp->events_used == mp->events.size()) {
-      xm_problem::TimedLaunch t{};
-      XM_HIP(hipEventCreate(&t.start));
-      XM_HIP(hipEventCreate(&t.stop));
-      mp->events.push_back(t);
-    }
-    ev = &mp->events[mp->events_used++];
-    ev->dtype = QVec<TQ>::dtype;
-    ev->bytes = 0.5 * static_cast<double>(p->n3) * (p->n3 + 1) * sizeof(TQ);
-    XM_HIP(hipEventRecord(ev->start, s));
-  }
-  hipLaunchKernelGGL((spmm_sym_kernel<TQ, TV, TA, R>), dim3(nchunks, nslabs), dim3(kB), 0, s, Q, p->ld, p->n3, Yt,
+  if (ev) XM_HIP(hipEventRecord(ev->start, s));
+  hipLaunchKernelGGL((spmm_sym_kernel<TQ, TV, TA, R>), dim3(nchunks, nslabs), dim3(kB), 0, s, M, ld, n, Yt,
                      colpart, rowpart);
   XM_LAUNCH_CHECK("spmm_sym_kernel");
   if (ev) XM_HIP(hipEventRecord(ev->stop, s));
   hipLaunchKernelGGL((spmm_sym_reduce_kernel<TA, TV, R, C>), dim3(cdiv(per, 64)), dim3(kB), 0, s, colpart, rowpart,
-                     p->n3, nchunks, out);
+                     n, nchunks, out);
   XM_LAUNCH_CHECK("spmm_sym_reduce_kernel");
 }
 
+xm_problem::TimedLaunch* timed_launch(const xm_problem* p, int dtype, double bytes) {
+  if (!p->timing) return nullptr;
+  auto* mp = const_cast<xm_problem*>(p);
+  if (mp->events_used == mp->events.size()) {
+    xm_problem::TimedLaunch t{};
+    XM_HIP(hipEventCreate(&t.start));
+    XM_HIP(hipEventCreate(&t.stop));
+    mp->events.push_back(t);
+  }
+  xm_problem::TimedLaunch* ev = &mp->events[mp->events_used++];
+  ev->dtype = dtype;
+  ev->bytes = bytes;
+  return ev;
+}
+
+template <typename TQ, typename TV, typename TA, int R>
+void launch_sym(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStream_t s) {
+  xm_problem::TimedLaunch* ev =
+      timed_launch(p, QVec<TQ>::dtype, 0.5 * static_cast<double>(p->n3) * (p->n3 + 1) * sizeof(TQ));
+  sym_product<TQ, TV, TA, R>(Q, p->ld, p->n3, Yt, out, const_cast<xm_problem*>(p)->spmm_scratch, ev, s);
+}
+
+// ---- factored product (FP64): Q = A_rr + B Gm B^T, Gm = -G^{-1} -------------
+// B = A_rt without the column of the anchored frame 0, G the grounded
+// Laplacian (Prop. "Scaled-Rotation-Only Formulation", App. A).  Q Yt is formed
+// without Q: W = B^T Yt (sparse, per frame), V = Gm W (the symmetric dense
+// product above on the (N-1)^2 matrix), out = A_rr Yt + B V (sparse, per
+// frame).  One wavefront per frame for the sparse parts, lanes over the frame's
+// co-visible frames, fixed-order wave sums: deterministic.
+
+// W[j-1][a] = sum_{s in row j} sum_c ArtT[s][c] Yt[3 col[s] + c][a], j >= 1
+template <int R>
+__global__ __launch_bounds__(kB) void fact_bt_kernel(int32_t N, const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ ArtT,
+                                                     const double* __restrict__ Yt, double* __restrict__ W) {
+  const int j = blockIdx.x * (kB / 64) + (threadIdx.x >> 6) + 1;
+  const int lane = threadIdx.x & 63;
+  if (j >= N) return;  // whole wavefronts only
+  double acc[R];
+#pragma unroll
+  for (int a = 0; a < R; ++a) acc[a] = 0.0;
+  for (int32_t s = row_ptr[j] + lane; s < row_ptr[j + 1]; s += 64) {
+    const int64_t i3 = 3 * static_cast<int64_t>(col[s]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double b = ArtT[3 * static_cast<int64_t>(s) + c];
+      const double* y = Yt + (i3 + c) * R;
+#pragma unroll
+      for (int a = 0; a < R; ++a) acc[a] += b * y[a];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < R; ++a) acc[a] = wave_sum(acc[a]);
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < R; ++a) W[static_cast<int64_t>(j - 1) * R + a] = acc[a];
+  }
+}
+
+// out[3i+c][a] = sum_{s in row i} (sum_d Arr[s][c][d] Yt[3 col[s] + d][a] + Art[s][c] V[col[s]-1][a])
+template <int R>
+__global__ __launch_bounds__(kB) void fact_out_kernel(int32_t N, const int32_t* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ Arr,
+                                                      const double* __restrict__ Art,
+                                                      const double* __restrict__ Yt,
+                                                      const double* __restrict__ V, double* __restrict__ out) {
+  const int i = blockIdx.x * (kB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= N) return;  // whole wavefronts only
+  double acc[3][R];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < R; ++a) acc[c][a] = 0.0;
+  for (int32_t s = row_ptr[i] + lane; s < row_ptr[i + 1]; s += 64) {
+    const int j = col[s];
+    const double* y = Yt + 3 * static_cast<int64_t>(j) * R;
+    const double* m = Arr + 9 * static_cast<int64_t>(s);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        const double yv = y[d * R + a];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c][a] += m[3 * c + d] * yv;
+      }
+    if (j > 0) {
+      const double* v = V + static_cast<int64_t>(j - 1) * R;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double b = Art[3 * static_cast<int64_t>(s) + c];
+#pragma unroll
+        for (int a = 0; a < R; ++a) acc[c][a] += b * v[a];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < R; ++a) acc[c][a] = wave_sum(acc[c][a]);
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int a = 0; a < R; ++a) out[(3 * static_cast<int64_t>(i) + c) * R + a] = acc[c][a];
+  }
+}
+
+template <int R>
+void launch_factored(const xm_problem* p, const double* Yt, double* out, hipStream_t s) {
+  auto* mp = const_cast<xm_problem*>(p);
+  const int32_t N = p->N, ng = N - 1;
+  const size_t per = static_cast<size_t>(ng) * R;
+  if (mp->fact_scratch.n < 2 * per) {
+    XM_HIP(hipStreamSynchronize(s));
+    mp->fact_scratch.alloc(2 * 8 * static_cast<size_t>(ng));
+  }
+  double* W = mp->fact_scratch.ptr;
+  double* Vv = W + per;
+  const double S = static_cast<double>(p->nnzb);
+  xm_problem::TimedLaunch* ev =
+      timed_launch(p, XM_STATS_FACTORED, 0.5 * static_cast<double>(ng) * (ng + 1) * 8.0 + S * 15.0 * 8.0);
+  if (ev) XM_HIP(hipEventRecord(ev->start, s));
+  const unsigned gb = cdiv(N, kB / 64);
+  hipLaunchKernelGGL((fact_bt_kernel<R>), dim3(gb), dim3(kB), 0, s, N, p->row_ptr.ptr, p->col.ptr, p->ArtT.ptr,
+                     Yt, W);
+  XM_LAUNCH_CHECK("fact_bt_kernel");
+  sym_product<double, double, double, R>(p->Gm.ptr, p->ldg, ng, W, Vv, mp->spmm_scratch, nullptr, s);
+  hipLaunchKernelGGL((fact_out_kernel<R>), dim3(gb), dim3(kB), 0, s, N, p->row_ptr.ptr, p->col.ptr, p->Arr.ptr,
+                     p->Art.ptr, Yt, Vv, out);
+  XM_LAUNCH_CHECK("fact_out_kernel");
+  if (ev) XM_HIP(hipEventRecord(ev->stop, s));
+}
+
+void dispatch_factored(const xm_problem* p, const double* Yt, int r, double* out, hipStream_t s) {
+  switch (r) {
+    case 1: launch_factored<1>(p, Yt, out, s); return;
+    case 2: launch_factored<2>(p, Yt, out, s); return;
+    case 3: launch_factored<3>(p, Yt, out, s); return;
+    case 4: launch_factored<4>(p, Yt, out, s); return;
+    case 5: launch_factored<5>(p, Yt, out, s); return;
+    case 6: launch_factored<6>(p, Yt, out, s); return;
+    case 7: launch_factored<7>(p, Yt, out, s); return;
+    case 8: launch_factored<8>(p, Yt, out, s); return;
+    default: throw Error(XM_EINVAL, "rank must be in [1, 8]");
+  }
+}
+
 template <typename TQ, typename TV, typename TA>
-void dispatch_r(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, hipStream_t s) {
-  if (p->spmm_kind[QVec<TQ>::dtype] == XM_SPMM_UPPER) {
+void dispatch_r(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, hipStream_t s, int role) {
+  if (p->spmm_kind[role][QVec<TQ>::dtype] == XM_SPMM_UPPER) {
     switch (r) {
       case 1: launch_sym<TQ, TV, TA, 1>(p, Q, Yt, out, s); return;
       case 2: launch_sym<TQ, TV, TA, 2>(p, Q, Yt, out, s); return;
@@ -442,19 +605,28 @@ void dispatch_r(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, 
 }  // namespace
 
 template <>
-void spmm_yt<double>(const xm_problem* p, xm_dtype qtype, const double* Yt, int r, double* out, hipStream_t s) {
+void spmm_yt<double>(const xm_problem* p, xm_dtype qtype, const double* Yt, int r, double* out, hipStream_t s,
+                     int role) {
   require(qtype == XM_F64, XM_EINVAL, "FP64 vectors are multiplied with the FP64 Q");
-  dispatch_r<double, double, double>(p, p->Q64.ptr, Yt, r, out, s);
+  require(role == XM_ROLE_RESIDUAL || role == XM_ROLE_CURVATURE, XM_EINVAL, "unknown product role");
+  if (p->spmm_kind[role][XM_F64] == XM_SPMM_FACTORED) {
+    dispatch_factored(p, Yt, r, out, s);
+    return;
+  }
+  require(p->Q64.ptr != nullptr, XM_EINVAL, "the dense FP64 Q was not kept");
+  dispatch_r<double, double, double>(p, p->Q64.ptr, Yt, r, out, s, role);
 }
 
 template <>
-void spmm_yt<float>(const xm_problem* p, xm_dtype qtype, const float* Yt, int r, float* out, hipStream_t s) {
+void spmm_yt<float>(const xm_problem* p, xm_dtype qtype, const float* Yt, int r, float* out, hipStream_t s,
+                    int role) {
+  require(role == XM_ROLE_RESIDUAL || role == XM_ROLE_CURVATURE, XM_EINVAL, "unknown product role");
   if (qtype == XM_F32) {
     require(p->Q32.ptr != nullptr, XM_EINVAL, "the FP32 copy of Q was not kept (XM_KEEP_F32)");
-    dispatch_r<float, float, float>(p, p->Q32.ptr, Yt, r, out, s);
+    dispatch_r<float, float, float>(p, p->Q32.ptr, Yt, r, out, s, role);
   } else if (qtype == XM_BF16) {
     require(p->Q16.ptr != nullptr, XM_EINVAL, "the BF16 copy of Q was not kept (XM_KEEP_BF16)");
-    dispatch_r<uint16_t, float, float>(p, p->Q16.ptr, Yt, r, out, s);
+    dispatch_r<uint16_t, float, float>(p, p->Q16.ptr, Yt, r, out, s, role);
   } else {
     throw Error(XM_EINVAL, "FP32 vectors are multiplied with the FP32 or BF16 Q");
   }

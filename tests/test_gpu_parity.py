@@ -154,9 +154,11 @@ def tiled_problem():
     return sc, _oracle_Q(sc)
 
 
-@pytest.mark.parametrize("kind", ["upper", "full"])
+@pytest.mark.parametrize("kind", ["upper", "full", "factored"])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_spmm_kernels_across_tiles(tiled_problem, kind, dtype):
+    if kind == "factored" and dtype != "f64":
+        pytest.skip("the factored product is FP64 only")
     _say(f"case: spmm {kind} {dtype} 3N=2100")
     sc, Qo = tiled_problem
     P = _build(sc, keep=("f32", "bf16"))
