@@ -200,7 +200,9 @@ def main():
     # the Y Q products (per stored precision) and the main assembly kernels
     kernels = {}
     names = {"f64": "spmm_sym_kernel (f64 Q)", "f32": "spmm_sym_kernel (f32 Q)",
-             "bf16": "spmm_split_kernel (bf16 Q)", "f64_factored": "factored product (f64: sparse A_rr, A_rt; dense G^-1)"}
+             "bf16": "spmm_split_kernel (bf16 Q)",
+             "f64_factored": "factored product (f64: sparse A_rr, A_rt; dense G^-1)",
+             "f32_factored": "factored product (f32: sparse A_rr, A_rt; dense G^-1)"}
     for k in stats:
         if stats[k]["launches"]:
             kernels[names[k]] = {
@@ -216,7 +218,7 @@ def main():
     gbs = bytes_l / (avg_ms * 1e-3) / 1e9
     tfs = flops_l / (avg_ms * 1e-3) / 1e12
     if flops_l and tfs / FP64_PEAK_TFS > gbs / HBM_PEAK_GBS:
-        roof = {"bound": "alu" if dom_name.startswith("gather") else "mfma", "achieved": round(tfs, 2),
+        roof = {"bound": "alu" if dom_name.startswith("group") else "mfma", "achieved": round(tfs, 2),
                 "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": round(tfs / FP64_PEAK_TFS, 4)}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -259,7 +261,7 @@ def main():
                   "lanczos": last["lanczos_iters"], "stair_steps": last["stair_steps"]},
         "spmm_GBps": {k: (round(v, 1) if v else None) for k, v in spmm_gbs.items()},
         "spmm_launches": {k: stats[k]["launches"] for k in stats},
-        "spmm_kernel": {"f64 residual": "upper", "f64 curvature": "factored", "f32": "upper", "bf16": "full"},
+        "spmm_kernel": {f"{d} {role}": P.spmm_kind(d, role) for d in ("f64", "f32") for role in ("residual", "curvature")},
         "roofline": roof,
         "kernels_ms": {k: round(v["total_ms"], 2) for k, v in kernels.items()},
     }

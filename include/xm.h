@@ -159,7 +159,7 @@ xm_status xm_spmm(xm_problem* p, xm_dtype dtype, const double* Y, int32_t r, dou
  *   XM_SPMM_UPPER  only Q[i][j], j >= i, is read (3N(3N+1)/2 elements), each
  *                  feeding both out[j] and out[i]: half the HBM bytes, with
  *                  twice the arithmetic per byte and a cross-lane reduction.
- *   XM_SPMM_FACTORED (FP64 only)  Q is not read at all: Q Y^T is formed from
+ *   XM_SPMM_FACTORED (FP64, FP32)  Q is not read at all: Q Y^T is formed from
  *                  the factors of its elimination, Q = A_rr - A_rt' G^{-1} A_rt'^T
  *                  (App. A; A_rt' = A_rt without the anchored frame's column,
  *                  G the grounded Laplacian), as A_rr Y^T (sparse 3x3 blocks
@@ -172,8 +172,11 @@ xm_status xm_spmm(xm_problem* p, xm_dtype dtype, const double* Y, int32_t r, dou
  *                  factored form carries that much more rounding: fine in FP64
  *                  for products of directions, not for the residual at the
  *                  iterate (an FP64 solve then stalls near 1e-7 relative
- *                  gradient), and too coarse in FP32 (~1e-3 relative error on
- *                  a 2000-frame loop), so FP32 and BF16 keep the dense forms.
+ *                  gradient).  FP32 (needs XM_KEEP_F32, which also keeps FP32
+ *                  factors) reaches ~1e-3 relative error on a 2000-frame loop:
+ *                  too coarse for residuals, usable for the curvature of a
+ *                  trust-region model, whose steps are accepted on the
+ *                  residual-role cost.  No BF16 form.
  * All are deterministic; their results differ by rounding order only.
  */
 typedef enum { XM_SPMM_FULL = 0, XM_SPMM_UPPER = 1, XM_SPMM_FACTORED = 2 } xm_spmm_kind;
@@ -183,11 +186,18 @@ typedef enum { XM_SPMM_FULL = 0, XM_SPMM_UPPER = 1, XM_SPMM_FACTORED = 2 } xm_sp
  * products of directions (Hessian-vector products of truncated CG and of the
  * adjoint, Lanczos steps of the certificate).  Defaults: residual products
  * XM_SPMM_UPPER (FP64, FP32) / XM_SPMM_FULL (BF16); curvature products
- * XM_SPMM_FACTORED for FP64, as the residual ones otherwise. */
+ * XM_SPMM_FACTORED for FP64; for FP32, XM_SPMM_FACTORED once the stored
+ * upper triangle of the FP32 Q (3N(3N+1)/2 values) exceeds 256 MiB, the
+ * GPU's last-level cache, below which the dense read stays cache-resident
+ * across products and XM_SPMM_UPPER is the default; BF16 as its residual. */
 typedef enum { XM_ROLE_RESIDUAL = 0, XM_ROLE_CURVATURE = 1 } xm_product_role;
-/* xm_set_spmm_kind sets the kernel of both roles; xm_set_product_kind of one. */
+/* xm_set_spmm_kind sets the kernel of both roles; xm_set_product_kind of one;
+ * xm_get_product_kind reads the kernel in use (the defaults above are set by
+ * xm_build_Q).  XM_EINVAL for an unknown role, dtype or kernel, a NULL
+ * argument, or a BF16 factored product. */
 xm_status xm_set_spmm_kind(xm_problem* p, xm_dtype dtype, xm_spmm_kind kind);
 xm_status xm_set_product_kind(xm_problem* p, xm_product_role role, xm_dtype dtype, xm_spmm_kind kind);
+xm_status xm_get_product_kind(const xm_problem* p, xm_product_role role, xm_dtype dtype, xm_spmm_kind* kind);
 
 typedef struct {
   int32_t r0;          /* initial rank (>= 3); the staircase starts here */
@@ -348,18 +358,18 @@ xm_status xm_adjoint(xm_problem* p, const double* R, const double* s, const doub
  * launch of the product kernel on a handle is bracketed by two HIP events on
  * the stream it runs on.  xm_spmm_stats synchronises those events and returns,
  * per product (index = xm_dtype for the dense kernels of each stored precision,
- * 3 for the FP64 factored product), the number of launches, their total device
+ * 3 and 4 for the FP64 and FP32 factored products), the number of launches, their total device
  * time and the algorithmic bytes of one launch (averaged over the recorded
  * launches): the values the product must read (see xm_set_spmm_kind) times
  * their size.  For the dense kernels only the main product kernel is bracketed,
  * not the pass that adds its partial sums; the factored product is bracketed
  * whole (its three kernels).  reset != 0 forgets the recorded launches.
  */
-#define XM_STATS_FACTORED 3
+#define XM_STATS_FACTORED 3   /* FP64 factored product; 4: its FP32 form */
 typedef struct {
-  int64_t launches[4];
-  double total_ms[4];
-  double bytes_per_launch[4];
+  int64_t launches[5];
+  double total_ms[5];
+  double bytes_per_launch[5];
 } xm_spmm_counters;
 xm_status xm_spmm_timing(xm_problem* p, int32_t enable);
 xm_status xm_spmm_stats(xm_problem* p, xm_spmm_counters* out, int32_t reset);

@@ -69,8 +69,8 @@ class _AdjInfo(ctypes.Structure):
 
 
 class _SpmmStats(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4),
-                ("bytes_per_launch", ctypes.c_double * 4)]
+    _fields_ = [("launches", ctypes.c_int64 * 5), ("total_ms", ctypes.c_double * 5),
+                ("bytes_per_launch", ctypes.c_double * 5)]
 
 
 def library_path() -> str:
@@ -116,6 +116,8 @@ def load_library() -> ctypes.CDLL:
     lib.xm_build_stats.restype = ctypes.c_int
     lib.xm_set_product_kind.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.xm_set_product_kind.restype = ctypes.c_int
+    lib.xm_get_product_kind.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.xm_get_product_kind.restype = ctypes.c_int
     lib.xm_set_spmm_kind.argtypes = [P, ctypes.c_int, ctypes.c_int]
     lib.xm_set_spmm_kind.restype = ctypes.c_int
     lib.xm_spmm_timing.argtypes = [P, I32]
@@ -222,13 +224,20 @@ class Problem:
 
     def set_spmm_kind(self, dtype: str, kind: str, role: str | None = None):
         """Product kernel for the stored Q of `dtype`: "upper" (reads the upper
-        triangle only), "full" (reads all of Q) or, for "f64", "factored" (from
-        the elimination factors of Q, without reading Q)."""
+        triangle only), "full" (reads all of Q) or, for "f64" and "f32",
+        "factored" (from the elimination factors of Q, without reading Q)."""
         k = {"full": 0, "upper": 1, "factored": 2}[kind]
         if role is None:
             _check(load_library().xm_set_spmm_kind(self._h, _DT[dtype], k))
         else:
             _check(load_library().xm_set_product_kind(self._h, {"residual": 0, "curvature": 1}[role], _DT[dtype], k))
+
+    def spmm_kind(self, dtype: str, role: str) -> str:
+        """Product kernel in use for `dtype` in `role` ("residual" or "curvature")."""
+        k = ctypes.c_int()
+        _check(load_library().xm_get_product_kind(self._h, {"residual": 0, "curvature": 1}[role], _DT[dtype],
+                                                  ctypes.byref(k)))
+        return ("full", "upper", "factored")[k.value]
 
     def spmm_timing(self, enable: bool = True):
         _check(load_library().xm_spmm_timing(self._h, int(enable)))
@@ -237,7 +246,7 @@ class Problem:
         st = _SpmmStats()
         _check(load_library().xm_spmm_stats(self._h, ctypes.byref(st), int(reset)))
         out = {}
-        for name, k in list(_DT.items()) + [("f64_factored", 3)]:
+        for name, k in list(_DT.items()) + [("f64_factored", 3), ("f32_factored", 4)]:
             out[name] = {"launches": st.launches[k], "total_ms": st.total_ms[k],
                          "bytes_per_launch": st.bytes_per_launch[k]}
         return out

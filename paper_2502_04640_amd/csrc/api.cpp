@@ -190,7 +190,7 @@ xm_status set_kind(xm_problem* p, int role, xm_dtype dtype, xm_spmm_kind kind) {
   if (dtype < XM_F64 || dtype > XM_BF16) return fail(XM_EINVAL, "unknown dtype");
   if (kind != XM_SPMM_FULL && kind != XM_SPMM_UPPER && kind != XM_SPMM_FACTORED)
     return fail(XM_EINVAL, "unknown product kernel");
-  if (kind == XM_SPMM_FACTORED && dtype != XM_F64) return fail(XM_EINVAL, "the factored product is FP64 only");
+  if (kind == XM_SPMM_FACTORED && dtype == XM_BF16) return fail(XM_EINVAL, "no BF16 factored product");
   if (role < 0) {
     p->spmm_kind[XM_ROLE_RESIDUAL][dtype] = kind;
     p->spmm_kind[XM_ROLE_CURVATURE][dtype] = kind;
@@ -211,6 +211,16 @@ xm_status xm_set_product_kind(xm_problem* p, xm_product_role role, xm_dtype dtyp
   XM_API_TRY
   if (role != XM_ROLE_RESIDUAL && role != XM_ROLE_CURVATURE) return fail(XM_EINVAL, "unknown product role");
   return set_kind(p, role, dtype, kind);
+  XM_API_CATCH
+}
+
+xm_status xm_get_product_kind(const xm_problem* p, xm_product_role role, xm_dtype dtype, xm_spmm_kind* kind) {
+  XM_API_TRY
+  if (!p || !kind) return fail(XM_EINVAL, "NULL argument");
+  if (role != XM_ROLE_RESIDUAL && role != XM_ROLE_CURVATURE) return fail(XM_EINVAL, "unknown product role");
+  if (dtype < XM_F64 || dtype > XM_BF16) return fail(XM_EINVAL, "unknown dtype");
+  *kind = static_cast<xm_spmm_kind>(p->spmm_kind[role][dtype]);
+  return XM_OK;
   XM_API_CATCH
 }
 
@@ -235,7 +245,7 @@ xm_status xm_spmm_stats(xm_problem* p, xm_spmm_counters* out, int32_t reset) {
     out->total_ms[e.dtype] += ms;
     out->bytes_per_launch[e.dtype] += e.bytes;
   }
-  for (int d = 0; d < 4; ++d)
+  for (int d = 0; d < 5; ++d)
     if (out->launches[d] > 0) out->bytes_per_launch[d] /= static_cast<double>(out->launches[d]);
   if (reset) p->events_used = 0;
   return XM_OK;

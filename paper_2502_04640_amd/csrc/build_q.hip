@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kB) void reduce_blocks_kernel(
     const int64_t* __restrict__ seg_start, const uint32_t* __restrict__ seg_key, int64_t S, int32_t N,
     const uint64_t* __restrict__ vals, const double* __restrict__ u_s, const double* __restrict__ w_s,
     const int32_t* __restrict__ lm_s, const double* __restrict__ Wl, double* Q, int32_t ld,
-    double* Art, double* Att, double* Arr) {
+    double* Art, double* Att, double* fac) {
   const int64_t s = static_cast<int64_t>(blockIdx.x) * (kB / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (s >= S) return;
@@ -190,7 +190,9 @@ __global__ __launch_bounds__(kB) void reduce_blocks_kernel(
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) Arr[9 * s + 3 * a + b] = acc[a * 4 + b];
+      for (int b = 0; b < 3; ++b) fac[(3 * a + b) * S + s] = acc[a * 4 + b];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) fac[(9 + a) * S + s] = acc[4 * a + 3];
     Art[3 * s] = acc[3];
     Art[3 * s + 1] = acc[7];
     Art[3 * s + 2] = acc[11];
@@ -198,8 +200,9 @@ __global__ __launch_bounds__(kB) void reduce_blocks_kernel(
   }
 }
 
-// ArtT[s] = Art[t] for the block s = (i, j) and its transpose t = (j, i)
-// (binary search of i in row j: columns are sorted within a row)
+// ArtT[c][s] = Art[t][c] for the block s = (i, j) and its transpose t = (j, i)
+// (binary search of i in row j: columns are sorted within a row); ArtT is
+// structure of arrays, [3][S]
 __global__ void transpose_art_kernel(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                      const double* __restrict__ Art, int32_t N, int64_t S, double* ArtT,
                                      int* flags) {
@@ -224,7 +227,7 @@ __global__ void transpose_art_kernel(const int32_t* __restrict__ row_ptr, const 
     return;
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) ArtT[3 * s + c] = Art[3 * static_cast<int64_t>(a) + c];
+  for (int c = 0; c < 3; ++c) ArtT[c * S + s] = Art[3 * static_cast<int64_t>(a) + c];
 }
 
 __global__ void pattern_kernel(const uint32_t* __restrict__ seg_key, int64_t S, int32_t N,
@@ -270,62 +273,52 @@ __global__ void scatter_grounded_kernel(const int32_t* __restrict__ row_ptr, con
 // rank-64 product per tile on FP64 matrix cores.
 constexpr int kNB = 64;
 
-// -A_KK^{-1} by Gauss-Jordan pivoting; a last block with nb < 64 is padded
-// with dscale * I.  Dinv (nb x nb) = A_KK^{-1}.  Thread t keeps the 16 entries
-// (ibase + 4c, j) of the block in registers; only the pivot column and row go
-// through LDS, double-buffered so that one barrier per pivot suffices.
+// -A_KK^{-1} by Gauss-Jordan pivoting in LDS; a last block with nb < 64 is
+// padded with dscale * I.  Dinv (nb x nb) = A_KK^{-1}.
 __global__ __launch_bounds__(kB) void sweep_pivot_kernel(const double* __restrict__ A, int32_t lda,
                                                          int32_t k0, int32_t nb, double dscale,
                                                          double* Dinv, int* flags) {
-  __shared__ double colbuf[2][kNB], rowbuf[2][kNB];
+  __shared__ double D[kNB][kNB + 1];
   const int t = threadIdx.x;
   const int j = t & 63, ibase = t >> 6;  // thread owns column j of rows ibase + 4c
-  double d[kNB / 4];
-#pragma unroll
   for (int c = 0; c < kNB / 4; ++c) {
     const int i = ibase + 4 * c;
-    d[c] = (i < nb && j < nb) ? A[static_cast<int64_t>(k0 + i) * lda + k0 + j] : (i == j ? dscale : 0.0);
-  }
-  // pivot 0's column and row
-#pragma unroll
-  for (int c = 0; c < kNB / 4; ++c) {
-    const int i = ibase + 4 * c;
-    if (j == 0) colbuf[0][i] = d[c];
-    if (i == 0) rowbuf[0][j] = d[c];
+    D[i][j] = (i < nb && j < nb) ? A[static_cast<int64_t>(k0 + i) * lda + k0 + j] : (i == j ? dscale : 0.0);
   }
   __syncthreads();
   for (int p = 0; p < kNB; ++p) {
-    const int par = p & 1;
-    const double piv = rowbuf[par][p];
-    if (!(piv > 1e-11 * dscale)) {
+    const double d = D[p][p];
+    if (!(d > 1e-11 * dscale)) {
       if (t == 0) flags[4] = 1;
-      return;  // uniform across the block: every thread read the same pivot
+      return;  // uniform across the block: every thread read the same d
     }
-    const double inv = 1.0 / piv;
-    const double rpj = rowbuf[par][j];  // old A[p][j]
+    const double inv = 1.0 / d;
+    const double dpj = D[p][j] * inv;
+    double upd[kNB / 4];
 #pragma unroll
     for (int c = 0; c < kNB / 4; ++c) {
       const int i = ibase + 4 * c;
-      const double cip = colbuf[par][i];  // old A[i][p]
-      if (i != p && j != p) d[c] -= cip * rpj * inv;
-      else if (i != p) d[c] = cip * inv;
-      else if (j != p) d[c] = rpj * inv;
-      else d[c] = -inv;
+      upd[c] = D[i][j] - D[i][p] * dpj;
     }
-    if (p + 1 < kNB) {
+    __syncthreads();
+    if (j != p) {
 #pragma unroll
       for (int c = 0; c < kNB / 4; ++c) {
         const int i = ibase + 4 * c;
-        if (j == p + 1) colbuf[par ^ 1][i] = d[c];
-        if (i == p + 1) rowbuf[par ^ 1][j] = d[c];
+        if (i != p) D[i][j] = upd[c];
       }
     }
     __syncthreads();
+    if (t < kNB && t != p) {
+      D[t][p] *= inv;
+      D[p][t] *= inv;
+    }
+    if (t == 0) D[p][p] = -inv;
+    __syncthreads();
   }
-#pragma unroll
   for (int c = 0; c < kNB / 4; ++c) {
     const int i = ibase + 4 * c;
-    if (i < nb && j < nb) Dinv[i * nb + j] = -d[c];
+    if (i < nb && j < nb) Dinv[i * nb + j] = -D[i][j];
   }
 }
 
@@ -472,82 +465,6 @@ __global__ void sweep_finish_kernel(double* A, int32_t lda, int32_t n, int32_t k
   }
 }
 
-// ---- sparse rows x dense:  out[3i+a][c] (+)= sum_{s in row i, j >= 1} Art[s][a] D[j-1][c]
-// With `upper`, only columns c >= 3i are formed (the block upper triangle of a
-// symmetric result; the lower part is copied from it afterwards).
-constexpr int kVPT = 4;
-__global__ __launch_bounds__(kB) void gather_product_kernel(const int32_t* __restrict__ row_ptr,
-                                                            const int32_t* __restrict__ col,
-                                                            const double* __restrict__ Art,
-                                                            const double* __restrict__ D, int32_t ldd,
-                                                            int32_t K, double* out, int32_t ldo,
-                                                            int accumulate, int upper) {
-  // grid: x = frame (fastest), y = column tile, so that the workgroups in flight
-  // share one column tile of D (N rows x 8 KB, resident in the last-level cache).
-  // Thread t owns the column pairs (c, c+1) and (c+512, c+513), c = tile + 2t;
-  // neighbours are taken 4 at a time so that 8 16-byte loads are in flight.
-  const int i = blockIdx.x;
-  const int cmin = upper ? 3 * i : 0;
-  if (static_cast<int>(blockIdx.y + 1) * (kB * kVPT) <= cmin) return;  // tile wholly left of the diagonal
-  const int c0 = blockIdx.y * (kB * kVPT) + 2 * threadIdx.x;
-  const bool in0 = c0 < K, in1 = c0 + 2 * kB < K;  // pair in range (c < K, K <= ldd, ldd even)
-  double acc[3][4] = {};
-  const int32_t s0 = row_ptr[i], s1 = row_ptr[i + 1];
-  int32_t s = s0;
-  for (; s + 4 <= s1; s += 4) {
-    double a[4][3];
-    double2 d0[4], d1[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int j = col[s + u];
-      const double w = (j == 0) ? 0.0 : 1.0;  // column 0 of A_rt is the anchored frame: no term
-      a[u][0] = w * Art[3 * (s + u)];
-      a[u][1] = w * Art[3 * (s + u) + 1];
-      a[u][2] = w * Art[3 * (s + u) + 2];
-      const double* Dj = D + static_cast<int64_t>(j > 0 ? j - 1 : 0) * ldd;
-      d0[u] = in0 ? *reinterpret_cast<const double2*>(Dj + c0) : double2{0.0, 0.0};
-      d1[u] = in1 ? *reinterpret_cast<const double2*>(Dj + c0 + 2 * kB) : double2{0.0, 0.0};
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        acc[q][0] += a[u][q] * d0[u].x;
-        acc[q][1] += a[u][q] * d0[u].y;
-        acc[q][2] += a[u][q] * d1[u].x;
-        acc[q][3] += a[u][q] * d1[u].y;
-      }
-  }
-  for (; s < s1; ++s) {
-    const int j = col[s];
-    if (j == 0) continue;
-    const double* Dj = D + static_cast<int64_t>(j - 1) * ldd;
-    const double2 e0 = in0 ? *reinterpret_cast<const double2*>(Dj + c0) : double2{0.0, 0.0};
-    const double2 e1 = in1 ? *reinterpret_cast<const double2*>(Dj + c0 + 2 * kB) : double2{0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const double aq = Art[3 * s + q];
-      acc[q][0] += aq * e0.x;
-      acc[q][1] += aq * e0.y;
-      acc[q][2] += aq * e1.x;
-      acc[q][3] += aq * e1.y;
-    }
-  }
-  const int cc[4] = {c0, c0 + 1, c0 + 2 * kB, c0 + 2 * kB + 1};
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    double* o = out + static_cast<int64_t>(3 * i + q) * ldo;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int c = cc[v];
-      if (c < K && c >= cmin) {
-        if (accumulate) o[c] += acc[q][v];
-        else o[c] = acc[q][v];
-      }
-    }
-  }
-}
-
 // out[c][r] = in[r][c]  (64 x 64 tiles through LDS)
 __global__ __launch_bounds__(kB) void transpose_kernel(const double* __restrict__ in, int32_t rows, int32_t cols,
                                                        int32_t ldi, double* out, int32_t ldo) {
@@ -690,6 +607,363 @@ __global__ void to_bf16_kernel(const double* __restrict__ in, int64_t n, uint16_
 
 // HIP events around every launch of one kernel on a stream; total() waits
 // for the last one and returns the summed device time in milliseconds.
+// ---- frame grouping for the two sparse-dense products ---------------------
+// P = B Gm and the correction B P^T both read, for every stored block (i, j),
+// a whole row j of a dense operand: frame by frame that is ~300 dense rows per
+// frame, and the products are bound by the traffic of those rows from the
+// caches.  Frames that are close in a Cuthill-McKee order of the co-visibility
+// graph share most of their co-visible frames, so kGroup consecutive frames in
+// that order are processed by one workgroup: each dense row of their union is
+// read once and applied to every frame of the group that sees it (a 4x cut in
+// rows read on clustered scenes).  The order is a breadth-first search from
+// the anchored frame 0 in which each new level is sorted by the position of its
+// first discoverer, then by frame index: deterministic.
+constexpr int kGroup = 16;
+constexpr int32_t kUnset = 0x7f7f7f7f;  // key of a frame not reached yet (memset byte 0x7f)
+
+// key[u] = min position (in the order) of a frontier frame adjacent to u, for unplaced u
+__global__ __launch_bounds__(kB) void cm_expand_kernel(const int32_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const int32_t* __restrict__ order, int32_t lo, int32_t hi,
+                                                       const int32_t* __restrict__ pos, int32_t* key) {
+  const int p = lo + blockIdx.x * (kB / 64) + (threadIdx.x >> 6);
+  if (p >= hi) return;  // whole wavefronts only
+  const int v = order[p];
+  for (int32_t s = row_ptr[v] + (threadIdx.x & 63); s < row_ptr[v + 1]; s += 64) {
+    const int u = col[s];
+    if (pos[u] < 0) atomicMin(key + u, p);
+  }
+}
+
+// flag[u] = 1 for the frames reached in this level (unplaced, with a key)
+__global__ void cm_flag_kernel(const int32_t* __restrict__ pos, const int32_t* __restrict__ key, int32_t N,
+                               int64_t* flag) {
+  const int u = blockIdx.x * kB + threadIdx.x;
+  if (u < N) flag[u] = (pos[u] < 0 && key[u] != kUnset) ? 1 : 0;
+}
+
+// compact the reached frames in index order: (key - lo, frame) pairs for a stable sort by key
+__global__ void cm_compact_kernel(const int32_t* __restrict__ pos, const int32_t* __restrict__ key,
+                                  const int64_t* __restrict__ slot, int32_t N, int32_t lo, uint32_t* ks,
+                                  uint64_t* vs) {
+  const int u = blockIdx.x * kB + threadIdx.x;
+  if (u >= N || !(pos[u] < 0 && key[u] != kUnset)) return;
+  ks[slot[u]] = static_cast<uint32_t>(key[u] - lo);
+  vs[slot[u]] = static_cast<uint64_t>(u);
+}
+
+__global__ void cm_place_kernel(const uint64_t* __restrict__ vs, int64_t count, int32_t hi, int32_t* order,
+                                int32_t* pos) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (t >= count) return;
+  const int u = static_cast<int>(vs[t]);
+  order[hi + t] = u;
+  pos[u] = static_cast<int32_t>(hi + t);
+}
+
+// frames never reached (a disconnected view graph, rejected later): appended in index order
+__global__ void cm_rest_kernel(const int64_t* __restrict__ slot, const int32_t* __restrict__ pos0, int32_t N,
+                               int32_t hi, int32_t* order, int32_t* pos) {
+  const int u = blockIdx.x * kB + threadIdx.x;
+  if (u >= N || pos0[u] >= 0) return;
+  order[hi + slot[u]] = u;
+  pos[u] = static_cast<int32_t>(hi + slot[u]);
+}
+
+__global__ void cm_unplaced_kernel(const int32_t* __restrict__ pos, int32_t N, int64_t* flag) {
+  const int u = blockIdx.x * kB + threadIdx.x;
+  if (u < N) flag[u] = pos[u] < 0 ? 1 : 0;
+}
+
+// Bitmap in LDS of the frames j >= 1 co-visible with some frame of group g
+// (the anchored frame 0 has no column in B).  Returns the number of words.
+__device__ void group_bitmap(int g, int32_t N, const int32_t* __restrict__ order,
+                             const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, uint32_t* bits) {
+  const int nw = (N + 31) / 32;
+  for (int w = threadIdx.x; w < nw; w += kB) bits[w] = 0u;
+  __syncthreads();
+  for (int f = 0; f < kGroup; ++f) {
+    const int a = g * kGroup + f;
+    if (a >= N) break;
+    const int i = order[a];
+    for (int32_t s = row_ptr[i] + threadIdx.x; s < row_ptr[i + 1]; s += kB) {
+      const int j = col[s];
+      if (j > 0) atomicOr(bits + (j >> 5), 1u << (j & 31));
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kB) void group_count_kernel(int32_t N, const int32_t* __restrict__ order,
+                                                         const int32_t* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ col, int64_t* ucount) {
+  extern __shared__ uint32_t bits[];
+  __shared__ int partial[kB];
+  group_bitmap(blockIdx.x, N, order, row_ptr, col, bits);
+  const int nw = (N + 31) / 32;
+  int c = 0;
+  for (int w = threadIdx.x; w < nw; w += kB) c += __popc(bits[w]);
+  partial[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int k = 0; k < kB; ++k) t += partial[k];
+    ucount[blockIdx.x] = t;
+  }
+}
+
+// uid[k]: the union of group g in increasing frame order (k from ustart[g]);
+// coef[k][f][q] = A_rt[3 order[g kGroup + f] + q][uid[k]] for q < 3 (rows of 4,
+// the last one 0; zero where frame f does not see uid[k]; coef is cleared
+// beforehand)
+__global__ __launch_bounds__(kB) void group_fill_kernel(int32_t N, const int32_t* __restrict__ order,
+                                                        const int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ Art,
+                                                        const int64_t* __restrict__ ustart, int32_t* uid,
+                                                        double* coef) {
+  extern __shared__ uint32_t bits[];
+  const int nw = (N + 31) / 32;
+  int* wpre = reinterpret_cast<int*>(bits + nw);  // exclusive prefix of set bits per word
+  const int g = blockIdx.x;
+  group_bitmap(g, N, order, row_ptr, col, bits);
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < nw; ++w) {
+      wpre[w] = t;
+      t += __popc(bits[w]);
+    }
+  }
+  __syncthreads();
+  const int64_t base = ustart[g];
+  for (int w = threadIdx.x; w < nw; w += kB) {
+    uint32_t b = bits[w];
+    int r = wpre[w];
+    while (b) {
+      const int t = __ffs(b) - 1;
+      uid[base + r++] = 32 * w + t;
+      b &= b - 1;
+    }
+  }
+  for (int f = 0; f < kGroup; ++f) {
+    const int a = g * kGroup + f;
+    if (a >= N) break;
+    const int i = order[a];
+    for (int32_t s = row_ptr[i] + threadIdx.x; s < row_ptr[i + 1]; s += kB) {
+      const int j = col[s];
+      if (j == 0) continue;
+      const int w = j >> 5;
+      const int64_t k = base + wpre[w] + __popc(bits[w] & ((1u << (j & 31)) - 1u));
+#pragma unroll
+      for (int q = 0; q < 3; ++q) coef[(k * kGroup + f) * 4 + q] = Art[3 * static_cast<int64_t>(s) + q];
+    }
+  }
+}
+
+// Grouped sparse-dense product on FP64 matrix cores.  For group g (frames at
+// positions a = g kGroup + f of the order) and column c:
+//   out[3a+q][c] = sum_{k in union of g} coef[k][f][q] D[uid[k]-1][c],
+// i.e. the 48 output rows of the group are a dense (48 x |union|) coefficient
+// block (zeros where a frame does not see a union frame) times the gathered
+// union rows of D.  P pass: D = Gm (N-1 x N-1), out = P with rows in the order.
+// Q pass: D = P^T (columns in the order), out = the correction in the order,
+// upper triangle only (c >= 3a).
+//
+// Workgroup = group x 256 columns.  The union is taken in chunks of 16 rows:
+// the chunk's rows of D (16 x 256) and coefficients (16 x 16 x 4) are staged in
+// LDS, double-buffered: the next chunk's global loads are in flight while the
+// current one is multiplied.  Each wave takes 64 columns as 3 x 4 tiles of
+// v_mfma_f64_16x16x4f64 per 4 union rows, the tile (q, t) holding rows 3f + q
+// and columns 4j + t (f, j < 16): lane l supplies A[f = l % 16][k = l / 16]
+// for the three q from one 32-byte read of coef[k][f][0..3] and B[k = l / 16]
+// [j = l % 16] for the four t from one 32-byte read of the union row, and
+// holds C[l / 16 + 4 r][l % 16] in register r.
+constexpr int kGroupCols = 256;
+constexpr int kChunk = 16;
+typedef double v4d_a __attribute__((ext_vector_type(4), aligned(32)));
+template <bool UPPER>
+__global__ __launch_bounds__(kB) void group_product_kernel(int32_t N, const int32_t* __restrict__ tile_start,
+                                                           int32_t ntiles, const int64_t* __restrict__ ustart,
+                                                           const int32_t* __restrict__ uid,
+                                                           const double* __restrict__ coef,
+                                                           const double* __restrict__ D, int32_t ldd, int32_t K,
+                                                           double* __restrict__ out, int32_t ldo) {
+  __shared__ v4d_a Bs[2][kChunk][kGroupCols / 4];
+  __shared__ v4d_a As[2][kChunk][kGroup];
+  // workgroup w -> (column tile y, group g): tile-major over the pairs that
+  // produce output (tile y holds the groups g < tile_start[y + 1] - tile_start[y]),
+  // so that the workgroups in flight read few column slices of D
+  const int w = blockIdx.x;
+  int lo = 0, hi = ntiles - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (tile_start[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  const int g = w - tile_start[lo];
+  const int row0 = 3 * kGroup * g;
+  const int cbase = lo * kGroupCols;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int kr = lane >> 4, lj = lane & 15;
+  // staging: thread t loads row t / 16 of the chunk, columns 16 (t % 16) .. + 15
+  // of the tile (four 32-byte pieces), and coefficient row t / 16, frame t % 16
+  const int sr = t >> 4, sc = (t & 15) * 16;
+  const int gc = cbase + sc;
+  const bool sfull = gc + 16 <= K;
+  const int64_t k0 = ustart[g], k1 = ustart[g + 1];
+  struct Stage {
+    v4d_a b[4], a;
+  };
+  auto fetch = [&](int64_t kc, Stage& st) {
+    const int64_t k = kc + sr;
+    const v4d_a z = v4d_a{0.0, 0.0, 0.0, 0.0};
+    if (k < k1) {
+      st.a = *reinterpret_cast<const v4d_a*>(coef + (k * kGroup + (t & 15)) * 4);
+      const double* drow = D + static_cast<int64_t>(uid[k] - 1) * ldd + gc;
+      if (sfull) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) st.b[p] = *reinterpret_cast<const v4d_a*>(drow + 4 * p);
+      } else {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          st.b[p] = z;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (gc + 4 * p + e < K) st.b[p][e] = drow[4 * p + e];
+        }
+      }
+    } else {
+      st.a = z;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) st.b[p] = z;
+    }
+  };
+  auto stash = [&](int buf, const Stage& st) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) Bs[buf][sr][(sc >> 2) + p] = st.b[p];
+    As[buf][sr][t & 15] = st.a;
+  };
+  v4d acc[3][4];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[q][u] = v4d{0.0, 0.0, 0.0, 0.0};
+  auto multiply = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < kChunk / 4; ++ks) {
+      const v4d_a av = As[buf][4 * ks + kr][lj];
+      const v4d_a bv = Bs[buf][4 * ks + kr][wave * 16 + lj];
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          acc[q][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[u], acc[q][u], 0, 0, 0);
+    }
+  };
+  // chunk c sits in LDS buffer c % 2; the next chunk's global loads are in
+  // flight (in registers) while chunk c is multiplied
+  Stage st;
+  fetch(k0, st);
+  stash(0, st);
+  __syncthreads();
+  const int64_t nchunks = (k1 - k0 + kChunk - 1) / kChunk;
+  for (int64_t c = 0; c < nchunks; ++c) {
+    const bool more = c + 1 < nchunks;
+    if (more) fetch(k0 + (c + 1) * kChunk, st);
+    multiply(c & 1);
+    if (more) {
+      stash((c + 1) & 1, st);
+      __syncthreads();
+    }
+  }
+  const int n3 = 3 * N;
+  const int c4 = cbase + wave * 64 + 4 * lj;  // this lane's four output columns
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int f = kr + 4 * r;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int orow = row0 + 3 * f + q;
+      if (orow >= n3) continue;
+      double* o = out + static_cast<int64_t>(orow) * ldo;
+      const int cmin = UPPER ? row0 + 3 * f : 0;
+      if (c4 + 4 <= K && c4 >= cmin) {
+        *reinterpret_cast<v4d_a*>(o + c4) = v4d_a{acc[q][0][r], acc[q][1][r], acc[q][2][r], acc[q][3][r]};
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (c4 + u < K && c4 + u >= cmin) o[c4 + u] = acc[q][u][r];
+      }
+    }
+  }
+}
+
+// Q[r][c] += Cperm at the same pair, r <= c (the upper triangle in frame
+// order): Cperm holds, for positions a <= b of the order, the block (a, b)
+// in rows 3a.. and columns 3b.. (block-upper, diagonal blocks whole)
+__global__ __launch_bounds__(kB) void unpermute_add_kernel(const double* __restrict__ Cp, int32_t ld, int32_t n3,
+                                                           const int32_t* __restrict__ pos, double* Q) {
+  const int r = blockIdx.x;  // grid: x = row, y = column tile
+  const int c = blockIdx.y * kB + threadIdx.x;
+  if (c < r || c >= n3) return;
+  const int a = pos[r / 3], b = pos[c / 3];
+  const int ra = 3 * a + r % 3, cb = 3 * b + c % 3;
+  const double v = (a <= b) ? Cp[static_cast<int64_t>(ra) * ld + cb] : Cp[static_cast<int64_t>(cb) * ld + ra];
+  Q[static_cast<int64_t>(r) * ld + c] += v;
+}
+
+// Cuthill-McKee order of the co-visibility graph from frame 0 (order:
+// position -> frame, pos: frame -> position); one host round trip per level.
+void cm_order(int32_t N, const int32_t* row_ptr, const int32_t* col, DevBuf<int32_t>& order, DevBuf<int32_t>& pos,
+              hipStream_t s) {
+  order.alloc(N);
+  pos.alloc(N);
+  DevBuf<int32_t> key(N);
+  DevBuf<int64_t> flag(N), slot(N + 1);
+  DevBuf<uint32_t> ks(N), kt(N);
+  DevBuf<uint64_t> vs(N), vt(N);
+  XM_HIP(hipMemsetAsync(pos.ptr, 0xff, N * sizeof(int32_t), s));
+  XM_HIP(hipMemsetAsync(key.ptr, 0x7f, N * sizeof(int32_t), s));
+  const int32_t zero = 0;
+  XM_HIP(hipMemcpyAsync(order.ptr, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  XM_HIP(hipMemcpyAsync(pos.ptr, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  int32_t lo = 0, hi = 1;
+  const unsigned gn = cdiv(N, kB);
+  while (hi < N) {
+    hipLaunchKernelGGL(cm_expand_kernel, dim3(cdiv(hi - lo, kB / 64)), dim3(kB), 0, s, row_ptr, col, order.ptr, lo,
+                       hi, pos.ptr, key.ptr);
+    XM_LAUNCH_CHECK("cm_expand_kernel");
+    hipLaunchKernelGGL(cm_flag_kernel, dim3(gn), dim3(kB), 0, s, pos.ptr, key.ptr, N, flag.ptr);
+    XM_LAUNCH_CHECK("cm_flag_kernel");
+    exclusive_scan_i64(flag.ptr, slot.ptr, N, s);  // synchronises
+    int64_t count = 0;
+    XM_HIP(hipMemcpy(&count, slot.ptr + N, sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (count == 0) break;
+    hipLaunchKernelGGL(cm_compact_kernel, dim3(gn), dim3(kB), 0, s, pos.ptr, key.ptr, slot.ptr, N, lo, ks.ptr,
+                       vs.ptr);
+    XM_LAUNCH_CHECK("cm_compact_kernel");
+    int bits = 1;
+    while ((int64_t(1) << bits) < (hi - lo)) ++bits;
+    radix_sort_pairs(ks.ptr, vs.ptr, kt.ptr, vt.ptr, count, bits, s);
+    hipLaunchKernelGGL(cm_place_kernel, dim3(cdiv(count, kB)), dim3(kB), 0, s, vs.ptr, count, hi, order.ptr,
+                       pos.ptr);
+    XM_LAUNCH_CHECK("cm_place_kernel");
+    lo = hi;
+    hi += static_cast<int32_t>(count);
+  }
+  if (hi < N) {
+    DevBuf<int32_t> pos0(N);
+    XM_HIP(hipMemcpyAsync(pos0.ptr, pos.ptr, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(cm_unplaced_kernel, dim3(gn), dim3(kB), 0, s, pos.ptr, N, flag.ptr);
+    XM_LAUNCH_CHECK("cm_unplaced_kernel");
+    exclusive_scan_i64(flag.ptr, slot.ptr, N, s);
+    hipLaunchKernelGGL(cm_rest_kernel, dim3(gn), dim3(kB), 0, s, slot.ptr, pos0.ptr, N, hi, order.ptr, pos.ptr);
+    XM_LAUNCH_CHECK("cm_rest_kernel");
+  }
+  XM_HIP(hipStreamSynchronize(s));
+}
+
 struct LaunchTimer {
   std::vector<hipEvent_t> ev;
   void start(hipStream_t s) { ev.push_back(record(s)); }
@@ -823,10 +1097,10 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   XM_HIP(hipMemsetAsync(P->Q64.ptr, 0, qn * sizeof(double), s));
   P->Art.alloc(3 * S);
   P->Att.alloc(S);
-  P->Arr.alloc(9 * S);
+  P->fac.alloc(15 * S);
   hipLaunchKernelGGL(reduce_blocks_kernel, dim3(cdiv(S, kB / 64)), dim3(kB), 0, s, seg_start.ptr, seg_key.ptr,
                      S, N, pvals.ptr, P->u_s.ptr, P->w_s.ptr, P->lm_s.ptr, P->Wl.ptr, P->Q64.ptr, P->ld,
-                     P->Art.ptr, P->Att.ptr, P->Arr.ptr);
+                     P->Art.ptr, P->Att.ptr, P->fac.ptr);
   XM_LAUNCH_CHECK("reduce_blocks_kernel");
   P->row_ptr.alloc(N + 1);
   P->col.alloc(S);
@@ -836,15 +1110,15 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   hipLaunchKernelGGL(check_diag_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, P->row_ptr.ptr, P->col.ptr,
                      P->Att.ptr, N, flags.ptr);
   XM_LAUNCH_CHECK("check_diag_kernel");
-  P->ArtT.alloc(3 * S);
   hipLaunchKernelGGL(transpose_art_kernel, dim3(cdiv(S, kB)), dim3(kB), 0, s, P->row_ptr.ptr, P->col.ptr,
-                     P->Art.ptr, N, S, P->ArtT.ptr, flags.ptr);
+                     P->Art.ptr, N, S, P->fac.ptr + 12 * S, flags.ptr);
   XM_LAUNCH_CHECK("transpose_art_kernel");
   XM_HIP(hipMemcpyAsync(hflags, flags.ptr, sizeof(hflags), hipMemcpyDeviceToHost, s));
   XM_HIP(hipStreamSynchronize(s));
   pkeys.release(); pvals.release(); seg_start.release(); seg_key.release();
   require(!hflags[3], XM_EGRAPH, "a frame has no observation shared with another frame");
   require(!hflags[5], XM_EINVAL, "internal: co-visibility pattern is not symmetric");
+  cm_order(N, P->row_ptr.ptr, P->col.ptr, P->order, P->pos, s);
 
   // a2-ii: translations.  G = A_tt[1:,1:] (dense), swept to -G^{-1}.
   const int32_t ng = N - 1;
@@ -900,33 +1174,73 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
                               cdiv(ng, kNB) * 8.0 * g2, static_cast<double>(ng) * g2});
   }
 
-  // P = A_rt[:,1:] (-G^{-1})   (3N x (N-1)), then Pt = P^T, then Q += A_rt[:,1:] Pt
+  // P = A_rt[:,1:] (-G^{-1})   (3N x (N-1)), then Pt = P^T, then Q += A_rt[:,1:] Pt,
+  // both products over groups of frames consecutive in the Cuthill-McKee order
   {
+    const int32_t ngroups = static_cast<int32_t>(cdiv(N, kGroup));
+    const int nw = (N + 31) / 32;
+    const size_t lds = 2 * static_cast<size_t>(nw) * sizeof(uint32_t);
+    DevBuf<int64_t> ucount(ngroups), ustart(ngroups + 1);
+    hipLaunchKernelGGL(group_count_kernel, dim3(ngroups), dim3(kB), lds, s, N, P->order.ptr, P->row_ptr.ptr,
+                       P->col.ptr, ucount.ptr);
+    XM_LAUNCH_CHECK("group_count_kernel");
+    exclusive_scan_i64(ucount.ptr, ustart.ptr, ngroups, s);
+    int64_t total = 0;
+    XM_HIP(hipMemcpy(&total, ustart.ptr + ngroups, sizeof(int64_t), hipMemcpyDeviceToHost));
+    DevBuf<int32_t> uid(std::max<int64_t>(total, 1));
+    DevBuf<double> coef(std::max<int64_t>(total, 1) * 4 * kGroup);
+    XM_HIP(hipMemsetAsync(coef.ptr, 0, coef.bytes(), s));
+    hipLaunchKernelGGL(group_fill_kernel, dim3(ngroups), dim3(kB), lds, s, N, P->order.ptr, P->row_ptr.ptr,
+                       P->col.ptr, P->Art.ptr, ustart.ptr, uid.ptr, coef.ptr);
+    XM_LAUNCH_CHECK("group_fill_kernel");
+    // workgroup lists of the two passes: tile-major (group, column tile) pairs;
+    // the Q pass only takes the pairs with columns right of the group's first row
+    auto tile_list = [&](int32_t K, bool upper, DevBuf<int32_t>& ts) {
+      const int32_t nt = static_cast<int32_t>(cdiv(K, kGroupCols));
+      std::vector<int32_t> h(nt + 1, 0);
+      for (int32_t y = 0; y < nt; ++y) {
+        const int64_t gmax = upper ? std::min<int64_t>(ngroups, ((y + 1) * int64_t(kGroupCols) + 3 * kGroup - 1) /
+                                                                     (3 * kGroup))
+                                   : ngroups;
+        h[y + 1] = h[y] + static_cast<int32_t>(gmax);
+      }
+      ts.alloc(nt + 1);
+      XM_HIP(hipMemcpy(ts.ptr, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+      return std::make_pair(nt, h[nt]);
+    };
+    DevBuf<int32_t> tsP, tsQ;
+    const auto lp = tile_list(ng, false, tsP);
+    const auto lq = tile_list(P->n3, true, tsQ);
     const int32_t ldp = static_cast<int32_t>(round_up(ng, 64));
     DevBuf<double> Pm(static_cast<size_t>(P->n3) * ldp);
     LaunchTimer t_gather, t_gather_q;
     t_gather.start(s);
-    hipLaunchKernelGGL(gather_product_kernel, dim3(N, cdiv(ng, kB * kVPT)), dim3(kB), 0, s, P->row_ptr.ptr,
-                       P->col.ptr, P->Art.ptr, P->Gm.ptr, P->ldg, ng, Pm.ptr, ldp, 0, 0);
-    XM_LAUNCH_CHECK("gather_product_kernel(P)");
+    hipLaunchKernelGGL((group_product_kernel<false>), dim3(lp.second), dim3(kB), 0, s, N, tsP.ptr, lp.first,
+                       ustart.ptr, uid.ptr, coef.ptr, P->Gm.ptr, P->ldg, ng, Pm.ptr, ldp);
+    XM_LAUNCH_CHECK("group_product_kernel(P)");
     t_gather.stop(s);
     DevBuf<double> Ptr(static_cast<size_t>(ng) * P->ld);
     hipLaunchKernelGGL(transpose_kernel, dim3(cdiv(ng, 64), cdiv(P->n3, 64)), dim3(kB), 0, s, Pm.ptr, P->n3, ng,
                        ldp, Ptr.ptr, P->ld);
     XM_LAUNCH_CHECK("transpose_kernel");
+    Pm.release();
+    DevBuf<double> Cp(static_cast<size_t>(P->n3) * P->ld);
     t_gather_q.start(s);
-    hipLaunchKernelGGL(gather_product_kernel, dim3(N, cdiv(P->n3, kB * kVPT)), dim3(kB), 0, s, P->row_ptr.ptr,
-                       P->col.ptr, P->Art.ptr, Ptr.ptr, P->ld, P->n3, P->Q64.ptr, P->ld, 1, 1);
-    XM_LAUNCH_CHECK("gather_product_kernel(Q)");
+    hipLaunchKernelGGL((group_product_kernel<true>), dim3(lq.second), dim3(kB), 0, s, N, tsQ.ptr, lq.first,
+                       ustart.ptr, uid.ptr, coef.ptr, Ptr.ptr, P->ld, P->n3, Cp.ptr, P->ld);
+    XM_LAUNCH_CHECK("group_product_kernel(Q)");
     t_gather_q.stop(s);
+    hipLaunchKernelGGL(unpermute_add_kernel, dim3(P->n3, cdiv(P->n3, kB)), dim3(kB), 0, s, Cp.ptr, P->ld, P->n3,
+                       P->pos.ptr, P->Q64.ptr);
+    XM_LAUNCH_CHECK("unpermute_add_kernel");
     XM_HIP(hipStreamSynchronize(s));
     // P pass: G^{-1} read once, P written once, 3 FMAs per (stored block, column);
-    // Q pass: P^T read once, the upper triangle of Q read and written once, half the columns
+    // Q pass: P^T read once, the upper triangle written once, half the columns
     const double nnz_off = static_cast<double>(S);  // every stored block of A_rt (the few with j = 0 are skipped)
-    P->build_stats.push_back({"gather_product_kernel (P)", 1, t_gather.total(),
+    P->build_stats.push_back({"group_product_kernel (P)", 1, t_gather.total(),
                               8.0 * (static_cast<double>(ng) * ng + 3.0 * N * ng), 6.0 * nnz_off * ng});
-    P->build_stats.push_back({"gather_product_kernel (Q)", 1, t_gather_q.total(),
-                              8.0 * (static_cast<double>(ng) * P->n3 + static_cast<double>(P->n3) * P->n3),
+    P->build_stats.push_back({"group_product_kernel (Q)", 1, t_gather_q.total(),
+                              8.0 * (static_cast<double>(ng) * P->n3 + 0.5 * static_cast<double>(P->n3) * P->n3),
                               6.0 * nnz_off * P->n3 * 0.5});
   }
   {
@@ -966,6 +1280,19 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
     hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(qn, kB)), dim3(kB), 0, s, P->Q64.ptr, static_cast<int64_t>(qn),
                        P->Q32.ptr);
     XM_LAUNCH_CHECK("to_f32_kernel");
+    // FP32 factors for the factored curvature product
+    auto to32 = [&](const DevBuf<double>& src, DevBuf<float>& dst) {
+      dst.alloc(src.n);
+      hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(src.n, kB)), dim3(kB), 0, s, src.ptr,
+                         static_cast<int64_t>(src.n), dst.ptr);
+      XM_LAUNCH_CHECK("to_f32_kernel");
+    };
+    to32(P->fac, P->fac32);
+    to32(P->Gm, P->Gm32);
+    // FP32 curvature products from the factors once the dense upper triangle
+    // no longer stays resident in the 256 MiB last-level cache
+    const double upper_bytes = 0.5 * static_cast<double>(P->n3) * (P->n3 + 1) * sizeof(float);
+    if (upper_bytes > 256.0 * 1024 * 1024) P->spmm_kind[XM_ROLE_CURVATURE][XM_F32] = XM_SPMM_FACTORED;
   }
   if (copies & XM_KEEP_BF16) {
     P->Q16.alloc(qn);

@@ -35,10 +35,16 @@ struct xm_problem {
   xm::DevBuf<double> Wl;           // per-landmark weight sum
   // co-visibility pattern (rows = frames), with the eliminated-landmark blocks
   xm::DevBuf<int32_t> row_ptr, col;  // [N+1], [nnzb]
+  // Cuthill-McKee order of the co-visibility graph: position -> frame, frame -> position
+  xm::DevBuf<int32_t> order, pos;
   xm::DevBuf<double> Art;            // [nnzb][3]: A_rt[3i+a][j]
-  xm::DevBuf<double> ArtT;           // [nnzb][3]: A_rt[3j+a][i] (the transposed block's entry)
-  xm::DevBuf<double> Arr;            // [nnzb][9]: A_rr[3i+a][3j+b], row-major 3x3
-  xm::DevBuf<double> fact_scratch;   // W and V of the factored product
+  // factors of the factored product, structure of arrays [15][nnzb]: for the
+  // block s = (i, j), rows 3a+b (a, b < 3): A_rr[3i+a][3j+b]; rows 9+a:
+  // A_rt[3i+a][j]; rows 12+a: A_rt[3j+a][i] (the transposed block's entry)
+  xm::DevBuf<double> fac;
+  xm::DevBuf<double> fact_scratch;   // padded Y^T, W and V of the factored product
+  // FP32 copies of the factors (with XM_KEEP_F32): fac as above, -G^{-1}
+  xm::DevBuf<float> fac32, Gm32;
   xm::DevBuf<double> Att;            // [nnzb]:    A_tt[i][j]
   // -(A_tt[1:,1:])^{-1}, row-major [N-1][ldg]
   xm::DevBuf<double> Gm;

@@ -134,13 +134,17 @@ __global__ __launch_bounds__(kB) void spmm_split_kernel(const TQ* __restrict__ Q
 // step with mask 32 (16, 8) then holds, in the slot the lane keeps, the row the
 // lane sends, so the three halving steps need no selects.  Within a batch a
 // wave still reads 8 whole row segments, each in 128-byte pieces.
-#ifndef XM_SYM_ROWS
-#define XM_SYM_ROWS 256
+//
+// Slabs are 256 rows (RS) unless that leaves fewer than kSymMinBlocks
+// workgroups on or above the diagonal (a small matrix, e.g. the 10^4-order
+// G^{-1} of the factored product); then 128 or 64.
+#ifndef XM_SYM_MIN_BLOCKS
+#define XM_SYM_MIN_BLOCKS 512
 #endif
 #ifndef XM_SYM_PERM
 #define XM_SYM_PERM 1
 #endif
-constexpr int kSymRows = XM_SYM_ROWS;  // RS
+constexpr int kSymMinBlocks = XM_SYM_MIN_BLOCKS;
 constexpr bool kSymPerm = XM_SYM_PERM;  // lane-permuted slots (else selects in the butterfly)
 #ifndef XM_SYM_BATCH
 #define XM_SYM_BATCH 8
@@ -204,13 +208,12 @@ __device__ __forceinline__ void sym_batch(const TQ* __restrict__ q, int32_t ld, 
 #else
 #define XM_SYM_ATTR
 #endif
-template <typename TQ, typename TV, typename TA, int R>
+template <typename TQ, typename TV, typename TA, int R, int RS>
 __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __restrict__ Q, int32_t ld, int32_t n3,
                                                       const TV* __restrict__ Yt, TA* __restrict__ colpart,
                                                       TA* __restrict__ rowpart) {
   constexpr int V = QVec<TQ>::V;
   constexpr int C = kB * V;
-  constexpr int RS = kSymRows;
   const int c = blockIdx.x, sl = blockIdx.y;
   const int j0 = c * C;
   const int i0 = sl * RS;
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __re
 // out[j][a] = sum_{s <= j / RS} colpart[s][j][a] + sum_{c >= j / C} rowpart[c][j][a]
 // 64 outputs per workgroup, 4 threads per output (every 4th partial each),
 // the 4 sums added in a fixed order: deterministic.
-template <typename TA, typename TV, int R, int C>
+template <typename TA, typename TV, int R, int C, int RS>
 __global__ __launch_bounds__(kB) void spmm_sym_reduce_kernel(const TA* __restrict__ colpart,
                                                              const TA* __restrict__ rowpart, int32_t n3,
                                                              int32_t nchunks, TV* __restrict__ out) {
@@ -316,7 +319,7 @@ __global__ __launch_bounds__(kB) void spmm_sym_reduce_kernel(const TA* __restric
   TA s = TA(0);
   if (e < m) {
     const int jrow = static_cast<int>(e / R);
-    const int smax = jrow / kSymRows;
+    const int smax = jrow / RS;
     for (int k = g; k <= smax; k += 4) s += colpart[static_cast<int64_t>(k) * m + e];
     for (int k = jrow / C + g; k < nchunks; k += 4) s += rowpart[static_cast<int64_t>(k) * m + e];
   }
@@ -397,15 +400,21 @@ void launch(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStream_t
   XM_LAUNCH_CHECK("spmm_reduce_kernel");
 }
 
-// out (n x R) = M Yt for a symmetric n x n matrix M (row-major, leading
-// dimension ld, zero padding columns) read through its upper triangle.
-template <typename TQ, typename TV, typename TA, int R>
-void sym_product(const TQ* M, int32_t ld, int32_t n, const TV* Yt, TV* out, DevBuf<char>& scratch,
-                 xm_problem::TimedLaunch* ev, hipStream_t s) {
+// workgroups of an (nchunks x nslabs) grid that are not wholly below the diagonal
+int64_t sym_active_blocks(int32_t n, int32_t ld, int C, int RS) {
+  const int nchunks = static_cast<int>(cdiv(ld, C)), nslabs = static_cast<int>(cdiv(n, RS));
+  int64_t active = 0;
+  for (int c = 0; c < nchunks; ++c) active += std::min<int64_t>(nslabs, (static_cast<int64_t>(c) * C + C - 1) / RS + 1);
+  return active;
+}
+
+template <typename TQ, typename TV, typename TA, int R, int RS>
+void sym_product_rs(const TQ* M, int32_t ld, int32_t n, const TV* Yt, TV* out, DevBuf<char>& scratch,
+                    xm_problem::TimedLaunch* ev, hipStream_t s) {
   constexpr int V = QVec<TQ>::V;
   constexpr int C = kB * V;
   const int nchunks = static_cast<int>(cdiv(ld, C));
-  const int nslabs = static_cast<int>(cdiv(n, kSymRows));
+  const int nslabs = static_cast<int>(cdiv(n, RS));
   const size_t per = static_cast<size_t>(n) * R;
   const size_t need = (static_cast<size_t>(nslabs) + nchunks) * per * sizeof(TA);
   if (scratch.n < need) {
@@ -415,13 +424,27 @@ void sym_product(const TQ* M, int32_t ld, int32_t n, const TV* Yt, TV* out, DevB
   TA* colpart = reinterpret_cast<TA*>(scratch.ptr);
   TA* rowpart = colpart + static_cast<size_t>(nslabs) * per;
   if (ev) XM_HIP(hipEventRecord(ev->start, s));
-  hipLaunchKernelGGL((spmm_sym_kernel<TQ, TV, TA, R>), dim3(nchunks, nslabs), dim3(kB), 0, s, M, ld, n, Yt,
+  hipLaunchKernelGGL((spmm_sym_kernel<TQ, TV, TA, R, RS>), dim3(nchunks, nslabs), dim3(kB), 0, s, M, ld, n, Yt,
                      colpart, rowpart);
   XM_LAUNCH_CHECK("spmm_sym_kernel");
   if (ev) XM_HIP(hipEventRecord(ev->stop, s));
-  hipLaunchKernelGGL((spmm_sym_reduce_kernel<TA, TV, R, C>), dim3(cdiv(per, 64)), dim3(kB), 0, s, colpart, rowpart,
-                     n, nchunks, out);
+  hipLaunchKernelGGL((spmm_sym_reduce_kernel<TA, TV, R, C, RS>), dim3(cdiv(per, 64)), dim3(kB), 0, s, colpart,
+                     rowpart, n, nchunks, out);
   XM_LAUNCH_CHECK("spmm_sym_reduce_kernel");
+}
+
+// out (n x R) = M Yt for a symmetric n x n matrix M (row-major, leading
+// dimension ld, zero padding columns) read through its upper triangle.
+template <typename TQ, typename TV, typename TA, int R>
+void sym_product(const TQ* M, int32_t ld, int32_t n, const TV* Yt, TV* out, DevBuf<char>& scratch,
+                 xm_problem::TimedLaunch* ev, hipStream_t s) {
+  constexpr int C = kB * QVec<TQ>::V;
+  if (sym_active_blocks(n, ld, C, 256) >= kSymMinBlocks)
+    sym_product_rs<TQ, TV, TA, R, 256>(M, ld, n, Yt, out, scratch, ev, s);
+  else if (sym_active_blocks(n, ld, C, 128) >= kSymMinBlocks)
+    sym_product_rs<TQ, TV, TA, R, 128>(M, ld, n, Yt, out, scratch, ev, s);
+  else
+    sym_product_rs<TQ, TV, TA, R, 64>(M, ld, n, Yt, out, scratch, ev, s);
 }
 
 xm_problem::TimedLaunch* timed_launch(const xm_problem* p, int dtype, double bytes) {
@@ -446,81 +469,156 @@ void launch_sym(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStre
   sym_product<TQ, TV, TA, R>(Q, p->ld, p->n3, Yt, out, const_cast<xm_problem*>(p)->spmm_scratch, ev, s);
 }
 
-// ---- factored product (FP64): Q = A_rr + B Gm B^T, Gm = -G^{-1} -------------
+// ---- factored product: Q = A_rr + B Gm B^T, Gm = -G^{-1} --------------------
 // B = A_rt without the column of the anchored frame 0, G the grounded
 // Laplacian (Prop. "Scaled-Rotation-Only Formulation", App. A).  Q Yt is formed
-// without Q: W = B^T Yt (sparse, per frame), V = Gm W (the symmetric dense
-// product above on the (N-1)^2 matrix), out = A_rr Yt + B V (sparse, per
-// frame).  One wavefront per frame for the sparse parts, lanes over the frame's
-// co-visible frames, fixed-order wave sums: deterministic.
+// without Q in three passes:
+//   1. per frame i: out[i] = sum_{s in row i} A_rr[s] Yt[col s] and
+//      W[i-1] = sum_s A_rt[(col s, i)]^T Yt[col s] (i >= 1): both read the same
+//      gathered Yt rows, so they share one pass over the co-visibility pattern;
+//   2. V = Gm W, the symmetric dense product above on the (N-1)^2 matrix;
+//   3. per frame i: out[i] += sum_s A_rt[s] V[col s - 1] (col s >= 1).
+// One wavefront per frame, lanes over the frame's co-visible frames; the
+// factors are structure of arrays, so every factor load is coalesced across
+// the wave; Yt is first copied to rows padded to 16 bytes, so that a frame's
+// 3r values come in whole 16-byte loads.  Fixed-order wave sums: deterministic.
 
-// W[j-1][a] = sum_{s in row j} sum_c ArtT[s][c] Yt[3 col[s] + c][a], j >= 1
-template <int R>
-__global__ __launch_bounds__(kB) void fact_bt_kernel(int32_t N, const int32_t* __restrict__ row_ptr,
-                                                     const int32_t* __restrict__ col,
-                                                     const double* __restrict__ ArtT,
-                                                     const double* __restrict__ Yt, double* __restrict__ W) {
-  const int j = blockIdx.x * (kB / 64) + (threadIdx.x >> 6) + 1;
-  const int lane = threadIdx.x & 63;
-  if (j >= N) return;  // whole wavefronts only
-  double acc[R];
-#pragma unroll
-  for (int a = 0; a < R; ++a) acc[a] = 0.0;
-  for (int32_t s = row_ptr[j] + lane; s < row_ptr[j + 1]; s += 64) {
-    const int64_t i3 = 3 * static_cast<int64_t>(col[s]);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double b = ArtT[3 * static_cast<int64_t>(s) + c];
-      const double* y = Yt + (i3 + c) * R;
-#pragma unroll
-      for (int a = 0; a < R; ++a) acc[a] += b * y[a];
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < R; ++a) acc[a] = wave_sum(acc[a]);
-  if (lane == 0) {
-#pragma unroll
-    for (int a = 0; a < R; ++a) W[static_cast<int64_t>(j - 1) * R + a] = acc[a];
-  }
+template <typename T>
+struct V16;
+template <>
+struct V16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int K = 4;
+};
+template <>
+struct V16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int K = 2;
+};
+template <typename T, int R>
+constexpr int padded_row() {
+  return (3 * R + V16<T>::K - 1) / V16<T>::K * V16<T>::K;
 }
 
-// out[3i+c][a] = sum_{s in row i} (sum_d Arr[s][c][d] Yt[3 col[s] + d][a] + Art[s][c] V[col[s]-1][a])
-template <int R>
-__global__ __launch_bounds__(kB) void fact_out_kernel(int32_t N, const int32_t* __restrict__ row_ptr,
-                                                      const int32_t* __restrict__ col,
-                                                      const double* __restrict__ Arr,
-                                                      const double* __restrict__ Art,
-                                                      const double* __restrict__ Yt,
-                                                      const double* __restrict__ V, double* __restrict__ out) {
+// Ytp[j][e] = Yt[3j + e / R][e % R] for e < 3R, 0 for the padding
+template <typename T, int R>
+__global__ void pad_rows_kernel(const T* __restrict__ Yt, int32_t N, T* __restrict__ Ytp) {
+  constexpr int RP = padded_row<T, R>();
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (e >= static_cast<int64_t>(N) * RP) return;
+  const int64_t j = e / RP;
+  const int k = static_cast<int>(e - j * RP);
+  Ytp[e] = (k < 3 * R) ? Yt[j * 3 * R + k] : T(0);
+}
+
+// Each lane takes kFactU blocks of the row per step (64 apart), all their loads
+// issued before the arithmetic: the gathers are latency-bound otherwise.
+#ifndef XM_FACT_U
+#define XM_FACT_U 2
+#endif
+constexpr int kFactU = XM_FACT_U;
+
+template <typename T, int R>
+__global__ __launch_bounds__(kB) void fact_rows_kernel(int32_t N, int64_t S, const int32_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const T* __restrict__ fac, const T* __restrict__ Ytp,
+                                                       T* __restrict__ out, T* __restrict__ W) {
+  constexpr int RP = padded_row<T, R>();
+  constexpr int K = V16<T>::K;
+  typedef typename V16<T>::type vec;
   const int i = blockIdx.x * (kB / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= N) return;  // whole wavefronts only
-  double acc[3][R];
+  T ao[3][R], aw[R];
+#pragma unroll
+  for (int a = 0; a < R; ++a) {
+    aw[a] = T(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ao[c][a] = T(0);
+  }
+  const int32_t end = row_ptr[i + 1];
+  for (int32_t s0 = row_ptr[i] + lane; s0 < end; s0 += 64 * kFactU) {
+    T y[kFactU][RP], m[kFactU][9], t[kFactU][3];
+#pragma unroll
+    for (int u = 0; u < kFactU; ++u) {
+      const int32_t s = s0 + 64 * u;
+      const bool ok = s < end;  // a block past the row end contributes zero
+      const int32_t sc = ok ? s : s0;
+      const vec* yp = reinterpret_cast<const vec*>(Ytp + static_cast<int64_t>(col[sc]) * RP);
+#pragma unroll
+      for (int q = 0; q < RP / K; ++q) {
+        const vec v = yp[q];
+#pragma unroll
+        for (int k = 0; k < K; ++k) y[u][q * K + k] = v[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) m[u][k] = ok ? fac[k * S + sc] : T(0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t[u][c] = ok ? fac[(12 + c) * S + sc] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kFactU; ++u)
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int a = 0; a < R; ++a) {
+          const T yv = y[u][d * R + a];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) ao[c][a] += m[u][3 * c + d] * yv;
+          aw[a] += t[u][d] * yv;
+        }
+  }
+#pragma unroll
+  for (int a = 0; a < R; ++a) {
+    aw[a] = wave_sum(aw[a]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ao[c][a] = wave_sum(ao[c][a]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int a = 0; a < R; ++a) out[(3 * static_cast<int64_t>(i) + c) * R + a] = ao[c][a];
+    if (i > 0) {
+#pragma unroll
+      for (int a = 0; a < R; ++a) W[static_cast<int64_t>(i - 1) * R + a] = aw[a];
+    }
+  }
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kB) void fact_cols_kernel(int32_t N, int64_t S, const int32_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const T* __restrict__ fac, const T* __restrict__ V,
+                                                       T* __restrict__ out) {
+  const int i = blockIdx.x * (kB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= N) return;  // whole wavefronts only
+  T acc[3][R];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int a = 0; a < R; ++a) acc[c][a] = 0.0;
-  for (int32_t s = row_ptr[i] + lane; s < row_ptr[i + 1]; s += 64) {
-    const int j = col[s];
-    const double* y = Yt + 3 * static_cast<int64_t>(j) * R;
-    const double* m = Arr + 9 * static_cast<int64_t>(s);
+    for (int a = 0; a < R; ++a) acc[c][a] = T(0);
+  const int32_t end = row_ptr[i + 1];
+  for (int32_t s0 = row_ptr[i] + lane; s0 < end; s0 += 64 * kFactU) {
+    T v[kFactU][R], b[kFactU][3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int u = 0; u < kFactU; ++u) {
+      const int32_t s = s0 + 64 * u;
+      const int j = (s < end) ? col[s] : 0;
+      const bool ok = j > 0;  // frame 0 is anchored (no column of B); past the end: zero
+      const T* vp = V + static_cast<int64_t>(ok ? j - 1 : 0) * R;
 #pragma unroll
-      for (int a = 0; a < R; ++a) {
-        const double yv = y[d * R + a];
+      for (int a = 0; a < R; ++a) v[u][a] = vp[a];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c][a] += m[3 * c + d] * yv;
-      }
-    if (j > 0) {
-      const double* v = V + static_cast<int64_t>(j - 1) * R;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double b = Art[3 * static_cast<int64_t>(s) + c];
-#pragma unroll
-        for (int a = 0; a < R; ++a) acc[c][a] += b * v[a];
-      }
+      for (int c = 0; c < 3; ++c) b[u][c] = ok ? fac[(9 + c) * S + s] : T(0);
     }
+#pragma unroll
+    for (int u = 0; u < kFactU; ++u)
+#pragma unroll
+      for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c][a] += b[u][c] * v[u][a];
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -530,46 +628,66 @@ __global__ __launch_bounds__(kB) void fact_out_kernel(int32_t N, const int32_t* 
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int a = 0; a < R; ++a) out[(3 * static_cast<int64_t>(i) + c) * R + a] = acc[c][a];
+      for (int a = 0; a < R; ++a) out[(3 * static_cast<int64_t>(i) + c) * R + a] += acc[c][a];
   }
 }
 
-template <int R>
-void launch_factored(const xm_problem* p, const double* Yt, double* out, hipStream_t s) {
+// the factors of one precision: the sparse blocks (structure of arrays) and -G^{-1}
+template <typename T>
+struct Factors {
+  const T *fac, *Gm;
+};
+Factors<double> factors(const xm_problem* p, double*) { return {p->fac.ptr, p->Gm.ptr}; }
+Factors<float> factors(const xm_problem* p, float*) {
+  require(p->fac32.ptr != nullptr, XM_EINVAL, "the FP32 factors were not kept (XM_KEEP_F32)");
+  return {p->fac32.ptr, p->Gm32.ptr};
+}
+
+template <typename T, int R>
+void launch_factored(const xm_problem* p, const T* Yt, T* out, hipStream_t s) {
   auto* mp = const_cast<xm_problem*>(p);
+  const Factors<T> f = factors(p, static_cast<T*>(nullptr));
   const int32_t N = p->N, ng = N - 1;
-  const size_t per = static_cast<size_t>(ng) * R;
-  if (mp->fact_scratch.n < 2 * per) {
+  constexpr int RP = padded_row<T, R>();
+  // scratch, in doubles: padded Yt (N rows of at most 24 values), W, V (ng x 8 each)
+  const size_t cap = 24 * static_cast<size_t>(N) + 16 * static_cast<size_t>(ng);
+  if (mp->fact_scratch.n < cap) {
     XM_HIP(hipStreamSynchronize(s));
-    mp->fact_scratch.alloc(2 * 8 * static_cast<size_t>(ng));
+    mp->fact_scratch.alloc(cap);
   }
-  double* W = mp->fact_scratch.ptr;
-  double* Vv = W + per;
-  const double S = static_cast<double>(p->nnzb);
+  T* Ytp = reinterpret_cast<T*>(mp->fact_scratch.ptr);
+  T* W = reinterpret_cast<T*>(mp->fact_scratch.ptr + 24 * static_cast<size_t>(N));
+  T* Vv = W + static_cast<size_t>(ng) * R;
+  const int64_t S = p->nnzb;
   xm_problem::TimedLaunch* ev =
-      timed_launch(p, XM_STATS_FACTORED, 0.5 * static_cast<double>(ng) * (ng + 1) * 8.0 + S * 15.0 * 8.0);
+      timed_launch(p, sizeof(T) == 8 ? XM_STATS_FACTORED : XM_STATS_FACTORED + 1,
+                   (0.5 * static_cast<double>(ng) * (ng + 1) + static_cast<double>(S) * 15.0) * sizeof(T));
   if (ev) XM_HIP(hipEventRecord(ev->start, s));
+  hipLaunchKernelGGL((pad_rows_kernel<T, R>), dim3(cdiv(static_cast<size_t>(N) * RP, kB)), dim3(kB), 0, s, Yt, N,
+                     Ytp);
+  XM_LAUNCH_CHECK("pad_rows_kernel");
   const unsigned gb = cdiv(N, kB / 64);
-  hipLaunchKernelGGL((fact_bt_kernel<R>), dim3(gb), dim3(kB), 0, s, N, p->row_ptr.ptr, p->col.ptr, p->ArtT.ptr,
-                     Yt, W);
-  XM_LAUNCH_CHECK("fact_bt_kernel");
-  sym_product<double, double, double, R>(p->Gm.ptr, p->ldg, ng, W, Vv, mp->spmm_scratch, nullptr, s);
-  hipLaunchKernelGGL((fact_out_kernel<R>), dim3(gb), dim3(kB), 0, s, N, p->row_ptr.ptr, p->col.ptr, p->Arr.ptr,
-                     p->Art.ptr, Yt, Vv, out);
-  XM_LAUNCH_CHECK("fact_out_kernel");
+  hipLaunchKernelGGL((fact_rows_kernel<T, R>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr, f.fac,
+                     Ytp, out, W);
+  XM_LAUNCH_CHECK("fact_rows_kernel");
+  sym_product<T, T, T, R>(f.Gm, p->ldg, ng, W, Vv, mp->spmm_scratch, nullptr, s);
+  hipLaunchKernelGGL((fact_cols_kernel<T, R>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr, f.fac,
+                     Vv, out);
+  XM_LAUNCH_CHECK("fact_cols_kernel");
   if (ev) XM_HIP(hipEventRecord(ev->stop, s));
 }
 
-void dispatch_factored(const xm_problem* p, const double* Yt, int r, double* out, hipStream_t s) {
+template <typename T>
+void dispatch_factored(const xm_problem* p, const T* Yt, int r, T* out, hipStream_t s) {
   switch (r) {
-    case 1: launch_factored<1>(p, Yt, out, s); return;
-    case 2: launch_factored<2>(p, Yt, out, s); return;
-    case 3: launch_factored<3>(p, Yt, out, s); return;
-    case 4: launch_factored<4>(p, Yt, out, s); return;
-    case 5: launch_factored<5>(p, Yt, out, s); return;
-    case 6: launch_factored<6>(p, Yt, out, s); return;
-    case 7: launch_factored<7>(p, Yt, out, s); return;
-    case 8: launch_factored<8>(p, Yt, out, s); return;
+    case 1: launch_factored<T, 1>(p, Yt, out, s); return;
+    case 2: launch_factored<T, 2>(p, Yt, out, s); return;
+    case 3: launch_factored<T, 3>(p, Yt, out, s); return;
+    case 4: launch_factored<T, 4>(p, Yt, out, s); return;
+    case 5: launch_factored<T, 5>(p, Yt, out, s); return;
+    case 6: launch_factored<T, 6>(p, Yt, out, s); return;
+    case 7: launch_factored<T, 7>(p, Yt, out, s); return;
+    case 8: launch_factored<T, 8>(p, Yt, out, s); return;
     default: throw Error(XM_EINVAL, "rank must be in [1, 8]");
   }
 }
@@ -610,7 +728,7 @@ void spmm_yt<double>(const xm_problem* p, xm_dtype qtype, const double* Yt, int 
   require(qtype == XM_F64, XM_EINVAL, "FP64 vectors are multiplied with the FP64 Q");
   require(role == XM_ROLE_RESIDUAL || role == XM_ROLE_CURVATURE, XM_EINVAL, "unknown product role");
   if (p->spmm_kind[role][XM_F64] == XM_SPMM_FACTORED) {
-    dispatch_factored(p, Yt, r, out, s);
+    dispatch_factored<double>(p, Yt, r, out, s);
     return;
   }
   require(p->Q64.ptr != nullptr, XM_EINVAL, "the dense FP64 Q was not kept");
@@ -621,6 +739,10 @@ template <>
 void spmm_yt<float>(const xm_problem* p, xm_dtype qtype, const float* Yt, int r, float* out, hipStream_t s,
                     int role) {
   require(role == XM_ROLE_RESIDUAL || role == XM_ROLE_CURVATURE, XM_EINVAL, "unknown product role");
+  if (qtype == XM_F32 && p->spmm_kind[role][XM_F32] == XM_SPMM_FACTORED) {
+    dispatch_factored<float>(p, Yt, r, out, s);
+    return;
+  }
   if (qtype == XM_F32) {
     require(p->Q32.ptr != nullptr, XM_EINVAL, "the FP32 copy of Q was not kept (XM_KEEP_F32)");
     dispatch_r<float, float, float>(p, p->Q32.ptr, Yt, r, out, s, role);

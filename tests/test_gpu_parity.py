@@ -148,28 +148,36 @@ def test_spmm_parity(r):
 
 @pytest.fixture(scope="module")
 def tiled_problem():
-    # 3N = 2100: five 512-row slabs (the last one 52 rows), three FP32 column
-    # chunks of 1024 and five FP64 chunks of 512, each with a ragged tail
+    # 3N = 2100: 64-row slabs (the last one 52 rows; a matrix this small gets
+    # the smallest slabs), three FP32 column chunks of 1024 and five FP64
+    # chunks of 512, each with a ragged tail
     sc = scenes.random_scene(700, 12000, L=4, sigma=0.02, seed=17)
-    return sc, _oracle_Q(sc)
+    Q, (A_rr, A_rt, A_tt) = odm.q_block_elimination(sc.N, sc.M, sc.frame, sc.landmark, sc.u, sc.w,
+                                                     return_parts=True)
+    B = np.abs(A_rt[:, 1:])
+    absfac = np.abs(A_rr) + B @ np.abs(np.linalg.inv(A_tt[1:, 1:])) @ B.T
+    return sc, Q, absfac
 
 
 @pytest.mark.parametrize("kind", ["upper", "full", "factored"])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_spmm_kernels_across_tiles(tiled_problem, kind, dtype):
-    if kind == "factored" and dtype != "f64":
-        pytest.skip("the factored product is FP64 only")
+    if kind == "factored" and dtype == "bf16":
+        pytest.skip("no BF16 factored product")
     _say(f"case: spmm {kind} {dtype} 3N=2100")
-    sc, Qo = tiled_problem
+    sc, Qo, absfac = tiled_problem
     P = _build(sc, keep=("f32", "bf16"))
     P.set_spmm_kind(dtype, kind)
     tol = {"f64": 1e-13, "f32": 3e-6, "bf16": 1e-2}[dtype]
+    # the factored form sums |A_rr| + |B| |G^-1| |B|^T in magnitude, not |Q|:
+    # its rounding error scales with that sum (forward error of the products)
+    mag = absfac if kind == "factored" else np.abs(Qo)
     for r in (1, 2, 5, 8):
         rng = np.random.default_rng(100 + r)
         Y = rng.standard_normal((r, 3 * sc.N))
         ref = Y @ Qo
         out = P.spmm(torch.from_numpy(Y).cuda(), dtype).cpu().numpy()
-        scale = np.abs(Y).max() * np.abs(Qo).sum(0).max()
+        scale = np.abs(Y).max() * mag.sum(0).max()
         assert np.abs(out - ref).max() <= tol * scale, (r, np.abs(out - ref).max() / scale)
         # deterministic: a second product is bitwise identical
         out2 = P.spmm(torch.from_numpy(Y).cuda(), dtype).cpu().numpy()
@@ -311,6 +319,8 @@ def test_unordered_and_sequential_configs(cfg):
     xm = _xm()
     sc = scenes.make_scene(cfg, 0)
     P = _build(sc, keep=("f32", "bf16"))
+    # FP32 Q upper triangle under 256 MiB: dense curvature products by default
+    assert P.spmm_kind("f32", "curvature") == "upper" and P.spmm_kind("f64", "curvature") == "factored"
     rng = np.random.default_rng(1)
     rows = np.sort(rng.choice(3 * sc.N, size=16, replace=False))
     Qo = odm.q_rows(sc.N, sc.M, sc.frame, sc.landmark, sc.u, sc.w, rows)
@@ -351,12 +361,34 @@ def test_large_workload_sampled_rows_and_certified_solves():
     xm = _xm()
     sc = scenes.make_scene("large", 0)
     P = _build(sc, keep=("f32",))
+    # 1.9 GB FP32 upper triangle: FP32 curvature products from the factors
+    assert P.spmm_kind("f32", "curvature") == "factored" and P.spmm_kind("f32", "residual") == "upper"
     rng = np.random.default_rng(0)
     rows = np.sort(rng.choice(3 * sc.N, size=12, replace=False))
     rows[0] = 0
     Qo = odm.q_rows(sc.N, sc.M, sc.frame, sc.landmark, sc.u, sc.w, rows)
     Qg = np.stack([P.Q_rows(int(r), 1).cpu().numpy()[0] for r in rows])
     assert np.abs(Qg - Qo).max() <= 1e-9 * np.abs(Qo).max()
+    # the products at full size, in the launch shapes the solve uses (dense
+    # upper-triangle kernel over Q: 256-row slabs; factored product: G^{-1}
+    # through 128-row (FP64) and 64-row (FP32) slabs), on the sampled columns:
+    # (Y Q)[:, j] = Y Q[j, :]^T by symmetry
+    # bars relative to |Y| max * the largest absolute row sum of Q, as in the
+    # tiled test; the factored form sums terms up to ~30x larger than Q's
+    # entries (its error scales with them), hence its looser bars
+    for r in (1, 5):
+        Y = rng.standard_normal((r, 3 * sc.N))
+        ref = Y @ Qo.T
+        scale = np.abs(Y).max() * np.abs(Qo).sum(1).max()
+        for dtype, kind, tol in (("f64", "upper", 1e-13), ("f64", "factored", 3e-12),
+                                 ("f32", "upper", 3e-6), ("f32", "factored", 1e-4)):
+            P.set_spmm_kind(dtype, kind, role="residual")
+            out = P.spmm(torch.from_numpy(Y).cuda(), dtype).cpu().numpy()[:, rows]
+            err = np.abs(out - ref).max() / scale
+            _say(f"  spmm {dtype} {kind} r={r}: err / scale {err:.2e}")
+            assert err <= tol, (dtype, kind, r, err)
+        P.set_spmm_kind("f64", "upper", role="residual")
+        P.set_spmm_kind("f32", "upper", role="residual")
     Y32, i32 = P.solve(xm.SolveOptions(compute="f32"))
     _say(f"  f32: r={i32['r']} cert={i32['certified']} outer={i32['outer_iters']} inner={i32['inner_iters']} "
          f"solve_ms={i32['solve_ms']:.0f} cert_ms={i32['cert_ms']:.0f}")
