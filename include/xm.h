@@ -353,23 +353,27 @@ xm_status xm_adjoint(xm_problem* p, const double* R, const double* s, const doub
                      double cg_tol, int32_t cg_max, xm_adjoint_info* info, void* stream);
 
 /*
- * Measurement hooks for the Y Q product kernel (the HBM-bound kernel of the
+ * Measurement hooks for the Y Q product kernels (the HBM-bound kernels of the
  * local solver and of the Lanczos certificate).  With timing enabled, every
- * launch of the product kernel on a handle is bracketed by two HIP events on
- * the stream it runs on.  xm_spmm_stats synchronises those events and returns,
- * per product (index = xm_dtype for the dense kernels of each stored precision,
- * 3 and 4 for the FP64 and FP32 factored products), the number of launches, their total device
- * time and the algorithmic bytes of one launch (averaged over the recorded
- * launches): the values the product must read (see xm_set_spmm_kind) times
- * their size.  For the dense kernels only the main product kernel is bracketed,
- * not the pass that adds its partial sums; the factored product is bracketed
- * whole (its three kernels).  reset != 0 forgets the recorded launches.
+ * product on a handle is bracketed by HIP events on the stream it runs on.
+ * xm_spmm_stats synchronises those events and returns, per slot, the number of
+ * launches, their total device time and the algorithmic bytes of one launch
+ * (averaged over the recorded launches): the values the product must read
+ * (see xm_set_spmm_kind) times their size.  Slots: xm_dtype (0..2) for the
+ * dense kernel over the stored Q of that precision (the main kernel only, not
+ * the pass that adds its partial sums); XM_STATS_FACTORED (3) and 4 for the
+ * FP64 and FP32 factored products, bracketed whole (all their kernels);
+ * XM_STATS_GINV (5) and 6 for the symmetric dense kernel over G^{-1} inside
+ * the FP64 and FP32 factored products (that kernel alone).  reset != 0
+ * forgets the recorded launches.
  */
-#define XM_STATS_FACTORED 3   /* FP64 factored product; 4: its FP32 form */
+#define XM_STATS_FACTORED 3
+#define XM_STATS_GINV 5
+#define XM_STATS_SLOTS 7
 typedef struct {
-  int64_t launches[5];
-  double total_ms[5];
-  double bytes_per_launch[5];
+  int64_t launches[XM_STATS_SLOTS];
+  double total_ms[XM_STATS_SLOTS];
+  double bytes_per_launch[XM_STATS_SLOTS];
 } xm_spmm_counters;
 xm_status xm_spmm_timing(xm_problem* p, int32_t enable);
 xm_status xm_spmm_stats(xm_problem* p, xm_spmm_counters* out, int32_t reset);

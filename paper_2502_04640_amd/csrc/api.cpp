@@ -245,7 +245,7 @@ xm_status xm_spmm_stats(xm_problem* p, xm_spmm_counters* out, int32_t reset) {
     out->total_ms[e.dtype] += ms;
     out->bytes_per_launch[e.dtype] += e.bytes;
   }
-  for (int d = 0; d < 5; ++d)
+  for (int d = 0; d < XM_STATS_SLOTS; ++d)
     if (out->launches[d] > 0) out->bytes_per_launch[d] /= static_cast<double>(out->launches[d]);
   if (reset) p->events_used = 0;
   return XM_OK;

@@ -383,22 +383,32 @@ __global__ __launch_bounds__(kB) void sweep_panel_kernel(const double* __restric
 // forms a 32 x 32 quarter as 2 x 2 blocks of v_mfma_f64_16x16x4f64 over 16
 // k-steps: lane l supplies A-operand [i = l % 16][k = l / 16] and B-operand
 // [k = l / 16][j = l % 16]; register q of the result holds [l / 16 + 4 q][l % 16].
+// The tile of A is loaded into registers first (its HBM latency overlaps the
+// panel staging), the rank-64 product is accumulated from zero and subtracted
+// once at the end (one rounding at the scale of A).  The panels go through LDS
+// in chunks of kSweepKC rows, double-buffered: the next chunk's loads are in
+// flight while the current one is multiplied.
+// Workgroup w takes tile tiles[w mod 8][w / 8] of a list cut into 8 contiguous
+// runs, one per XCD (w runs on XCD w mod 8), each run ordered by 8 x 8 blocks
+// of tiles, so that the panel slices a run needs at a time stay in its L2.
 typedef double v4d __attribute__((ext_vector_type(4)));
-// The tile of A is loaded into registers first, so its HBM latency overlaps the
-// panel staging and the matrix-core work; the panels go through LDS in
-// k-chunks of kSweepKC rows (smaller chunks: less LDS, more workgroups per CU).
+#ifndef XM_SWEEP_SB
+#define XM_SWEEP_SB 8
+#endif
 #ifndef XM_SWEEP_KC
 #define XM_SWEEP_KC 16
 #endif
 constexpr int kSweepKC = XM_SWEEP_KC;
 __global__ __launch_bounds__(kB) void sweep_update_kernel(double* A, int32_t lda, int32_t n,
                                                           const double* __restrict__ Ct,
-                                                          const double* __restrict__ Pt, int32_t ldt,
-                                                          int32_t nb) {
-  if (blockIdx.x < blockIdx.y) return;  // lower tile: not kept
-  __shared__ double Cs[kSweepKC][64];
-  __shared__ double Ps[kSweepKC][64];
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+                                                          const double* __restrict__ Pt, int32_t ldt, int32_t nb,
+                                                          const int32_t* __restrict__ tiles, int32_t ntiles) {
+  const int per = (ntiles + 7) / 8;
+  const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (idx >= ntiles) return;
+  __shared__ double Cs[2][kSweepKC][64];
+  __shared__ double Ps[2][kSweepKC][64];
+  const int i0 = 64 * tiles[2 * idx], j0 = 64 * tiles[2 * idx + 1];
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
@@ -419,23 +429,47 @@ __global__ __launch_bounds__(kB) void sweep_update_kernel(double* A, int32_t lda
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int kc = 0; kc < kNB; kc += kSweepKC) {
-    if (kc > 0) __syncthreads();  // the previous chunk has been consumed
-    for (int e = t; e < kSweepKC * 64; e += kB) {
-      const int p = e >> 6, c = e & 63;
-      const int pp = kc + p;
-      Cs[p][c] = (pp < nb && i0 + c < n) ? Ct[static_cast<int64_t>(pp) * ldt + i0 + c] : 0.0;
-      Ps[p][c] = (pp < nb && j0 + c < n) ? Pt[static_cast<int64_t>(pp) * ldt + j0 + c] : 0.0;
+  // panel chunks of kSweepKC rows, double-buffered: thread t stages entries
+  // t + kB m (m < kSweepKC * 64 / kB) of the chunk
+  constexpr int kPer = kSweepKC * 64 / kB;
+  double rc[kPer], rp[kPer];
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = t + kB * m;
+      const int pp = kc + (e >> 6), c = e & 63;
+      rc[m] = (pp < nb && i0 + c < n) ? Ct[static_cast<int64_t>(pp) * ldt + i0 + c] : 0.0;
+      rp[m] = (pp < nb && j0 + c < n) ? Pt[static_cast<int64_t>(pp) * ldt + j0 + c] : 0.0;
     }
-    __syncthreads();
-#pragma unroll 4
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = t + kB * m;
+      Cs[buf][e >> 6][e & 63] = rc[m];
+      Ps[buf][e >> 6][e & 63] = rp[m];
+    }
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+#pragma unroll
+  for (int ch = 0; ch < kNB / kSweepKC; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < kNB / kSweepKC;
+    if (more) fetch((ch + 1) * kSweepKC);
+#pragma unroll
     for (int k = 0; k < kSweepKC; k += 4) {
-      const double a0 = Cs[k + lk][wi + lr], a1 = Cs[k + lk][wi + 16 + lr];
-      const double b0 = Ps[k + lk][wj + lr], b1 = Ps[k + lk][wj + 16 + lr];
+      const double a0 = Cs[buf][k + lk][wi + lr], a1 = Cs[buf][k + lk][wi + 16 + lr];
+      const double b0 = Ps[buf][k + lk][wj + lr], b1 = Ps[buf][k + lk][wj + 16 + lr];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    if (more) {
+      stash(buf ^ 1);
+      __syncthreads();
     }
   }
 #pragma unroll
@@ -448,6 +482,21 @@ __global__ __launch_bounds__(kB) void sweep_update_kernel(double* A, int32_t lda
         const int j = j0 + wj + 16 * b + lr;
         if (i < n && j < n) A[static_cast<int64_t>(i) * lda + j] = g[a][b][q] - acc[a][b][q];
       }
+}
+
+// the upper tiles (I <= J) of a T x T tiling, blocked by SB x SB tiles in
+// row-major block order, as (I, J) pairs
+std::vector<int32_t> sweep_tile_list(int T) {
+  constexpr int SB = XM_SWEEP_SB;
+  std::vector<int32_t> out;
+  for (int bi = 0; bi < T; bi += SB)
+    for (int bj = bi; bj < T; bj += SB)
+      for (int I = bi; I < std::min(T, bi + SB); ++I)
+        for (int J = std::max(I, bj); J < std::min(T, bj + SB); ++J) {
+          out.push_back(I);
+          out.push_back(J);
+        }
+  return out;
 }
 
 __global__ void sweep_finish_kernel(double* A, int32_t lda, int32_t n, int32_t k0, int32_t nb,
@@ -1141,7 +1190,11 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
     require(dscale > 0.0, XM_EGRAPH, "the grounded Laplacian has no positive diagonal entry");
     DevBuf<double> Dinv(kNB * kNB);
     DevBuf<double> Ct(static_cast<size_t>(kNB) * P->ldg), Pt(static_cast<size_t>(kNB) * P->ldg);
-    const unsigned tiles = cdiv(ng, 64);
+    const std::vector<int32_t> htiles = sweep_tile_list(static_cast<int>(cdiv(ng, 64)));
+    const int32_t ntiles = static_cast<int32_t>(htiles.size() / 2);
+    DevBuf<int32_t> tiles(htiles.size());
+    XM_HIP(hipMemcpy(tiles.ptr, htiles.data(), htiles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    const unsigned ublocks = 8 * cdiv(ntiles, 8);
     LaunchTimer t_sweep;
     for (int32_t k0 = 0; k0 < ng; k0 += kNB) {
       const int32_t nb = std::min(kNB, ng - k0);
@@ -1152,8 +1205,8 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
                          Dinv.ptr, Ct.ptr, Pt.ptr, P->ldg);
       XM_LAUNCH_CHECK("sweep_panel_kernel");
       t_sweep.start(s);
-      hipLaunchKernelGGL(sweep_update_kernel, dim3(tiles, tiles), dim3(kB), 0, s, P->Gm.ptr, P->ldg, ng, Ct.ptr,
-                         Pt.ptr, P->ldg, nb);
+      hipLaunchKernelGGL(sweep_update_kernel, dim3(ublocks), dim3(kB), 0, s, P->Gm.ptr, P->ldg, ng, Ct.ptr,
+                         Pt.ptr, P->ldg, nb, tiles.ptr, ntiles);
       XM_LAUNCH_CHECK("sweep_update_kernel");
       t_sweep.stop(s);
       hipLaunchKernelGGL(sweep_finish_kernel, dim3(cdiv(ng, kB), nb), dim3(kB), 0, s, P->Gm.ptr, P->ldg, ng, k0,

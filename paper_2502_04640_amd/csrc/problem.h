@@ -1,6 +1,7 @@
 // The problem handle and the internal launch interfaces of libxm.
 #pragma once
 
+#include <deque>
 #include <memory>
 
 #include "common.h"
@@ -70,7 +71,7 @@ struct xm_problem {
   int spmm_kind[2][3] = {{XM_SPMM_UPPER, XM_SPMM_UPPER, XM_SPMM_FULL},
                          {XM_SPMM_FACTORED, XM_SPMM_UPPER, XM_SPMM_FULL}};
   bool timing = false;
-  std::vector<TimedLaunch> events;
+  std::deque<TimedLaunch> events;  // deque: a pointer to one stays valid while more are added
   size_t events_used = 0;
 
   ~xm_problem();

@@ -670,7 +670,9 @@ void launch_factored(const xm_problem* p, const T* Yt, T* out, hipStream_t s) {
   hipLaunchKernelGGL((fact_rows_kernel<T, R>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr, f.fac,
                      Ytp, out, W);
   XM_LAUNCH_CHECK("fact_rows_kernel");
-  sym_product<T, T, T, R>(f.Gm, p->ldg, ng, W, Vv, mp->spmm_scratch, nullptr, s);
+  xm_problem::TimedLaunch* evg = timed_launch(p, sizeof(T) == 8 ? XM_STATS_GINV : XM_STATS_GINV + 1,
+                                              0.5 * static_cast<double>(ng) * (ng + 1) * sizeof(T));
+  sym_product<T, T, T, R>(f.Gm, p->ldg, ng, W, Vv, mp->spmm_scratch, evg, s);
   hipLaunchKernelGGL((fact_cols_kernel<T, R>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr, f.fac,
                      Vv, out);
   XM_LAUNCH_CHECK("fact_cols_kernel");
