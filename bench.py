@@ -31,9 +31,12 @@ METRIC = "time-to-certified-optimum (s) + BSR SpMM GB/s, FP32 vs FP64, N=10k fra
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6   # MI355X FP64, vector and matrix
 # HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain
-# copy kernel (profiles/hbm_traffic_spmm_sym_f32_large.md); valid for the large
-# workload and the kernel as it was profiled -- re-measure after changing it.
-PMC_TRAFFIC_BYTES = {("large", "spmm_sym_kernel (f32 Q)"): 1.981e9}
+# copy kernel (profiles/hbm_traffic_sweep_update_large.md,
+# profiles/hbm_traffic_spmm_sym_f32_large.md); valid for the large workload and
+# the kernels as they were profiled -- re-measure after changing one.
+PMC_TRAFFIC_BYTES = {("large", "sweep_update_kernel"): 0.903e9,
+                     ("large", "spmm_sym_kernel (f32 Q)"): 1.981e9,
+                     ("large", "spmm_sym_kernel (f32 G^-1, in the factored product)"): 0.248e9}
 
 
 def log(msg):
@@ -266,6 +269,11 @@ def main():
         "iters": {"outer": last["outer_iters"], "inner": last["inner_iters"], "spmm": last["spmm_count"],
                   "lanczos": last["lanczos_iters"], "stair_steps": last["stair_steps"]},
         "spmm_GBps": {k: (round(v, 1) if v else None) for k, v in spmm_gbs.items()},
+        # the metric's SpMM: the Y Q product over the stored FP32 Q (residual products)
+        "spmm_roofline": ({"kernel": names["f32"], "bound": "hbm", "achieved": round(spmm_gbs["f32"], 1),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(spmm_gbs["f32"] / HBM_PEAK_GBS, 4),
+                           "traffic": PMC_TRAFFIC_BYTES.get((args.workload, names["f32"]))}
+                          if spmm_gbs.get("f32") else None),
         "spmm_launches": {k: stats[k]["launches"] for k in stats},
         "spmm_kernel": {f"{d} {role}": P.spmm_kind(d, role) for d in ("f64", "f32") for role in ("residual", "curvature")},
         "roofline": roof,
