@@ -127,14 +127,28 @@ __global__ void zapply_scaled_kernel(int32_t N, const double* __restrict__ Lam, 
 }
 
 // c[b] = <V[b], w> (one block per basis vector)
+// part[b][g] = sum over segment g of V[b][i] w[i]  (grid: basis vector b x
+// segment g, so that a few dozen vectors still fill the chip)
+constexpr int kDotSeg = 16;
 __global__ __launch_bounds__(kB) void multidot_kernel(const double* __restrict__ V, int64_t n,
-                                                      const double* __restrict__ w, double* __restrict__ c) {
+                                                      const double* __restrict__ w, double* __restrict__ part) {
+  const int64_t seg = (n + kDotSeg - 1) / kDotSeg;
+  const int64_t i0 = blockIdx.y * seg, i1 = std::min(n, i0 + seg);
   const double* Vb = V + static_cast<int64_t>(blockIdx.x) * n;
   double v[1] = {0.0};
-  for (int64_t i = threadIdx.x; i < n; i += kB) v[0] += Vb[i] * w[i];
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kB) v[0] += Vb[i] * w[i];
   __shared__ double lds[kB / 64];
   block_sum<1>(v, lds);
-  if (threadIdx.x == 0) c[blockIdx.x] = v[0];
+  if (threadIdx.x == 0) part[blockIdx.x * kDotSeg + blockIdx.y] = v[0];
+}
+
+// c[b] = sum_g part[b][g], in segment order
+__global__ void multidot_sum_kernel(const double* __restrict__ part, int nv, double* __restrict__ c) {
+  const int b = blockIdx.x * kB + threadIdx.x;
+  if (b >= nv) return;
+  double t = 0.0;
+  for (int g = 0; g < kDotSeg; ++g) t += part[b * kDotSeg + g];
+  c[b] = t;
 }
 
 // w[i] += sign * sum_b c[b] V[b][i]
@@ -257,9 +271,22 @@ void launch_lambda(int32_t N, const double* Yt, const double* G, double* Lam, do
 
 }  // namespace
 
+// The solver reads a few hundred partial sums per iteration: through a pinned
+// (page-locked) staging buffer, one per host thread, the copy is a single DMA
+// instead of a staged pageable transfer.  The buffer lives until the process
+// ends (it is not freed at thread exit, when the runtime may be gone).
 void read_partials(const double* dev, int blocks, int nq, double* out, hipStream_t s) {
-  std::vector<double> h(static_cast<size_t>(blocks) * nq);
-  XM_HIP(hipMemcpyAsync(h.data(), dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  static thread_local double* h = nullptr;
+  static thread_local size_t cap = 0;
+  const size_t n = static_cast<size_t>(blocks) * nq;
+  if (n > cap) {
+    void* ptr = nullptr;
+    XM_HIP(hipHostMalloc(&ptr, n * sizeof(double), hipHostMallocDefault));
+    if (h) (void)hipHostFree(h);
+    h = static_cast<double*>(ptr);
+    cap = n;
+  }
+  XM_HIP(hipMemcpyAsync(h, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
   XM_HIP(hipStreamSynchronize(s));
   for (int q = 0; q < nq; ++q) {
     double acc = 0.0;
@@ -303,11 +330,16 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
   DevBuf<double> V(static_cast<size_t>(cap) * n), w(n), Qx(n), yv(n), c1(cap), c2(cap), alpha(max_iter),
       beta(max_iter);
   const unsigned gb = cdiv(n, kB);
+  DevBuf<double> dpart(static_cast<size_t>(cap) * kDotSeg);
+  auto multidot = [&](int nv, double* c) {  // c = V[0..nv) w
+    hipLaunchKernelGGL(multidot_kernel, dim3(nv, kDotSeg), dim3(kB), 0, s, V.ptr, n, w.ptr, dpart.ptr);
+    hipLaunchKernelGGL(multidot_sum_kernel, dim3(cdiv(nv, kB)), dim3(kB), 0, s, dpart.ptr, nv, c);
+  };
   auto orthogonalize = [&](int nv) {  // w -= V[0..nv) (V^T w), twice
     if (nv == 0) return;
-    hipLaunchKernelGGL(multidot_kernel, dim3(nv), dim3(kB), 0, s, V.ptr, n, w.ptr, c1.ptr);
+    multidot(nv, c1.ptr);
     hipLaunchKernelGGL(multiaxpy_kernel, dim3(gb), dim3(kB), 0, s, V.ptr, nv, n, c1.ptr, -1.0, w.ptr);
-    hipLaunchKernelGGL(multidot_kernel, dim3(nv), dim3(kB), 0, s, V.ptr, n, w.ptr, c2.ptr);
+    multidot(nv, c2.ptr);
     hipLaunchKernelGGL(multiaxpy_kernel, dim3(gb), dim3(kB), 0, s, V.ptr, nv, n, c2.ptr, -1.0, w.ptr);
     XM_LAUNCH_CHECK("orthogonalize");
   };
