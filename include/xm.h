@@ -135,7 +135,10 @@ xm_status xm_build_stats(const xm_problem* p, xm_kernel_stat* out, int32_t cap, 
 
 /*
  * Copy rows [row0, row0 + nrows) of the FP64 Q into `out` (device, row-major
- * [nrows][3N]).  For checks against a reference.  Synchronises `stream`.
+ * [nrows][3N]), rows and columns in frame-index order (the library stores Q
+ * with its frames in a Cuthill-McKee order of the co-visibility graph and
+ * gathers the rows back).  For checks against a reference.  Synchronises
+ * `stream`.
  */
 xm_status xm_get_Q_rows(const xm_problem* p, int32_t row0, int32_t nrows, double* out,
                         void* stream);

@@ -91,8 +91,7 @@ xm_status xm_get_Q_rows(const xm_problem* p, int32_t row0, int32_t nrows, double
   if (row0 < 0 || nrows < 0 || row0 + static_cast<int64_t>(nrows) > p->n3) return fail(XM_EINVAL, "row range out of bounds");
   if (nrows == 0) return XM_OK;
   hipStream_t s = as_stream(stream);
-  XM_HIP(hipMemcpy2DAsync(out, p->n3 * sizeof(double), p->Q64.ptr + static_cast<int64_t>(row0) * p->ld,
-                          p->ld * sizeof(double), p->n3 * sizeof(double), nrows, hipMemcpyDeviceToDevice, s));
+  xm::get_q_rows(p, row0, nrows, out, s);
   XM_HIP(hipStreamSynchronize(s));
   return XM_OK;
   XM_API_CATCH

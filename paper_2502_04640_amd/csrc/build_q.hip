@@ -151,8 +151,8 @@ __global__ void segment_starts_kernel(const uint32_t* __restrict__ keys, const i
 __global__ __launch_bounds__(kB) void reduce_blocks_kernel(
     const int64_t* __restrict__ seg_start, const uint32_t* __restrict__ seg_key, int64_t S, int32_t N,
     const uint64_t* __restrict__ vals, const double* __restrict__ u_s, const double* __restrict__ w_s,
-    const int32_t* __restrict__ lm_s, const double* __restrict__ Wl, double* Q, int32_t ld,
-    double* Art, double* Att, double* fac) {
+    const int32_t* __restrict__ lm_s, const double* __restrict__ Wl, const int32_t* __restrict__ pos, double* Q,
+    int32_t ld, double* Art, double* Att, double* fac) {
   const int64_t s = static_cast<int64_t>(blockIdx.x) * (kB / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (s >= S) return;
@@ -180,8 +180,8 @@ __global__ __launch_bounds__(kB) void reduce_blocks_kernel(
   if (lane == 0) {
     const uint32_t key = seg_key[s];
     const int64_t i = key / static_cast<uint32_t>(N), j = key % static_cast<uint32_t>(N);
-    if (Q) {
-      double* Qb = Q + (3 * i) * static_cast<int64_t>(ld) + 3 * j;
+    if (Q) {  // Q is stored in the frame order: block (pos[i], pos[j])
+      double* Qb = Q + (3 * static_cast<int64_t>(pos[i])) * ld + 3 * static_cast<int64_t>(pos[j]);
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -574,22 +574,24 @@ __global__ __launch_bounds__(kB) void diag_max_kernel(const double* __restrict__
 }
 
 // q_kk = tr(Q_kk) / 3 per frame (the preconditioner of the local solver)
-__global__ void diag_block_kernel(const double* __restrict__ Q, int32_t N, int32_t ld, double* __restrict__ q) {
+__global__ void diag_block_kernel(const double* __restrict__ Q, int32_t N, int32_t ld,
+                                  const int32_t* __restrict__ pos, double* __restrict__ q) {
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= N) return;
-  const int64_t i = 3 * static_cast<int64_t>(k);
+  const int64_t i = 3 * static_cast<int64_t>(pos[k]);
   q[k] = (Q[i * ld + i] + Q[(i + 1) * ld + i + 1] + Q[(i + 2) * ld + i + 2]) / 3.0;
 }
 
 // Q_kk^{1/2}, Q_kk^{-1/2} by a cyclic Jacobi eigendecomposition of each 3x3
 // diagonal block; eigenvalues are floored at 1e-12 of their block's largest so
 // that a degenerate block still gives an SPD scaling.  ext[k] = (min, max) eig.
-__global__ void block_sqrt_kernel(const double* __restrict__ Q, int32_t N, int32_t ld, double* __restrict__ Dh,
+__global__ void block_sqrt_kernel(const double* __restrict__ Q, int32_t N, int32_t ld,
+                                  const int32_t* __restrict__ pos, double* __restrict__ Dh,
                                   double* __restrict__ Dmh, double* __restrict__ ext) {
   const int k = blockIdx.x * kB + threadIdx.x;
   if (k >= N) return;
   double A[3][3], V[3][3];
-  const int64_t i0 = 3 * static_cast<int64_t>(k);
+  const int64_t i0 = 3 * static_cast<int64_t>(pos[k]);
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) {
       A[a][b] = 0.5 * (Q[(i0 + a) * ld + i0 + b] + Q[(i0 + b) * ld + i0 + a]);
@@ -815,8 +817,8 @@ __global__ __launch_bounds__(kB) void group_fill_kernel(int32_t N, const int32_t
 // i.e. the 48 output rows of the group are a dense (48 x |union|) coefficient
 // block (zeros where a frame does not see a union frame) times the gathered
 // union rows of D.  P pass: D = Gm (N-1 x N-1), out = P with rows in the order.
-// Q pass: D = P^T (columns in the order), out = the correction in the order,
-// upper triangle only (c >= 3a).
+// Q pass: D = P^T (columns in the order), out = Q (stored in the order), to
+// which the correction is added on the upper triangle (c >= 3a).
 //
 // Workgroup = group x 256 columns.  The union is taken in chunks of 16 rows:
 // the chunk's rows of D (16 x 256) and coefficients (16 x 16 x 4) are staged in
@@ -898,6 +900,32 @@ __global__ __launch_bounds__(kB) void group_product_kernel(int32_t N, const int3
   for (int q = 0; q < 3; ++q)
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[q][u] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int n3 = 3 * N;
+  const int c4 = cbase + wave * 64 + 4 * lj;  // this lane's four output columns
+  if (UPPER) {
+    // the Q pass adds to the stored Q: its tile is the accumulators' start
+    // (loaded here, so the loads overlap the first chunk's staging)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int f = kr + 4 * r;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int orow = row0 + 3 * f + q;
+        if (orow >= n3) continue;
+        const double* o = out + static_cast<int64_t>(orow) * ldo;
+        const int cmin = row0 + 3 * f;
+        if (c4 + 4 <= K && c4 >= cmin) {
+          const v4d_a v = *reinterpret_cast<const v4d_a*>(o + c4);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[q][u][r] = v[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (c4 + u < K && c4 + u >= cmin) acc[q][u][r] = o[c4 + u];
+        }
+      }
+    }
+  }
   auto multiply = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < kChunk / 4; ++ks) {
@@ -926,8 +954,6 @@ __global__ __launch_bounds__(kB) void group_product_kernel(int32_t N, const int3
       __syncthreads();
     }
   }
-  const int n3 = 3 * N;
-  const int c4 = cbase + wave * 64 + 4 * lj;  // this lane's four output columns
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int f = kr + 4 * r;
@@ -946,20 +972,6 @@ __global__ __launch_bounds__(kB) void group_product_kernel(int32_t N, const int3
       }
     }
   }
-}
-
-// Q[r][c] += Cperm at the same pair, r <= c (the upper triangle in frame
-// order): Cperm holds, for positions a <= b of the order, the block (a, b)
-// in rows 3a.. and columns 3b.. (block-upper, diagonal blocks whole)
-__global__ __launch_bounds__(kB) void unpermute_add_kernel(const double* __restrict__ Cp, int32_t ld, int32_t n3,
-                                                           const int32_t* __restrict__ pos, double* Q) {
-  const int r = blockIdx.x;  // grid: x = row, y = column tile
-  const int c = blockIdx.y * kB + threadIdx.x;
-  if (c < r || c >= n3) return;
-  const int a = pos[r / 3], b = pos[c / 3];
-  const int ra = 3 * a + r % 3, cb = 3 * b + c % 3;
-  const double v = (a <= b) ? Cp[static_cast<int64_t>(ra) * ld + cb] : Cp[static_cast<int64_t>(cb) * ld + ra];
-  Q[static_cast<int64_t>(r) * ld + c] += v;
 }
 
 // Cuthill-McKee order of the co-visibility graph from frame 0 (order:
@@ -1042,6 +1054,19 @@ int bits_for(uint64_t v) {  // number of bits needed to represent values < v
   int b = 1;
   while (b < 64 && (uint64_t(1) << b) < v) ++b;
   return b;
+}
+
+
+// rows row0 .. row0 + nrows of Q in frame-index order (Q is stored in the frame order)
+__global__ void q_rows_kernel(const double* __restrict__ Q, int32_t ld, int32_t n3, const int32_t* __restrict__ pos,
+                              int32_t row0, double* __restrict__ out) {
+  const int t = blockIdx.x;  // grid: x = row, y = column tile
+  const int c = blockIdx.y * kB + threadIdx.x;
+  if (c >= n3) return;
+  const int r = row0 + t;
+  const int64_t pr = 3 * static_cast<int64_t>(pos[r / 3]) + r % 3;
+  const int64_t pc = 3 * static_cast<int64_t>(pos[c / 3]) + c % 3;
+  out[static_cast<int64_t>(t) * n3 + c] = Q[pr * ld + pc];
 }
 
 }  // namespace
@@ -1144,18 +1169,20 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   const size_t qn = static_cast<size_t>(P->n3) * P->ld;
   P->Q64.alloc(qn);
   XM_HIP(hipMemsetAsync(P->Q64.ptr, 0, qn * sizeof(double), s));
-  P->Art.alloc(3 * S);
-  P->Att.alloc(S);
-  P->fac.alloc(15 * S);
-  hipLaunchKernelGGL(reduce_blocks_kernel, dim3(cdiv(S, kB / 64)), dim3(kB), 0, s, seg_start.ptr, seg_key.ptr,
-                     S, N, pvals.ptr, P->u_s.ptr, P->w_s.ptr, P->lm_s.ptr, P->Wl.ptr, P->Q64.ptr, P->ld,
-                     P->Art.ptr, P->Att.ptr, P->fac.ptr);
-  XM_LAUNCH_CHECK("reduce_blocks_kernel");
   P->row_ptr.alloc(N + 1);
   P->col.alloc(S);
   hipLaunchKernelGGL(pattern_kernel, dim3(cdiv(S + 1, kB)), dim3(kB), 0, s, seg_key.ptr, S, N, P->row_ptr.ptr,
                      P->col.ptr);
   XM_LAUNCH_CHECK("pattern_kernel");
+  // frame order (Cuthill-McKee): Q is stored and assembled in it
+  cm_order(N, P->row_ptr.ptr, P->col.ptr, P->order, P->pos, s);
+  P->Art.alloc(3 * S);
+  P->Att.alloc(S);
+  P->fac.alloc(15 * S);
+  hipLaunchKernelGGL(reduce_blocks_kernel, dim3(cdiv(S, kB / 64)), dim3(kB), 0, s, seg_start.ptr, seg_key.ptr,
+                     S, N, pvals.ptr, P->u_s.ptr, P->w_s.ptr, P->lm_s.ptr, P->Wl.ptr, P->pos.ptr, P->Q64.ptr,
+                     P->ld, P->Art.ptr, P->Att.ptr, P->fac.ptr);
+  XM_LAUNCH_CHECK("reduce_blocks_kernel");
   hipLaunchKernelGGL(check_diag_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, P->row_ptr.ptr, P->col.ptr,
                      P->Att.ptr, N, flags.ptr);
   XM_LAUNCH_CHECK("check_diag_kernel");
@@ -1167,7 +1194,6 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   pkeys.release(); pvals.release(); seg_start.release(); seg_key.release();
   require(!hflags[3], XM_EGRAPH, "a frame has no observation shared with another frame");
   require(!hflags[5], XM_EINVAL, "internal: co-visibility pattern is not symmetric");
-  cm_order(N, P->row_ptr.ptr, P->col.ptr, P->order, P->pos, s);
 
   // a2-ii: translations.  G = A_tt[1:,1:] (dense), swept to -G^{-1}.
   const int32_t ng = N - 1;
@@ -1277,15 +1303,11 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
                        ldp, Ptr.ptr, P->ld);
     XM_LAUNCH_CHECK("transpose_kernel");
     Pm.release();
-    DevBuf<double> Cp(static_cast<size_t>(P->n3) * P->ld);
     t_gather_q.start(s);
     hipLaunchKernelGGL((group_product_kernel<true>), dim3(lq.second), dim3(kB), 0, s, N, tsQ.ptr, lq.first,
-                       ustart.ptr, uid.ptr, coef.ptr, Ptr.ptr, P->ld, P->n3, Cp.ptr, P->ld);
+                       ustart.ptr, uid.ptr, coef.ptr, Ptr.ptr, P->ld, P->n3, P->Q64.ptr, P->ld);
     XM_LAUNCH_CHECK("group_product_kernel(Q)");
     t_gather_q.stop(s);
-    hipLaunchKernelGGL(unpermute_add_kernel, dim3(P->n3, cdiv(P->n3, kB)), dim3(kB), 0, s, Cp.ptr, P->ld, P->n3,
-                       P->pos.ptr, P->Q64.ptr);
-    XM_LAUNCH_CHECK("unpermute_add_kernel");
     XM_HIP(hipStreamSynchronize(s));
     // P pass: G^{-1} read once, P written once, 3 FMAs per (stored block, column);
     // Q pass: P^T read once, the upper triangle written once, half the columns
@@ -1309,13 +1331,15 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
     P->qbar = htr / P->n3;
   }
   P->qkk.alloc(N);
-  hipLaunchKernelGGL(diag_block_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, P->Q64.ptr, N, P->ld, P->qkk.ptr);
+  hipLaunchKernelGGL(diag_block_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, P->Q64.ptr, N, P->ld, P->pos.ptr,
+                     P->qkk.ptr);
   XM_LAUNCH_CHECK("diag_block_kernel");
   {
     P->Dhalf.alloc(9 * static_cast<size_t>(N));
     P->Dmhalf.alloc(9 * static_cast<size_t>(N));
     DevBuf<double> ext(2 * static_cast<size_t>(N));
-    hipLaunchKernelGGL(block_sqrt_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, P->Q64.ptr, N, P->ld, P->Dhalf.ptr,
+    hipLaunchKernelGGL(block_sqrt_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, P->Q64.ptr, N, P->ld, P->pos.ptr,
+                       P->Dhalf.ptr,
                        P->Dmhalf.ptr, ext.ptr);
     XM_LAUNCH_CHECK("block_sqrt_kernel");
     std::vector<double> he(2 * static_cast<size_t>(N));
@@ -1362,6 +1386,13 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   return P;
+}
+
+void get_q_rows(const xm_problem* p, int32_t row0, int32_t nrows, double* out, hipStream_t s) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(q_rows_kernel, dim3(nrows, cdiv(p->n3, kB)), dim3(kB), 0, s, p->Q64.ptr, p->ld, p->n3,
+                     p->pos.ptr, row0, out);
+  XM_LAUNCH_CHECK("q_rows_kernel");
 }
 
 }  // namespace xm

@@ -24,6 +24,8 @@ struct xm_problem {
   std::vector<KernelStat> build_stats;
 
   // Q, row-major [3N][ld], zero padding columns
+  // Q, rows and columns in the frame order (`order` / `pos` below): row 3 pos[k] + c
+  // of the stored matrix is row 3k + c of Q
   xm::DevBuf<double> Q64;
   xm::DevBuf<float> Q32;
   xm::DevBuf<uint16_t> Q16;
@@ -44,6 +46,7 @@ struct xm_problem {
   // A_rt[3i+a][j]; rows 12+a: A_rt[3j+a][i] (the transposed block's entry)
   xm::DevBuf<double> fac;
   xm::DevBuf<double> fact_scratch;   // padded Y^T, W and V of the factored product
+  xm::DevBuf<double> perm_scratch;   // Y^T and Y^T Q in the frame order (dense products)
   // FP32 copies of the factors (with XM_KEEP_F32): fac as above, -G^{-1}
   xm::DevBuf<float> fac32, Gm32;
   xm::DevBuf<double> Att;            // [nnzb]:    A_tt[i][j]
@@ -125,5 +128,7 @@ AdjointResult adjoint(xm_problem* p, const double* R, const double* s, const dou
 
 // Host sum of per-block partials [blocks][nq] (fixed order) after a stream sync.
 void read_partials(const double* dev, int blocks, int nq, double* out, hipStream_t s);
+// rows row0 .. row0 + nrows of Q (frame-index order) into out [nrows][3N]
+void get_q_rows(const xm_problem* p, int32_t row0, int32_t nrows, double* out, hipStream_t s);
 
 }  // namespace xm

@@ -694,8 +694,19 @@ void dispatch_factored(const xm_problem* p, const T* Yt, int r, T* out, hipStrea
   }
 }
 
+// out[a][e] = in[map[a]][e] over N rows of w values: with map = order it takes
+// a frame-major array into the frame order, with map = pos back out of it
+template <typename T>
+__global__ void permute_frames_kernel(const T* __restrict__ in, const int32_t* __restrict__ map, int32_t N, int w,
+                                      T* __restrict__ out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (e >= static_cast<int64_t>(N) * w) return;
+  const int64_t a = e / w;
+  out[e] = in[static_cast<int64_t>(map[a]) * w + (e - a * w)];
+}
+
 template <typename TQ, typename TV, typename TA>
-void dispatch_r(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, hipStream_t s, int role) {
+void dispatch_r_ordered(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, hipStream_t s, int role) {
   if (p->spmm_kind[role][QVec<TQ>::dtype] == XM_SPMM_UPPER) {
     switch (r) {
       case 1: launch_sym<TQ, TV, TA, 1>(p, Q, Yt, out, s); return;
@@ -720,6 +731,29 @@ void dispatch_r(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, 
     case 8: launch<TQ, TV, TA, 8>(p, Q, Yt, out, s); break;
     default: throw Error(XM_EINVAL, "rank must be in [1, 8]");
   }
+}
+
+// The stored Q is in the frame order (that of the assembly): Yt goes into that
+// order, the product is taken there, and its rows come back to frame order.
+template <typename TQ, typename TV, typename TA>
+void dispatch_r(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, hipStream_t s, int role) {
+  require(r >= 1 && r <= 8, XM_EINVAL, "rank must be in [1, 8]");
+  auto* mp = const_cast<xm_problem*>(p);
+  const int32_t N = p->N;
+  const int w = 3 * r;
+  const size_t n = static_cast<size_t>(N) * w;
+  const size_t cap = 48 * static_cast<size_t>(N);  // doubles: two [N][3r] arrays, r <= 8, values <= 8 bytes
+  if (mp->perm_scratch.n < cap) {
+    XM_HIP(hipStreamSynchronize(s));
+    mp->perm_scratch.alloc(cap);
+  }
+  TV* Yp = reinterpret_cast<TV*>(mp->perm_scratch.ptr);
+  TV* Op = Yp + n;
+  hipLaunchKernelGGL((permute_frames_kernel<TV>), dim3(cdiv(n, kB)), dim3(kB), 0, s, Yt, p->order.ptr, N, w, Yp);
+  XM_LAUNCH_CHECK("permute_frames_kernel");
+  dispatch_r_ordered<TQ, TV, TA>(p, Q, Yp, r, Op, s, role);
+  hipLaunchKernelGGL((permute_frames_kernel<TV>), dim3(cdiv(n, kB)), dim3(kB), 0, s, Op, p->pos.ptr, N, w, out);
+  XM_LAUNCH_CHECK("permute_frames_kernel");
 }
 
 }  // namespace
