@@ -137,14 +137,16 @@ __global__ __launch_bounds__(kB) void spmm_split_kernel(const TQ* __restrict__ Q
 //
 // Slabs are 256 rows (RS) unless that leaves fewer than kSymMinBlocks
 // workgroups on or above the diagonal (a small matrix, e.g. the 10^4-order
-// G^{-1} of the factored product); then 128 or 64.
+// G^{-1} of the factored product); then 128 or 64.  FP32 matrices settle for
+// half as many workgroups (each streams twice the values per load; measured
+// at N = 10155: 64-row slabs cost the FP32 product more in partial sums than
+// they gain in parallelism).
 #ifndef XM_SYM_MIN_BLOCKS
 #define XM_SYM_MIN_BLOCKS 512
 #endif
 #ifndef XM_SYM_PERM
 #define XM_SYM_PERM 1
 #endif
-constexpr int kSymMinBlocks = XM_SYM_MIN_BLOCKS;
 constexpr bool kSymPerm = XM_SYM_PERM;  // lane-permuted slots (else selects in the butterfly)
 #ifndef XM_SYM_BATCH
 #define XM_SYM_BATCH 8
@@ -439,6 +441,7 @@ template <typename TQ, typename TV, typename TA, int R>
 void sym_product(const TQ* M, int32_t ld, int32_t n, const TV* Yt, TV* out, DevBuf<char>& scratch,
                  xm_problem::TimedLaunch* ev, hipStream_t s) {
   constexpr int C = kB * QVec<TQ>::V;
+  const int64_t kSymMinBlocks = sizeof(TQ) == 8 ? XM_SYM_MIN_BLOCKS : XM_SYM_MIN_BLOCKS / 2;
   if (sym_active_blocks(n, ld, C, 256) >= kSymMinBlocks)
     sym_product_rs<TQ, TV, TA, R, 256>(M, ld, n, Yt, out, scratch, ev, s);
   else if (sym_active_blocks(n, ld, C, 128) >= kSymMinBlocks)

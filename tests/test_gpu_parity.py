@@ -371,8 +371,8 @@ def test_large_workload_sampled_rows_and_certified_solves():
     assert np.abs(Qg - Qo).max() <= 1e-9 * np.abs(Qo).max()
     # the products at full size, in the launch shapes the solve uses (dense
     # upper-triangle kernel over Q: 256-row slabs; factored product: G^{-1}
-    # through 128-row (FP64) and 64-row (FP32) slabs), on the sampled columns:
-    # (Y Q)[:, j] = Y Q[j, :]^T by symmetry
+    # through 128-row slabs; the 64-row slabs are covered by the tiled test),
+    # on the sampled columns: (Y Q)[:, j] = Y Q[j, :]^T by symmetry
     # bars relative to |Y| max * the largest absolute row sum of Q, as in the
     # tiled test; the factored form sums terms up to ~30x larger than Q's
     # entries (its error scales with them), hence its looser bars
