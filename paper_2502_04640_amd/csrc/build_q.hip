@@ -398,6 +398,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 #ifndef XM_SWEEP_KC
 #define XM_SWEEP_KC 16
 #endif
+// The tile of G is streamed: read once and written once per step, and the
+// whole upper triangle (0.4 GB at N = 10^4) does not stay in any cache between
+// steps, so its loads and stores carry the non-temporal hint (measured 4 %
+// faster at N = 10155).
+#ifndef XM_SWEEP_NT
+#define XM_SWEEP_NT 1
+#endif
 constexpr int kSweepKC = XM_SWEEP_KC;
 __global__ __launch_bounds__(kB) void sweep_update_kernel(double* A, int32_t lda, int32_t n,
                                                           const double* __restrict__ Ct,
@@ -422,7 +429,11 @@ __global__ __launch_bounds__(kB) void sweep_update_kernel(double* A, int32_t lda
       for (int q = 0; q < 4; ++q) {
         const int i = i0 + wi + 16 * a + lk + 4 * q;
         const int j = j0 + wj + 16 * b + lr;
+#if XM_SWEEP_NT
+        g[a][b][q] = (i < n && j < n) ? __builtin_nontemporal_load(A + static_cast<int64_t>(i) * lda + j) : 0.0;
+#else
         g[a][b][q] = (i < n && j < n) ? A[static_cast<int64_t>(i) * lda + j] : 0.0;
+#endif
       }
   v4d acc[2][2];
 #pragma unroll
@@ -480,7 +491,11 @@ __global__ __launch_bounds__(kB) void sweep_update_kernel(double* A, int32_t lda
       for (int q = 0; q < 4; ++q) {
         const int i = i0 + wi + 16 * a + lk + 4 * q;
         const int j = j0 + wj + 16 * b + lr;
+#if XM_SWEEP_NT
+        if (i < n && j < n) __builtin_nontemporal_store(g[a][b][q] - acc[a][b][q], A + static_cast<int64_t>(i) * lda + j);
+#else
         if (i < n && j < n) A[static_cast<int64_t>(i) * lda + j] = g[a][b][q] - acc[a][b][q];
+#endif
       }
 }
 
