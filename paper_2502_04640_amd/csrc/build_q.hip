@@ -273,52 +273,54 @@ __global__ void scatter_grounded_kernel(const int32_t* __restrict__ row_ptr, con
 // rank-64 product per tile on FP64 matrix cores.
 constexpr int kNB = 64;
 
-// -A_KK^{-1} by Gauss-Jordan pivoting in LDS; a last block with nb < 64 is
-// padded with dscale * I.  Dinv (nb x nb) = A_KK^{-1}.
+// A_KK^{-1} by the symmetric sweep operator: with d = a_pp, pivot p maps
+//   a_ij -> a_ij - a_ip a_pj / d,  a_ip -> a_ip / d,  a_pj -> a_pj / d,  a_pp -> -1/d,
+// which keeps the block symmetric, so the pivot row is the pivot column.
+// Thread t keeps column j = t % 64 of rows t / 64 + 4c (16 values) in registers;
+// per pivot, the four threads of column p publish it through LDS (double-
+// buffered, so one barrier per pivot suffices).  After all pivots the block
+// holds -A_KK^{-1}.  A last block with nb < 64 is padded with dscale * I.
+// Dinv (nb x nb) = A_KK^{-1}.
 __global__ __launch_bounds__(kB) void sweep_pivot_kernel(const double* __restrict__ A, int32_t lda,
                                                          int32_t k0, int32_t nb, double dscale,
                                                          double* Dinv, int* flags) {
-  __shared__ double D[kNB][kNB + 1];
+  __shared__ double colp[2][kNB];
   const int t = threadIdx.x;
-  const int j = t & 63, ibase = t >> 6;  // thread owns column j of rows ibase + 4c
+  const int j = t & 63, ibase = t >> 6;
+  double a[kNB / 4];
+#pragma unroll
   for (int c = 0; c < kNB / 4; ++c) {
     const int i = ibase + 4 * c;
-    D[i][j] = (i < nb && j < nb) ? A[static_cast<int64_t>(k0 + i) * lda + k0 + j] : (i == j ? dscale : 0.0);
+    a[c] = (i < nb && j < nb) ? A[static_cast<int64_t>(k0 + i) * lda + k0 + j] : (i == j ? dscale : 0.0);
   }
-  __syncthreads();
   for (int p = 0; p < kNB; ++p) {
-    const double d = D[p][p];
+    double* cp = colp[p & 1];
+    if (j == p) {
+#pragma unroll
+      for (int c = 0; c < kNB / 4; ++c) cp[ibase + 4 * c] = a[c];
+    }
+    __syncthreads();
+    const double d = cp[p];
     if (!(d > 1e-11 * dscale)) {
       if (t == 0) flags[4] = 1;
       return;  // uniform across the block: every thread read the same d
     }
     const double inv = 1.0 / d;
-    const double dpj = D[p][j] * inv;
-    double upd[kNB / 4];
+    const double f = cp[j] * inv;  // a_pj / d
+    const bool piv_col = j == p;
 #pragma unroll
     for (int c = 0; c < kNB / 4; ++c) {
       const int i = ibase + 4 * c;
-      upd[c] = D[i][j] - D[i][p] * dpj;
+      const double ci = cp[i];
+      const double off = piv_col ? ci * inv : a[c] - ci * f;
+      const double on = piv_col ? -inv : f;
+      a[c] = (i == p) ? on : off;
     }
-    __syncthreads();
-    if (j != p) {
-#pragma unroll
-      for (int c = 0; c < kNB / 4; ++c) {
-        const int i = ibase + 4 * c;
-        if (i != p) D[i][j] = upd[c];
-      }
-    }
-    __syncthreads();
-    if (t < kNB && t != p) {
-      D[t][p] *= inv;
-      D[p][t] *= inv;
-    }
-    if (t == 0) D[p][p] = -inv;
-    __syncthreads();
   }
+#pragma unroll
   for (int c = 0; c < kNB / 4; ++c) {
     const int i = ibase + 4 * c;
-    if (i < nb && j < nb) Dinv[i * nb + j] = -D[i][j];
+    if (i < nb && j < nb) Dinv[i * nb + j] = -a[c];
   }
 }
 
