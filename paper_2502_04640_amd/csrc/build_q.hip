@@ -837,18 +837,23 @@ __global__ __launch_bounds__(kB) void group_fill_kernel(int32_t N, const int32_t
 // Q pass: D = P^T (columns in the order), out = Q (stored in the order), to
 // which the correction is added on the upper triangle (c >= 3a).
 //
-// Workgroup = group x 256 columns.  The union is taken in chunks of 16 rows:
-// the chunk's rows of D (16 x 256) and coefficients (16 x 16 x 4) are staged in
-// LDS, double-buffered: the next chunk's global loads are in flight while the
-// current one is multiplied.  Each wave takes 64 columns as 3 x 4 tiles of
-// v_mfma_f64_16x16x4f64 per 4 union rows, the tile (q, t) holding rows 3f + q
-// and columns 4j + t (f, j < 16): lane l supplies A[f = l % 16][k = l / 16]
-// for the three q from one 32-byte read of coef[k][f][0..3] and B[k = l / 16]
-// [j = l % 16] for the four t from one 32-byte read of the union row, and
-// holds C[l / 16 + 4 r][l % 16] in register r.
-constexpr int kGroupCols = 256;
+// Workgroup = group x 64 kCPL columns.  The union is taken in chunks of 16
+// rows: the chunk's rows of D (16 x 64 kCPL) and coefficients (16 x 16 x 4) are
+// staged in LDS, double-buffered: the next chunk's global loads are in flight
+// while the current one is multiplied.  Each wave takes 16 kCPL columns as
+// 3 x kCPL tiles of v_mfma_f64_16x16x4f64 per 4 union rows, the tile (q, u)
+// holding rows 3f + q and columns kCPL j + u (f, j < 16): lane l supplies
+// A[f = l % 16][k = l / 16] for the three q from one 32-byte read of
+// coef[k][f][0..3] and B[k = l / 16][j = l % 16] for the kCPL values of u from
+// one read of the union row, and holds C[l / 16 + 4 r][l % 16] in register r.
+#ifndef XM_GROUP_CPL
+#define XM_GROUP_CPL 2
+#endif
+constexpr int kCPL = XM_GROUP_CPL;            // output columns per lane (= MFMA column tiles per wave)
+constexpr int kGroupCols = 64 * kCPL;         // columns per workgroup: 4 waves x 16 lanes x kCPL
 constexpr int kChunk = 16;
 typedef double v4d_a __attribute__((ext_vector_type(4), aligned(32)));
+typedef double vcol __attribute__((ext_vector_type(kCPL), aligned(8 * kCPL)));
 template <bool UPPER>
 __global__ __launch_bounds__(kB) void group_product_kernel(int32_t N, const int32_t* __restrict__ tile_start,
                                                            int32_t ntiles, const int64_t* __restrict__ ustart,
@@ -856,7 +861,7 @@ __global__ __launch_bounds__(kB) void group_product_kernel(int32_t N, const int3
                                                            const double* __restrict__ coef,
                                                            const double* __restrict__ D, int32_t ldd, int32_t K,
                                                            double* __restrict__ out, int32_t ldo) {
-  __shared__ v4d_a Bs[2][kChunk][kGroupCols / 4];
+  __shared__ vcol Bs[2][kChunk][kGroupCols / kCPL];
   __shared__ v4d_a As[2][kChunk][kGroup];
   // workgroup w -> (column tile y, group g): tile-major over the pairs that
   // produce output (tile y holds the groups g < tile_start[y + 1] - tile_start[y]),
@@ -874,51 +879,51 @@ __global__ __launch_bounds__(kB) void group_product_kernel(int32_t N, const int3
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int kr = lane >> 4, lj = lane & 15;
-  // staging: thread t loads row t / 16 of the chunk, columns 16 (t % 16) .. + 15
-  // of the tile (four 32-byte pieces), and coefficient row t / 16, frame t % 16
-  const int sr = t >> 4, sc = (t & 15) * 16;
+  // staging: thread t loads row t / 16 of the chunk, four kCPL-wide pieces of
+  // the tile from column 4 kCPL (t % 16), and coefficient row t / 16, frame t % 16
+  constexpr int SW = 4 * kCPL;
+  const int sr = t >> 4, sc = (t & 15) * SW;
   const int gc = cbase + sc;
-  const bool sfull = gc + 16 <= K;
+  const bool sfull = gc + SW <= K;
   const int64_t k0 = ustart[g], k1 = ustart[g + 1];
   struct Stage {
-    v4d_a b[4], a;
+    vcol b[4];
+    v4d_a a;
   };
   auto fetch = [&](int64_t kc, Stage& st) {
     const int64_t k = kc + sr;
-    const v4d_a z = v4d_a{0.0, 0.0, 0.0, 0.0};
     if (k < k1) {
       st.a = *reinterpret_cast<const v4d_a*>(coef + (k * kGroup + (t & 15)) * 4);
       const double* drow = D + static_cast<int64_t>(uid[k] - 1) * ldd + gc;
       if (sfull) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) st.b[p] = *reinterpret_cast<const v4d_a*>(drow + 4 * p);
+        for (int p = 0; p < 4; ++p) st.b[p] = *reinterpret_cast<const vcol*>(drow + kCPL * p);
       } else {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          st.b[p] = z;
+        for (int p = 0; p < 4; ++p)
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (gc + 4 * p + e < K) st.b[p][e] = drow[4 * p + e];
-        }
+          for (int e = 0; e < kCPL; ++e) st.b[p][e] = (gc + kCPL * p + e < K) ? drow[kCPL * p + e] : 0.0;
       }
     } else {
-      st.a = z;
+      st.a = v4d_a{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int p = 0; p < 4; ++p) st.b[p] = z;
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int e = 0; e < kCPL; ++e) st.b[p][e] = 0.0;
     }
   };
   auto stash = [&](int buf, const Stage& st) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) Bs[buf][sr][(sc >> 2) + p] = st.b[p];
+    for (int p = 0; p < 4; ++p) Bs[buf][sr][(t & 15) * 4 + p] = st.b[p];
     As[buf][sr][t & 15] = st.a;
   };
-  v4d acc[3][4];
+  v4d acc[3][kCPL];
 #pragma unroll
   for (int q = 0; q < 3; ++q)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[q][u] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < kCPL; ++u) acc[q][u] = v4d{0.0, 0.0, 0.0, 0.0};
   const int n3 = 3 * N;
-  const int c4 = cbase + wave * 64 + 4 * lj;  // this lane's four output columns
+  const int cl = cbase + wave * 16 * kCPL + kCPL * lj;  // this lane's kCPL output columns
   if (UPPER) {
     // the Q pass adds to the stored Q: its tile is the accumulators' start
     // (loaded here, so the loads overlap the first chunk's staging)
@@ -931,14 +936,14 @@ __global__ __launch_bounds__(kB) void group_product_kernel(int32_t N, const int3
         if (orow >= n3) continue;
         const double* o = out + static_cast<int64_t>(orow) * ldo;
         const int cmin = row0 + 3 * f;
-        if (c4 + 4 <= K && c4 >= cmin) {
-          const v4d_a v = *reinterpret_cast<const v4d_a*>(o + c4);
+        if (cl + kCPL <= K && cl >= cmin) {
+          const vcol v = *reinterpret_cast<const vcol*>(o + cl);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) acc[q][u][r] = v[u];
+          for (int u = 0; u < kCPL; ++u) acc[q][u][r] = v[u];
         } else {
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (c4 + u < K && c4 + u >= cmin) acc[q][u][r] = o[c4 + u];
+          for (int u = 0; u < kCPL; ++u)
+            if (cl + u < K && cl + u >= cmin) acc[q][u][r] = o[cl + u];
         }
       }
     }
@@ -947,11 +952,11 @@ __global__ __launch_bounds__(kB) void group_product_kernel(int32_t N, const int3
 #pragma unroll
     for (int ks = 0; ks < kChunk / 4; ++ks) {
       const v4d_a av = As[buf][4 * ks + kr][lj];
-      const v4d_a bv = Bs[buf][4 * ks + kr][wave * 16 + lj];
+      const vcol bv = Bs[buf][4 * ks + kr][wave * 16 + lj];
 #pragma unroll
       for (int q = 0; q < 3; ++q)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kCPL; ++u)
           acc[q][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[u], acc[q][u], 0, 0, 0);
     }
   };
@@ -980,12 +985,15 @@ __global__ __launch_bounds__(kB) void group_product_kernel(int32_t N, const int3
       if (orow >= n3) continue;
       double* o = out + static_cast<int64_t>(orow) * ldo;
       const int cmin = UPPER ? row0 + 3 * f : 0;
-      if (c4 + 4 <= K && c4 >= cmin) {
-        *reinterpret_cast<v4d_a*>(o + c4) = v4d_a{acc[q][0][r], acc[q][1][r], acc[q][2][r], acc[q][3][r]};
+      if (cl + kCPL <= K && cl >= cmin) {
+        vcol v;
+#pragma unroll
+        for (int u = 0; u < kCPL; ++u) v[u] = acc[q][u][r];
+        *reinterpret_cast<vcol*>(o + cl) = v;
       } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (c4 + u < K && c4 + u >= cmin) o[c4 + u] = acc[q][u][r];
+        for (int u = 0; u < kCPL; ++u)
+          if (cl + u < K && cl + u >= cmin) o[cl + u] = acc[q][u][r];
       }
     }
   }
