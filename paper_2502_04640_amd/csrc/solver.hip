@@ -101,7 +101,10 @@ void grad_product(xm_problem* p, xm_dtype qg, const T* Yt, int r, T* G, double* 
   }
   hipLaunchKernelGGL(sub_kernel<T>, dim3(cdiv(n, 256)), dim3(256), 0, st, n, Yt, rb.Yref, rb.tmp);
   XM_LAUNCH_CHECK("sub_kernel");
-  spmm_yt<T>(p, qg, rb.tmp, r, G, st);
+  // the product of the small difference Y - Yref: no cancellation at the scale
+  // of Q Y, so the curvature-role product (the factored form on large
+  // problems) is accurate enough
+  spmm_yt<T>(p, qg, rb.tmp, r, G, st, XM_ROLE_CURVATURE);
   hipLaunchKernelGGL(combine_kernel<T>, dim3(cdiv(n, 256)), dim3(256), 0, st, n, rb.Gref, G, G64);
   XM_LAUNCH_CHECK("combine_kernel");
 }
