@@ -92,6 +92,12 @@ __global__ void combine_kernel(int64_t n, const double* __restrict__ Gref, T* __
 }
 
 template <typename T>
+__global__ void widen_kernel(int64_t n, const T* __restrict__ a, double* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) out[i] = static_cast<double>(a[i]);
+}
+
+template <typename T>
 void grad_product(xm_problem* p, xm_dtype qg, const T* Yt, int r, T* G, double* G64, const Rebase<T>& rb,
                   hipStream_t st) {
   const int64_t n = p->n3 * static_cast<int64_t>(r);
@@ -139,6 +145,27 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
   mf.scale(r, V.Rt.ptr, V.s.ptr, V.Yt.ptr, st);
   double* G64 = rb.G64;
   double* G2_64 = rb.G2_64;
+  // Candidate products from the step (reduced precision, factored curvature
+  // products): G(Y+) = G(Y) + Q (Y+ - Y), the product of the small difference
+  // taken in the curvature role and added in FP64.  Its rounding scales with
+  // |Y+ - Y|, so while the steps taken since the last full product sum to at
+  // most kChainFrac |Y| the accumulated error stays at the level of one full
+  // reduced-precision product; past that, a full product restarts the chain.
+  constexpr double kChainFrac = 0.05;
+  const size_t nvr0 = static_cast<size_t>(3) * N * r;
+  const bool chain = !rb.on() && sizeof(T) == 4 && p->spmm_kind[XM_ROLE_CURVATURE][qg] == XM_SPMM_FACTORED;
+  DevBuf<T> dY;
+  DevBuf<double> C64a, C64b;  // FP64 G at the current point and at the candidate
+  double* Gc64 = nullptr;
+  double* Gc2_64 = nullptr;
+  double chain_dist = 0.0;
+  if (chain) {
+    dY.alloc(nvr0);
+    C64a.alloc(nvr0);
+    C64b.alloc(nvr0);
+    Gc64 = C64a.ptr;
+    Gc2_64 = C64b.ptr;
+  }
   auto form_grad = [&]() {
     if (rb.on()) mf.grad(r, V.Rt.ptr, V.s.ptr, static_cast<const double*>(G64), V.gR.ptr, V.gs.ptr, V.Sc.ptr,
                          V.ec.ptr, V.part.ptr, st);
@@ -147,6 +174,11 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
   };
   grad_product<T>(p, qg, V.Yt.ptr, r, V.G.ptr, G64, rb, st);
   ++out.spmm;
+  if (chain) {
+    hipLaunchKernelGGL(widen_kernel<T>, dim3(cdiv(nvr0, 256)), dim3(256), 0, st, static_cast<int64_t>(nvr0),
+                       V.G.ptr, Gc64);
+    XM_LAUNCH_CHECK("widen_kernel");
+  }
   form_grad();
   read_partials(V.part.ptr, nb, 5, sums, st);
   double f = sums[0], gg = sums[1], gnorm = std::sqrt(sums[1]), ynorm = std::sqrt(sums[2]);
@@ -202,7 +234,28 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
     out.inner += std::min(j, max_inner);
     // ---- candidate and ratio test ----
     mf.retract(r, V.Rt.ptr, V.s.ptr, V.etaR.ptr, V.etas.ptr, V.Rt2.ptr, V.s2.ptr, V.Yt2.ptr, st);
-    grad_product<T>(p, qg, V.Yt2.ptr, r, V.G2.ptr, G2_64, rb, st);
+    bool chained = false;
+    double step = 0.0;
+    if (chain) {
+      const int64_t n = static_cast<int64_t>(nvr0);
+      hipLaunchKernelGGL(sub_kernel<T>, dim3(cdiv(n, 256)), dim3(256), 0, st, n, V.Yt2.ptr, V.Yt.ptr, dY.ptr);
+      XM_LAUNCH_CHECK("sub_kernel");
+      step = std::sqrt(vec_dot<T>(dY.ptr, dY.ptr, n, V.part.ptr, 8, st));
+      if (chain_dist + step <= kChainFrac * ynorm) {
+        spmm_yt<T>(p, qg, dY.ptr, r, V.G2.ptr, st, XM_ROLE_CURVATURE);
+        hipLaunchKernelGGL(combine_kernel<T>, dim3(cdiv(n, 256)), dim3(256), 0, st, n, Gc64, V.G2.ptr, Gc2_64);
+        XM_LAUNCH_CHECK("combine_kernel");
+        chained = true;
+      }
+    }
+    if (!chained) {
+      grad_product<T>(p, qg, V.Yt2.ptr, r, V.G2.ptr, G2_64, rb, st);
+      if (chain) {
+        hipLaunchKernelGGL(widen_kernel<T>, dim3(cdiv(nvr0, 256)), dim3(256), 0, st, static_cast<int64_t>(nvr0),
+                           V.G2.ptr, Gc2_64);
+        XM_LAUNCH_CHECK("widen_kernel");
+      }
+    }
     ++out.spmm;
     if (rb.on())
       mf.model(r, V.s.ptr, V.gR.ptr, V.gs.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr, V.Yt.ptr,
@@ -239,6 +292,10 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
       std::swap(V.Yt.ptr, V.Yt2.ptr);
       std::swap(V.G.ptr, V.G2.ptr);
       std::swap(G64, G2_64);
+      if (chain) {
+        std::swap(Gc64, Gc2_64);
+        chain_dist = chained ? chain_dist + step : 0.0;
+      }
       form_grad();
       read_partials(V.part.ptr, nb, 5, sums, st);
       f = sums[0];
