@@ -172,7 +172,9 @@ __device__ __forceinline__ void sym_batch(const TQ* __restrict__ q, int32_t ld, 
 #pragma unroll
   for (int b = 0; b < kSymBatch; ++b) {
     const int row = b ^ pi;
-    if (row < nb) {
+    // in a tile that crosses the diagonal, a lane whose V columns all lie left
+    // of the row loads nothing (its values would be masked to zero below)
+    if (row < nb && (!kMask || jcol + V - 1 >= i_base + row)) {
       QVec<TQ>::load(q + static_cast<int64_t>(row) * ld, qv[b]);
     } else {
 #pragma unroll
