@@ -52,3 +52,29 @@ def test_null_arguments_are_rejected_without_gpu():
     assert code == -1 and b"N must be" in lib.xm_last_error()
     lib.xm_get_info.restype = ctypes.c_int
     assert lib.xm_get_info(None, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libxm.so not built")
+def test_product_kind_calls_reject_bad_arguments_without_gpu():
+    # argument checks of the product-kernel selectors run before any HIP call
+    lib = ctypes.CDLL(LIB)
+    lib.xm_last_error.restype = ctypes.c_char_p
+    for fn in (lib.xm_set_spmm_kind, lib.xm_set_product_kind, lib.xm_get_product_kind, lib.xm_spmm_timing,
+               lib.xm_spmm_stats):
+        fn.restype = ctypes.c_int
+    assert lib.xm_set_spmm_kind(None, 0, 1) == -1
+    assert lib.xm_set_product_kind(None, 0, 0, 1) == -1
+    k = ctypes.c_int(-7)
+    assert lib.xm_get_product_kind(None, 1, 0, ctypes.byref(k)) == -1
+    assert k.value == -7  # output untouched on failure
+    assert lib.xm_spmm_timing(None, 1) == -1
+    assert lib.xm_spmm_stats(None, None, 0) == -1
+    assert lib.xm_last_error() != b""
+
+
+def test_stats_struct_matches_header():
+    # the ctypes mirror of xm_spmm_counters has as many slots as the header declares
+    text = open(HEADER).read()
+    slots = int(re.search(r"#define XM_STATS_SLOTS (\d+)", text).group(1))
+    from paper_2502_04640_amd.api import _SpmmStats
+    assert len(_SpmmStats().launches) == slots == len(_SpmmStats().total_ms) == len(_SpmmStats().bytes_per_launch)
