@@ -145,15 +145,15 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
   mf.scale(r, V.Rt.ptr, V.s.ptr, V.Yt.ptr, st);
   double* G64 = rb.G64;
   double* G2_64 = rb.G2_64;
-  // Candidate products from the step (reduced precision, factored curvature
-  // products): G(Y+) = G(Y) + Q (Y+ - Y), the product of the small difference
+  // Candidate products from the step (when the curvature products are
+  // factored): G(Y+) = G(Y) + Q (Y+ - Y), the product of the small difference
   // taken in the curvature role and added in FP64.  Its rounding scales with
   // |Y+ - Y|, so while the steps taken since the last full product sum to at
   // most kChainFrac |Y| the accumulated error stays at the level of one full
-  // reduced-precision product; past that, a full product restarts the chain.
+  // product; past that, a full product restarts the chain.
   constexpr double kChainFrac = 0.05;
   const size_t nvr0 = static_cast<size_t>(3) * N * r;
-  const bool chain = !rb.on() && sizeof(T) == 4 && p->spmm_kind[XM_ROLE_CURVATURE][qg] == XM_SPMM_FACTORED;
+  const bool chain = !rb.on() && p->spmm_kind[XM_ROLE_CURVATURE][qg] == XM_SPMM_FACTORED;
   DevBuf<T> dY;
   DevBuf<double> C64a, C64b;  // FP64 G at the current point and at the candidate
   double* Gc64 = nullptr;
