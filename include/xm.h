@@ -92,7 +92,9 @@ typedef struct xm_problem xm_problem;
  * Observations may come in any order; a landmark seen once contributes
  * nothing.  Errors: XM_EINVAL (sizes, index out of range, non-finite u,
  * w <= 0), XM_EGRAPH (frame without observations, disconnected graph).
- * Synchronises `stream`.
+ * Synchronises `stream`.  The inversion of the grounded Laplacian also uses a
+ * private second stream (default priority), ordered against `stream` by
+ * events and finished before the call returns.
  */
 xm_status xm_build_Q(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame,
                      const int32_t* landmark, const void* u, xm_dtype u_dtype,

@@ -270,83 +270,149 @@ __global__ void scatter_grounded_kernel(const int32_t* __restrict__ row_ptr, con
 // its upper triangle (64 x 64 tiles J >= I) is kept current; values of A_iK
 // for i past K are read from A_Ki, and the lower triangle is copied from the
 // upper one at the end.  The trailing update A_ij -= C_i P_j is a dense
-// rank-64 product per tile on FP64 matrix cores.
-constexpr int kNB = 64;
+// rank-kNB product per 64 x 64 tile on FP64 matrix cores; each step reads and
+// writes the whole upper triangle, so wider pivot blocks mean fewer passes.
+#ifndef XM_SWEEP_NB
+#define XM_SWEEP_NB 128
+#endif
+constexpr int kNB = XM_SWEEP_NB;  // pivot block width: 64 or 128
+static_assert(kNB == 64 || kNB == 128, "pivot blocks of 64 or 128");
 
 // A_KK^{-1} by the symmetric sweep operator: with d = a_pp, pivot p maps
 //   a_ij -> a_ij - a_ip a_pj / d,  a_ip -> a_ip / d,  a_pj -> a_pj / d,  a_pp -> -1/d,
 // which keeps the block symmetric, so the pivot row is the pivot column.
-// Thread t keeps column j = t % 64 of rows t / 64 + 4c (16 values) in registers;
-// per pivot, the four threads of column p publish it through LDS (double-
-// buffered, so one barrier per pivot suffices).  After all pivots the block
-// holds -A_KK^{-1}.  A last block with nb < 64 is padded with dscale * I.
-// Dinv (nb x nb) = A_KK^{-1}.
-__global__ __launch_bounds__(kB) void sweep_pivot_kernel(const double* __restrict__ A, int32_t lda,
-                                                         int32_t k0, int32_t nb, double dscale,
-                                                         double* Dinv, int* flags) {
+// Thread t keeps column j = t % kNB of rows t / kNB + G c (G = kNB / 16 row
+// groups, 16 values) in registers, so the serial work per pivot is the same
+// at either block width; per pivot, the G threads of column p publish it
+// through LDS (double-buffered, so one barrier per pivot suffices).
+// After all pivots the block holds -A_KK^{-1}.  A last block with nb < kNB is
+// padded with dscale * I.  Dinv (nb x nb) = A_KK^{-1}.
+// Look-ahead (Dsave non-null): the block is formed here from the copy Dsave
+// (upper triangle, row stride kNB) taken before the previous step's trailing
+// update, minus that update's own terms sum_q Ct[q][k0+i] Pt[q][k0+j]
+// (q < nbp), so the inversion need not wait for the whole update to finish.
+constexpr int kPivotRows = 16;                          // rows per thread
+constexpr int kPivotThreads = kNB * kNB / kPivotRows;   // 256 or 1024
+constexpr int kPivotQC = 32;                            // panel rows per LDS chunk
+__global__ __launch_bounds__(kPivotThreads) void sweep_pivot_kernel(
+    const double* __restrict__ A, int32_t lda, int32_t k0, int32_t nb, double dscale,
+    const double* __restrict__ Dsave, const double* __restrict__ Ct, const double* __restrict__ Pt, int32_t ldt,
+    int32_t nbp, double* Dinv, int* flags) {
+  constexpr int G = kNB / kPivotRows;  // row groups
+  constexpr int RPT = kPivotRows;
   __shared__ double colp[2][kNB];
+  __shared__ double Cs[kPivotQC][kNB], Ps[kPivotQC][kNB];
   const int t = threadIdx.x;
-  const int j = t & 63, ibase = t >> 6;
-  double a[kNB / 4];
+  const int j = t % kNB, ibase = t / kNB;
+  double a[RPT];
+  if (Dsave == nullptr) {
 #pragma unroll
-  for (int c = 0; c < kNB / 4; ++c) {
-    const int i = ibase + 4 * c;
-    a[c] = (i < nb && j < nb) ? A[static_cast<int64_t>(k0 + i) * lda + k0 + j] : (i == j ? dscale : 0.0);
+    for (int c = 0; c < RPT; ++c) {
+      const int i = ibase + G * c;
+      // only the upper triangle of A is current: (i, j) is read as (min, max)
+      const int lo = i < j ? i : j, hi = i < j ? j : i;
+      a[c] = (i < nb && j < nb) ? A[static_cast<int64_t>(k0 + lo) * lda + k0 + hi] : (i == j ? dscale : 0.0);
+    }
+  } else {
+    double acc[RPT];
+#pragma unroll
+    for (int c = 0; c < RPT; ++c) acc[c] = 0.0;
+    for (int q0 = 0; q0 < nbp; q0 += kPivotQC) {
+      for (int e = t; e < kPivotQC * kNB; e += kPivotThreads) {
+        const int q = q0 + e / kNB, i = e % kNB;
+        const bool ok = q < nbp && i < nb;
+        Cs[e / kNB][i] = ok ? Ct[static_cast<int64_t>(q) * ldt + k0 + i] : 0.0;
+        Ps[e / kNB][i] = ok ? Pt[static_cast<int64_t>(q) * ldt + k0 + i] : 0.0;
+      }
+      __syncthreads();
+      for (int q = 0; q < kPivotQC; ++q) {
+        const double pj = Ps[q][j];
+#pragma unroll
+        for (int c = 0; c < RPT; ++c) acc[c] += Cs[q][ibase + G * c] * pj;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < RPT; ++c) {
+      const int i = ibase + G * c;
+      const int lo = i < j ? i : j, hi = i < j ? j : i;
+      a[c] = (i < nb && j < nb) ? Dsave[lo * kNB + hi] - acc[c] : (i == j ? dscale : 0.0);
+    }
   }
-  for (int p = 0; p < kNB; ++p) {
-    double* cp = colp[p & 1];
-    if (j == p) {
+  // pivot p = G c0 + g sits in register c0 of the threads with ibase == g, so
+  // with c0 unrolled the pivot row is a fixed register and every other entry
+  // takes one FMA per pivot
 #pragma unroll
-      for (int c = 0; c < kNB / 4; ++c) cp[ibase + 4 * c] = a[c];
-    }
-    __syncthreads();
-    const double d = cp[p];
-    if (!(d > 1e-11 * dscale)) {
-      if (t == 0) flags[4] = 1;
-      return;  // uniform across the block: every thread read the same d
-    }
-    const double inv = 1.0 / d;
-    const double f = cp[j] * inv;  // a_pj / d
-    const bool piv_col = j == p;
+  for (int c0 = 0; c0 < RPT; ++c0) {
+#pragma nounroll
+    for (int g = 0; g < G; ++g) {
+      const int p = G * c0 + g;
+      double* cp = colp[p & 1];
+      if (j == p) {
 #pragma unroll
-    for (int c = 0; c < kNB / 4; ++c) {
-      const int i = ibase + 4 * c;
-      const double ci = cp[i];
-      const double off = piv_col ? ci * inv : a[c] - ci * f;
-      const double on = piv_col ? -inv : f;
-      a[c] = (i == p) ? on : off;
+        for (int c = 0; c < RPT; ++c) cp[ibase + G * c] = a[c];
+      }
+      __syncthreads();
+      const double d = cp[p];
+      if (!(d > 1e-11 * dscale)) {
+        if (t == 0) flags[4] = 1;
+        return;  // uniform across the block: every thread read the same d
+      }
+      double ci[RPT];  // column p at this thread's rows, all read before use
+#pragma unroll
+      for (int c = 0; c < RPT; ++c) ci[c] = cp[ibase + G * c];
+      const double inv = 1.0 / d;
+      const double f = cp[j] * inv;  // a_pj / d
+      // a_ij - a_ip a_pj / d, and a_ip / d in the pivot column, as one
+      // branch-free FMA: x = -f, keep = 1 off the pivot column, x = 1/d, keep = 0 on it
+      const bool pc = j == p;
+      const double x = pc ? inv : -f, keep = pc ? 0.0 : 1.0;
+#pragma unroll
+      for (int c = 0; c < RPT; ++c) a[c] = __builtin_fma(ci[c], x, a[c] * keep);
+      if (ibase == g) a[c0] = (j == p) ? -inv : f;  // pivot row
     }
   }
 #pragma unroll
-  for (int c = 0; c < kNB / 4; ++c) {
-    const int i = ibase + 4 * c;
+  for (int c = 0; c < RPT; ++c) {
+    const int i = ibase + G * c;
     if (i < nb && j < nb) Dinv[i * nb + j] = -a[c];
   }
 }
 
 // Ct[q][i] = sum_p A[i][k0+p] Dinv[p][q] (0 for i in K); Pt[q][i] = A[i][k0+q].
-// One workgroup per 64 rows i: the 64 x 64 panel slice is staged in LDS with
-// coalesced loads (rows of A for i < k0, rows of A_K. for i >= k0, since only
-// the upper triangle is current), then multiplied by Dinv (4 x 4 outputs per
-// thread, indices strided by 16 so that LDS reads are conflict-free).
+// Workgroup (64 rows i, 64 columns q from qb = 64 blockIdx.y): the 64 x kNB
+// panel slice is staged in LDS with coalesced loads (rows of A for i < k0,
+// rows of A_K. for i >= k0, since only the upper triangle is current), then
+// multiplied by the kNB x 64 slice of Dinv (4 x 4 outputs per thread, indices
+// strided by 16 so that LDS reads are conflict-free).  One more column of
+// workgroups (i0 >= n) copies the upper triangle of the next pivot block
+// (k1, nb1 wide) into Dsave before this step's trailing update changes it.
 __global__ __launch_bounds__(kB) void sweep_panel_kernel(const double* __restrict__ A, int32_t lda, int32_t n,
                                                          int32_t k0, int32_t nb, const double* __restrict__ Dinv,
-                                                         double* Ct, double* Pt, int32_t ldt) {
-  __shared__ double T[64][65];   // T[r][p] = A[i0 + r][k0 + p]
-  __shared__ double Ds[64][65];  // Ds[p][q] = Dinv[p][q]
+                                                         double* Ct, double* Pt, int32_t ldt, int32_t k1,
+                                                         int32_t nb1, double* Dsave) {
+  __shared__ double T[64][kNB + 1];  // T[r][p] = A[i0 + r][k0 + p]
+  __shared__ double Ds[kNB][65];     // Ds[p][qq] = Dinv[p][qb + qq]
   const int t = threadIdx.x;
-  const int i0 = blockIdx.x * 64;
-  for (int e = t; e < 64 * 64; e += kB) {
-    const int p = e >> 6, q = e & 63;
-    Ds[p][q] = (p < nb && q < nb) ? Dinv[p * nb + q] : 0.0;
+  const int i0 = blockIdx.x * 64, qb = blockIdx.y * 64;
+  if (i0 >= n) {
+    for (int e = t; e < 64 * kNB; e += kB) {
+      const int r = qb + e / kNB, c = e % kNB;
+      if (r < nb1 && c >= r && c < nb1) Dsave[r * kNB + c] = A[static_cast<int64_t>(k1 + r) * lda + k1 + c];
+    }
+    return;
   }
-  if (i0 < k0) {  // the whole tile lies above K (k0 and i0 are multiples of 64)
-    for (int e = t; e < 64 * 64; e += kB) {
-      const int r = e >> 6, p = e & 63;
+  for (int e = t; e < kNB * 64; e += kB) {
+    const int p = e >> 6, qq = e & 63;
+    Ds[p][qq] = (p < nb && qb + qq < nb) ? Dinv[p * nb + qb + qq] : 0.0;
+  }
+  if (i0 < k0) {  // the whole slice lies above K (k0 and i0 are multiples of 64)
+    for (int e = t; e < 64 * kNB; e += kB) {
+      const int r = e / kNB, p = e % kNB;
       T[r][p] = (i0 + r < n && p < nb) ? A[static_cast<int64_t>(i0 + r) * lda + k0 + p] : 0.0;
     }
   } else {
-    for (int e = t; e < 64 * 64; e += kB) {
+    for (int e = t; e < 64 * kNB; e += kB) {
       const int p = e >> 6, r = e & 63;
       T[r][p] = (i0 + r < n && p < nb) ? A[static_cast<int64_t>(k0 + p) * lda + i0 + r] : 0.0;
     }
@@ -354,7 +420,7 @@ __global__ __launch_bounds__(kB) void sweep_panel_kernel(const double* __restric
   __syncthreads();
   const int tx = t & 15, ty = t >> 4;
   double acc[4][4] = {};
-  for (int p = 0; p < 64; ++p) {
+  for (int p = 0; p < kNB; ++p) {
     double tv[4], dv[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) tv[a] = T[ty + 16 * a][p];
@@ -371,12 +437,13 @@ __global__ __launch_bounds__(kB) void sweep_panel_kernel(const double* __restric
     const bool inK = (i >= k0 && i < k0 + nb);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int q = tx + 16 * c;
+      const int q = qb + tx + 16 * c;
       if (i < n && q < nb) Ct[static_cast<int64_t>(q) * ldt + i] = inK ? 0.0 : acc[a][c];
     }
   }
   for (int e = t; e < 64 * 64; e += kB) {
-    const int q = e >> 6, r = e & 63;
+    const int qq = e >> 6, r = e & 63;
+    const int q = qb + qq;
     if (i0 + r < n && q < nb) Pt[static_cast<int64_t>(q) * ldt + i0 + r] = T[r][q];
   }
 }
@@ -1239,29 +1306,56 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
       XM_HIP(hipStreamSynchronize(s));
     }
     require(dscale > 0.0, XM_EGRAPH, "the grounded Laplacian has no positive diagonal entry");
-    DevBuf<double> Dinv(kNB * kNB);
+    // Dinv of the current and of the next step; Dsave: copy of the next pivot block
+    DevBuf<double> Dinv(2 * kNB * kNB), Dsave(kNB * kNB);
     DevBuf<double> Ct(static_cast<size_t>(kNB) * P->ldg), Pt(static_cast<size_t>(kNB) * P->ldg);
     const std::vector<int32_t> htiles = sweep_tile_list(static_cast<int>(cdiv(ng, 64)));
     const int32_t ntiles = static_cast<int32_t>(htiles.size() / 2);
     DevBuf<int32_t> tiles(htiles.size());
     XM_HIP(hipMemcpy(tiles.ptr, htiles.data(), htiles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     const unsigned ublocks = 8 * cdiv(ntiles, 8);
+    // The inversion of the next pivot block runs on a second stream while the
+    // trailing update of the current step runs on s (look-ahead).
+    struct SideStream {
+      hipStream_t st = nullptr;
+      hipEvent_t panel_done = nullptr, pivot_done = nullptr;
+      ~SideStream() {
+        if (panel_done) (void)hipEventDestroy(panel_done);
+        if (pivot_done) (void)hipEventDestroy(pivot_done);
+        if (st) (void)hipStreamDestroy(st);
+      }
+    } side;
+    XM_HIP(hipStreamCreateWithFlags(&side.st, hipStreamNonBlocking));
+    XM_HIP(hipEventCreateWithFlags(&side.panel_done, hipEventDisableTiming));
+    XM_HIP(hipEventCreateWithFlags(&side.pivot_done, hipEventDisableTiming));
     LaunchTimer t_sweep;
-    for (int32_t k0 = 0; k0 < ng; k0 += kNB) {
+    hipLaunchKernelGGL(sweep_pivot_kernel, dim3(1), dim3(kPivotThreads), 0, s, P->Gm.ptr, P->ldg, 0,
+                       std::min(kNB, ng), dscale, nullptr, nullptr, nullptr, 0, 0, Dinv.ptr, flags.ptr);
+    XM_LAUNCH_CHECK("sweep_pivot_kernel");
+    for (int32_t k0 = 0, step = 0; k0 < ng; k0 += kNB, ++step) {
       const int32_t nb = std::min(kNB, ng - k0);
-      hipLaunchKernelGGL(sweep_pivot_kernel, dim3(1), dim3(kB), 0, s, P->Gm.ptr, P->ldg, k0, nb, dscale,
-                         Dinv.ptr, flags.ptr);
-      XM_LAUNCH_CHECK("sweep_pivot_kernel");
-      hipLaunchKernelGGL(sweep_panel_kernel, dim3(cdiv(ng, 64)), dim3(kB), 0, s, P->Gm.ptr, P->ldg, ng, k0, nb,
-                         Dinv.ptr, Ct.ptr, Pt.ptr, P->ldg);
+      const int32_t k1 = k0 + kNB, nb1 = std::max(0, std::min(kNB, ng - k1));
+      double* Dk = Dinv.ptr + (step & 1) * kNB * kNB;
+      double* Dn = Dinv.ptr + ((step + 1) & 1) * kNB * kNB;
+      if (step > 0) XM_HIP(hipStreamWaitEvent(s, side.pivot_done, 0));
+      hipLaunchKernelGGL(sweep_panel_kernel, dim3(cdiv(ng, 64) + (nb1 > 0 ? 1 : 0), kNB / 64), dim3(kB), 0, s,
+                         P->Gm.ptr, P->ldg, ng, k0, nb, Dk, Ct.ptr, Pt.ptr, P->ldg, k1, nb1, Dsave.ptr);
       XM_LAUNCH_CHECK("sweep_panel_kernel");
+      if (nb1 > 0) {
+        XM_HIP(hipEventRecord(side.panel_done, s));
+        XM_HIP(hipStreamWaitEvent(side.st, side.panel_done, 0));
+        hipLaunchKernelGGL(sweep_pivot_kernel, dim3(1), dim3(kPivotThreads), 0, side.st, P->Gm.ptr, P->ldg, k1,
+                           nb1, dscale, Dsave.ptr, Ct.ptr, Pt.ptr, P->ldg, nb, Dn, flags.ptr);
+        XM_LAUNCH_CHECK("sweep_pivot_kernel");
+        XM_HIP(hipEventRecord(side.pivot_done, side.st));
+      }
       t_sweep.start(s);
       hipLaunchKernelGGL(sweep_update_kernel, dim3(ublocks), dim3(kB), 0, s, P->Gm.ptr, P->ldg, ng, Ct.ptr,
                          Pt.ptr, P->ldg, nb, tiles.ptr, ntiles);
       XM_LAUNCH_CHECK("sweep_update_kernel");
       t_sweep.stop(s);
       hipLaunchKernelGGL(sweep_finish_kernel, dim3(cdiv(ng, kB), nb), dim3(kB), 0, s, P->Gm.ptr, P->ldg, ng, k0,
-                         nb, Ct.ptr, P->ldg, Dinv.ptr);
+                         nb, Ct.ptr, P->ldg, Dk);
       XM_LAUNCH_CHECK("sweep_finish_kernel");
     }
     {
