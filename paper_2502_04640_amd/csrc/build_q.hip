@@ -380,19 +380,24 @@ __global__ __launch_bounds__(kPivotThreads) void sweep_pivot_kernel(
 }
 
 // Ct[q][i] = sum_p A[i][k0+p] Dinv[p][q] (0 for i in K); Pt[q][i] = A[i][k0+q].
-// Workgroup (64 rows i, 64 columns q from qb = 64 blockIdx.y): the 64 x kNB
-// panel slice is staged in LDS with coalesced loads (rows of A for i < k0,
-// rows of A_K. for i >= k0, since only the upper triangle is current), then
-// multiplied by the kNB x 64 slice of Dinv (4 x 4 outputs per thread, indices
-// strided by 16 so that LDS reads are conflict-free).  One more column of
-// workgroups (i0 >= n) copies the upper triangle of the next pivot block
+// Workgroup: the 64 x 64 block of Ct at columns q from qb = 64 blockIdx.y and
+// rows i from i0 = 64 blockIdx.x, on FP64 matrix cores: each wave a 32 x 32
+// quarter as 2 x 2 v_mfma_f64_16x16x4f64 blocks (A operand Dinv[p][q] as [q][p],
+// B operand the panel as [p][i], so the 16 lanes of a result row hold
+// consecutive i and the stores to Ct are contiguous).  The panel (rows of A for
+// i < k0, rows of A_K. for i >= k0, since only the upper triangle is current)
+// and Dinv go through LDS in chunks of 16 p, double-buffered; the workgroups
+// with blockIdx.y = 0 also write the staged panel out as Pt.  One more column
+// of workgroups (i0 >= n) copies the upper triangle of the next pivot block
 // (k1, nb1 wide) into Dsave before this step's trailing update changes it.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kPanelKC = 16;
 __global__ __launch_bounds__(kB) void sweep_panel_kernel(const double* __restrict__ A, int32_t lda, int32_t n,
                                                          int32_t k0, int32_t nb, const double* __restrict__ Dinv,
                                                          double* Ct, double* Pt, int32_t ldt, int32_t k1,
                                                          int32_t nb1, double* Dsave) {
-  __shared__ double T[64][kNB + 1];  // T[r][p] = A[i0 + r][k0 + p]
-  __shared__ double Ds[kNB][65];     // Ds[p][qq] = Dinv[p][qb + qq]
+  __shared__ double Ds[2][kPanelKC][64];  // Ds[k][q] = Dinv[p0 + k][qb + q]
+  __shared__ double Ts[2][kPanelKC][64];  // Ts[k][i] = A[i0 + i][k0 + p0 + k]
   const int t = threadIdx.x;
   const int i0 = blockIdx.x * 64, qb = blockIdx.y * 64;
   if (i0 >= n) {
@@ -402,50 +407,79 @@ __global__ __launch_bounds__(kB) void sweep_panel_kernel(const double* __restric
     }
     return;
   }
-  for (int e = t; e < kNB * 64; e += kB) {
-    const int p = e >> 6, qq = e & 63;
-    Ds[p][qq] = (p < nb && qb + qq < nb) ? Dinv[p * nb + qb + qq] : 0.0;
-  }
-  if (i0 < k0) {  // the whole slice lies above K (k0 and i0 are multiples of 64)
-    for (int e = t; e < 64 * kNB; e += kB) {
-      const int r = e / kNB, p = e % kNB;
-      T[r][p] = (i0 + r < n && p < nb) ? A[static_cast<int64_t>(i0 + r) * lda + k0 + p] : 0.0;
+  const bool above = i0 < k0;  // the whole slice lies above K (k0 and i0 are multiples of 64)
+  const bool write_pt = blockIdx.y == 0;
+  constexpr int kPer = kPanelKC * 64 / kB;  // staged entries per thread and operand
+  double rd[kPer], rt[kPer];
+  auto fetch = [&](int p0) {
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = t + kB * m;
+      {
+        const int k = e >> 6, q = e & 63;
+        const int pp = p0 + k;
+        rd[m] = (pp < nb && qb + q < nb) ? Dinv[pp * nb + qb + q] : 0.0;
+      }
+      if (above) {  // 16 consecutive p per row i
+        const int k = e & 15, i = e >> 4;
+        rt[m] = (i0 + i < n && p0 + k < nb) ? A[static_cast<int64_t>(i0 + i) * lda + k0 + p0 + k] : 0.0;
+      } else {      // 64 consecutive i per row p
+        const int k = e >> 6, i = e & 63;
+        rt[m] = (i0 + i < n && p0 + k < nb) ? A[static_cast<int64_t>(k0 + p0 + k) * lda + i0 + i] : 0.0;
+      }
     }
-  } else {
-    for (int e = t; e < 64 * kNB; e += kB) {
-      const int p = e >> 6, r = e & 63;
-      T[r][p] = (i0 + r < n && p < nb) ? A[static_cast<int64_t>(k0 + p) * lda + i0 + r] : 0.0;
+  };
+  auto stash = [&](int buf, int p0) {
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = t + kB * m;
+      Ds[buf][e >> 6][e & 63] = rd[m];
+      const int k = above ? (e & 15) : (e >> 6), i = above ? (e >> 4) : (e & 63);
+      Ts[buf][k][i] = rt[m];
+      if (write_pt && p0 + k < nb && i0 + i < n) Pt[static_cast<int64_t>(p0 + k) * ldt + i0 + i] = rt[m];
     }
-  }
+  };
+  const int lane = t & 63, wave = t >> 6;
+  const int wq = (wave >> 1) * 32, wi = (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  stash(0, 0);
   __syncthreads();
-  const int tx = t & 15, ty = t >> 4;
-  double acc[4][4] = {};
-  for (int p = 0; p < kNB; ++p) {
-    double tv[4], dv[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) tv[a] = T[ty + 16 * a][p];
+  for (int ch = 0; ch < kNB / kPanelKC; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < kNB / kPanelKC;
+    if (more) fetch((ch + 1) * kPanelKC);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) dv[c] = Ds[p][tx + 16 * c];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] += tv[a] * dv[c];
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = i0 + ty + 16 * a;
-    const bool inK = (i >= k0 && i < k0 + nb);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int q = qb + tx + 16 * c;
-      if (i < n && q < nb) Ct[static_cast<int64_t>(q) * ldt + i] = inK ? 0.0 : acc[a][c];
+    for (int k = 0; k < kPanelKC; k += 4) {
+      const double a0 = Ds[buf][k + lk][wq + lr], a1 = Ds[buf][k + lk][wq + 16 + lr];
+      const double b0 = Ts[buf][k + lk][wi + lr], b1 = Ts[buf][k + lk][wi + 16 + lr];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    if (more) {
+      stash(buf ^ 1, (ch + 1) * kPanelKC);
+      __syncthreads();
     }
   }
-  for (int e = t; e < 64 * 64; e += kB) {
-    const int qq = e >> 6, r = e & 63;
-    const int q = qb + qq;
-    if (i0 + r < n && q < nb) Pt[static_cast<int64_t>(q) * ldt + i0 + r] = T[r][q];
-  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = qb + wq + 16 * a + lk + 4 * r;
+        const int i = i0 + wi + 16 * b + lr;
+        const bool inK = (i >= k0 && i < k0 + nb);
+        if (q < nb && i < n) Ct[static_cast<int64_t>(q) * ldt + i] = inK ? 0.0 : acc[a][b][r];
+      }
 }
 
 // A[i][j] -= sum_p Ct[p][i] Pt[p][j] on the 64 x 64 tiles J >= I.  Each wave
@@ -460,7 +494,6 @@ __global__ __launch_bounds__(kB) void sweep_panel_kernel(const double* __restric
 // Workgroup w takes tile tiles[w mod 8][w / 8] of a list cut into 8 contiguous
 // runs, one per XCD (w runs on XCD w mod 8), each run ordered by 8 x 8 blocks
 // of tiles, so that the panel slices a run needs at a time stay in its L2.
-typedef double v4d __attribute__((ext_vector_type(4)));
 #ifndef XM_SWEEP_SB
 #define XM_SWEEP_SB 8
 #endif
