@@ -146,21 +146,29 @@ __global__ void segment_starts_kernel(const uint32_t* __restrict__ keys, const i
   }
 }
 
-// One wavefront per frame pair: sum the 4x4 contributions of its observation
-// pairs, write the rotation block into Q and the A_rt / A_tt entries.
+// One group of kRedLanes lanes per frame pair: sum the 4x4 contributions of
+// its observation pairs (strided over the group, then a fixed xor tree), write
+// the rotation block into Q and the A_rt / A_tt entries.  A frame pair holds
+// about ten observation pairs on average (the diagonal ones hundreds), so a
+// group narrower than the wavefront wastes fewer lanes and reduction steps.
+#ifndef XM_RED_LANES
+#define XM_RED_LANES 16
+#endif
+constexpr int kRedLanes = XM_RED_LANES;
+static_assert(kRedLanes == 8 || kRedLanes == 16 || kRedLanes == 32 || kRedLanes == 64, "lane groups of 8 to 64");
 __global__ __launch_bounds__(kB) void reduce_blocks_kernel(
     const int64_t* __restrict__ seg_start, const uint32_t* __restrict__ seg_key, int64_t S, int32_t N,
     const uint64_t* __restrict__ vals, const double* __restrict__ u_s, const double* __restrict__ w_s,
     const int32_t* __restrict__ lm_s, const double* __restrict__ Wl, const int32_t* __restrict__ pos, double* Q,
     int32_t ld, double* Art, double* Att, double* fac) {
-  const int64_t s = static_cast<int64_t>(blockIdx.x) * (kB / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * (kB / kRedLanes) + threadIdx.x / kRedLanes;
+  const int lane = threadIdx.x % kRedLanes;
   if (s >= S) return;
   const int64_t lo = seg_start[s], hi = seg_start[s + 1];
   double acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  for (int64_t q = lo + lane; q < hi; q += 64) {
+  for (int64_t q = lo + lane; q < hi; q += kRedLanes) {
     const uint64_t v = vals[q];
     const int64_t pa = static_cast<int64_t>(v >> 32), pb = static_cast<int64_t>(v & 0xffffffffull);
     const double wa = w_s[pa], wb = w_s[pb];
@@ -176,7 +184,9 @@ __global__ __launch_bounds__(kB) void reduce_blocks_kernel(
     }
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = wave_sum(acc[q]);
+  for (int q = 0; q < 16; ++q)
+#pragma unroll
+    for (int off = kRedLanes / 2; off >= 1; off >>= 1) acc[q] += __shfl_xor(acc[q], off, kRedLanes);
   if (lane == 0) {
     const uint32_t key = seg_key[s];
     const int64_t i = key / static_cast<uint32_t>(N), j = key % static_cast<uint32_t>(N);
@@ -1304,7 +1314,7 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   P->Art.alloc(3 * S);
   P->Att.alloc(S);
   P->fac.alloc(15 * S);
-  hipLaunchKernelGGL(reduce_blocks_kernel, dim3(cdiv(S, kB / 64)), dim3(kB), 0, s, seg_start.ptr, seg_key.ptr,
+  hipLaunchKernelGGL(reduce_blocks_kernel, dim3(cdiv(S, kB / kRedLanes)), dim3(kB), 0, s, seg_start.ptr, seg_key.ptr,
                      S, N, pvals.ptr, P->u_s.ptr, P->w_s.ptr, P->lm_s.ptr, P->Wl.ptr, P->pos.ptr, P->Q64.ptr,
                      P->ld, P->Art.ptr, P->Att.ptr, P->fac.ptr);
   XM_LAUNCH_CHECK("reduce_blocks_kernel");
