@@ -125,6 +125,14 @@ def test_build_q_errors():
     with pytest.raises(xm.XMError, match="XM_EGRAPH"):
         xm.build_Q(12, 100, torch.from_numpy(fr2).cuda(), torch.from_numpy(lm2).cuda(),
                    torch.from_numpy(u2).cuda(), torch.from_numpy(w2).cuda())
+    # the same with 2 x 150 frames: the inversion spans several 128-wide pivot
+    # blocks, and the zero pivot falls in one inverted ahead on the second stream
+    b = scenes.random_scene(150, 1500, L=4, sigma=0.01, seed=2)
+    fr3 = np.r_[b.frame, b.frame + 150].astype(np.int32)
+    lm3 = np.r_[b.landmark, b.landmark + 1500].astype(np.int32)
+    with pytest.raises(xm.XMError, match="XM_EGRAPH"):
+        xm.build_Q(300, 3000, torch.from_numpy(fr3).cuda(), torch.from_numpy(lm3).cuda(),
+                   torch.from_numpy(np.r_[b.u, b.u]).cuda(), torch.from_numpy(np.r_[b.w, b.w]).cuda())
 
 
 @pytest.mark.parametrize("r", [1, 3, 5, 8])
