@@ -493,11 +493,11 @@ __global__ __launch_bounds__(kB) void sweep_panel_kernel(const double* __restric
 }
 
 // A[i][j] -= sum_p Ct[p][i] Pt[p][j] on the 64 x 64 tiles J >= I.  Each wave
-// forms a 32 x 32 quarter as 2 x 2 blocks of v_mfma_f64_16x16x4f64 over 16
+// forms a 32 x 32 quarter as 2 x 2 blocks of v_mfma_f64_16x16x4f64 over kNB / 4
 // k-steps: lane l supplies A-operand [i = l % 16][k = l / 16] and B-operand
 // [k = l / 16][j = l % 16]; register q of the result holds [l / 16 + 4 q][l % 16].
 // The tile of A is loaded into registers first (its HBM latency overlaps the
-// panel staging), the rank-64 product is accumulated from zero and subtracted
+// panel staging), the rank-kNB product is accumulated from zero and subtracted
 // once at the end (one rounding at the scale of A).  The panels go through LDS
 // in chunks of kSweepKC rows, double-buffered: the next chunk's loads are in
 // flight while the current one is multiplied.
