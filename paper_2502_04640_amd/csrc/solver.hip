@@ -91,6 +91,25 @@ __global__ void combine_kernel(int64_t n, const double* __restrict__ Gref, T* __
   G[i] = static_cast<T>(g);
 }
 
+// start of a truncated-CG solve: eta = 0, H eta = 0, residual = gradient
+// (rotation block of nvr values and scale block of N values, in one launch)
+template <typename T>
+__global__ void tcg_init_kernel(int64_t nvr, int32_t N, const T* __restrict__ gR, const T* __restrict__ gs,
+                                T* __restrict__ etaR, T* __restrict__ etas, T* __restrict__ HetaR,
+                                T* __restrict__ Hetas, T* __restrict__ resR, T* __restrict__ ress) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < nvr) {
+    etaR[i] = T(0);
+    HetaR[i] = T(0);
+    resR[i] = gR[i];
+  }
+  if (i < N) {
+    etas[i] = T(0);
+    Hetas[i] = T(0);
+    ress[i] = gs[i];
+  }
+}
+
 template <typename T>
 __global__ void widen_kernel(int64_t n, const T* __restrict__ a, double* __restrict__ out) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
@@ -192,12 +211,10 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
       break;
     }
     // ---- truncated CG ----
-    XM_HIP(hipMemsetAsync(V.etaR.ptr, 0, nvr * sizeof(T), st));
-    XM_HIP(hipMemsetAsync(V.etas.ptr, 0, N * sizeof(T), st));
-    XM_HIP(hipMemsetAsync(V.HetaR.ptr, 0, nvr * sizeof(T), st));
-    XM_HIP(hipMemsetAsync(V.Hetas.ptr, 0, N * sizeof(T), st));
-    XM_HIP(hipMemcpyAsync(V.resR.ptr, V.gR.ptr, nvr * sizeof(T), hipMemcpyDeviceToDevice, st));
-    XM_HIP(hipMemcpyAsync(V.ress.ptr, V.gs.ptr, N * sizeof(T), hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(tcg_init_kernel<T>, dim3(cdiv(std::max<size_t>(nvr, N), 256)), dim3(256), 0, st,
+                       static_cast<int64_t>(nvr), N, V.gR.ptr, V.gs.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr,
+                       V.Hetas.ptr, V.resR.ptr, V.ress.ptr);
+    XM_LAUNCH_CHECK("tcg_init_kernel");
     mf.pscale = pscale;
     double z_r = gpg;  // <res, P res>
     const double norm_r0 = std::sqrt(gg);
