@@ -769,9 +769,30 @@ __global__ void block_sqrt_kernel(const double* __restrict__ Q, int32_t N, int32
   ext[2 * k + 1] = fmax(lam[0], fmax(lam[1], lam[2]));
 }
 
+// four values per thread (32-byte loads, 16-byte stores; in and out are
+// allocation starts, so every group of four is aligned)
+constexpr int kF32Per = 4;
 __global__ void to_f32_kernel(const double* __restrict__ in, int64_t n, float* out) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
-  if (e < n) out[e] = static_cast<float>(in[e]);
+  const int64_t e = (static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x) * kF32Per;
+  if (e + kF32Per <= n) {
+    const double2 a = *reinterpret_cast<const double2*>(in + e);
+    const double2 b = *reinterpret_cast<const double2*>(in + e + 2);
+    *reinterpret_cast<float4*>(out + e) = make_float4(static_cast<float>(a.x), static_cast<float>(a.y),
+                                                      static_cast<float>(b.x), static_cast<float>(b.y));
+  } else {
+    for (int64_t k = e; k < n; ++k) out[k] = static_cast<float>(in[k]);
+  }
+}
+
+// Zero row i of Q from column c0 = 3 floor(i / 3) rounded down to a multiple
+// of 64 to the end of the row (padding included): every entry the assembly
+// reads before the lower triangle is copied from the upper one.
+__global__ __launch_bounds__(kB) void zero_upper_kernel(double* Q, int32_t ld) {
+  const int i = blockIdx.x;
+  const int c0 = (3 * (i / 3)) & ~63;
+  double2* row = reinterpret_cast<double2*>(Q + static_cast<int64_t>(i) * ld + c0);
+  const int n2 = (ld - c0) / 2;
+  for (int e = threadIdx.x; e < n2; e += kB) row[e] = make_double2(0.0, 0.0);
 }
 
 // round-to-nearest-even FP64 -> BF16 (through FP32; NaN not expected here)
@@ -1300,10 +1321,12 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   XM_LAUNCH_CHECK("segment_starts_kernel");
   sidx.release();
 
-  // Q storage (zeroed) and the per-block reduction
+  // Q storage (zeroed on and right of the diagonal blocks; the lower triangle
+  // is written from the upper one at the end) and the per-block reduction
   const size_t qn = static_cast<size_t>(P->n3) * P->ld;
   P->Q64.alloc(qn);
-  XM_HIP(hipMemsetAsync(P->Q64.ptr, 0, qn * sizeof(double), s));
+  hipLaunchKernelGGL(zero_upper_kernel, dim3(P->n3), dim3(kB), 0, s, P->Q64.ptr, P->ld);
+  XM_LAUNCH_CHECK("zero_upper_kernel");
   P->row_ptr.alloc(N + 1);
   P->col.alloc(S);
   hipLaunchKernelGGL(pattern_kernel, dim3(cdiv(S + 1, kB)), dim3(kB), 0, s, seg_key.ptr, S, N, P->row_ptr.ptr,
@@ -1516,13 +1539,14 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   }
   if (copies & XM_KEEP_F32) {
     P->Q32.alloc(qn);
-    hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(qn, kB)), dim3(kB), 0, s, P->Q64.ptr, static_cast<int64_t>(qn),
+    hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(qn, kF32Per * kB)), dim3(kB), 0, s, P->Q64.ptr,
+                       static_cast<int64_t>(qn),
                        P->Q32.ptr);
     XM_LAUNCH_CHECK("to_f32_kernel");
     // FP32 factors for the factored curvature product
     auto to32 = [&](const DevBuf<double>& src, DevBuf<float>& dst) {
       dst.alloc(src.n);
-      hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(src.n, kB)), dim3(kB), 0, s, src.ptr,
+      hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(src.n, kF32Per * kB)), dim3(kB), 0, s, src.ptr,
                          static_cast<int64_t>(src.n), dst.ptr);
       XM_LAUNCH_CHECK("to_f32_kernel");
     };
