@@ -660,20 +660,33 @@ __global__ __launch_bounds__(kB) void transpose_kernel(const double* __restrict_
 // Q[c][r] <- Q[r][c] for r < c: the lower triangle copied from the upper one,
 // one 32 x 32 tile pair (I <= J) per block, staged through LDS so that both
 // the read of tile (I, J) and the write of tile (J, I) are coalesced.
-__global__ __launch_bounds__(kB) void symmetrize_kernel(double* Q, int32_t n, int32_t ld) {
+__global__ __launch_bounds__(kB) void symmetrize_kernel(double* Q, int32_t n, int32_t ld, float* Q32) {
   const int I = blockIdx.y, J = blockIdx.x;
   if (I > J) return;
   __shared__ double a[32][33];
   const int r0 = I * 32, c0 = J * 32;
   for (int e = threadIdx.x; e < 32 * 32; e += kB) {
     const int r = e / 32, c = e % 32;
-    a[r][c] = (r0 + r < n && c0 + c < n) ? Q[static_cast<int64_t>(r0 + r) * ld + c0 + c] : 0.0;  // tile (I, J)
+    const bool in = r0 + r < n && c0 + c < n;
+    a[r][c] = in ? Q[static_cast<int64_t>(r0 + r) * ld + c0 + c] : 0.0;  // tile (I, J)
+    // FP32 copy of the upper triangle (diagonal included) as it is read
+    if (Q32 && in && r0 + r <= c0 + c)
+      Q32[static_cast<int64_t>(r0 + r) * ld + c0 + c] = static_cast<float>(a[r][c]);
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 32 * 32; e += kB) {
     const int c = e / 32, r = e % 32;  // write row c0 + c of tile (J, I), consecutive r
-    if (r0 + r < n && c0 + c < n && r0 + r < c0 + c) Q[static_cast<int64_t>(c0 + c) * ld + r0 + r] = a[r][c];
+    if (r0 + r < n && c0 + c < n && r0 + r < c0 + c) {
+      Q[static_cast<int64_t>(c0 + c) * ld + r0 + r] = a[r][c];
+      if (Q32) Q32[static_cast<int64_t>(c0 + c) * ld + r0 + r] = static_cast<float>(a[r][c]);
+    }
   }
+}
+
+// columns n .. ld of every row (the padding of the FP32 copy of Q)
+__global__ __launch_bounds__(kB) void zero_pad_kernel(float* Q32, int32_t n, int32_t ld) {
+  const int i = blockIdx.x;
+  for (int c = n + threadIdx.x; c < ld; c += kB) Q32[static_cast<int64_t>(i) * ld + c] = 0.0f;
 }
 
 __global__ __launch_bounds__(kB) void trace_kernel(const double* __restrict__ Q, int32_t n, int32_t ld,
@@ -1426,7 +1439,7 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
     }
     {
       const unsigned T = cdiv(ng, 32);
-      hipLaunchKernelGGL(symmetrize_kernel, dim3(T, T), dim3(kB), 0, s, P->Gm.ptr, ng, P->ldg);
+      hipLaunchKernelGGL(symmetrize_kernel, dim3(T, T), dim3(kB), 0, s, P->Gm.ptr, ng, P->ldg, nullptr);
       XM_LAUNCH_CHECK("symmetrize_kernel(G)");
     }
     XM_HIP(hipMemcpyAsync(hflags, flags.ptr, sizeof(hflags), hipMemcpyDeviceToHost, s));
@@ -1504,8 +1517,16 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
                               6.0 * nnz_off * P->n3 * 0.5});
   }
   {
+    // the FP32 copy of Q (XM_KEEP_F32) is written while the lower triangle is filled
+    float* q32 = nullptr;
+    if (copies & XM_KEEP_F32) {
+      P->Q32.alloc(qn);
+      hipLaunchKernelGGL(zero_pad_kernel, dim3(P->n3), dim3(kB), 0, s, P->Q32.ptr, P->n3, P->ld);
+      XM_LAUNCH_CHECK("zero_pad_kernel");
+      q32 = P->Q32.ptr;
+    }
     const unsigned T = cdiv(P->n3, 32);
-    hipLaunchKernelGGL(symmetrize_kernel, dim3(T, T), dim3(kB), 0, s, P->Q64.ptr, P->n3, P->ld);
+    hipLaunchKernelGGL(symmetrize_kernel, dim3(T, T), dim3(kB), 0, s, P->Q64.ptr, P->n3, P->ld, q32);
     XM_LAUNCH_CHECK("symmetrize_kernel");
     DevBuf<double> tr(1);
     hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(kB), 0, s, P->Q64.ptr, P->n3, P->ld, tr.ptr);
@@ -1538,11 +1559,6 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
     }
   }
   if (copies & XM_KEEP_F32) {
-    P->Q32.alloc(qn);
-    hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(qn, kF32Per * kB)), dim3(kB), 0, s, P->Q64.ptr,
-                       static_cast<int64_t>(qn),
-                       P->Q32.ptr);
-    XM_LAUNCH_CHECK("to_f32_kernel");
     // FP32 factors for the factored curvature product
     auto to32 = [&](const DevBuf<double>& src, DevBuf<float>& dst) {
       dst.alloc(src.n);
