@@ -26,6 +26,12 @@ rows(U) in the coordinates of Z); for v in that complement
 v^T Z v >= ls v^T D v, which gives the lower bound
 lambda_bound = ls * (d_min if ls >= 0 else d_max) over unit v, d_min, d_max
 the extreme eigenvalues of the Q_kk.
+
+That bound covers the complement only, which decides PSD-ness of Z only when
+Z U^T = 0.  certificate_bound folds in the deflated block itself (its
+smallest eigenvalue and its coupling to the complement, both zero at a
+critical point) to bound the whole spectrum, so that a U that is not a
+critical point is not taken for a certificate.
 """
 from __future__ import annotations
 
@@ -110,6 +116,55 @@ def min_eig_scaled(Q, Z, U):
     return lam, bound, dmin, dmax
 
 
+def _orth_basis(A, rel=1e-10):
+    """Orthonormal basis of the column space of A (columns with a singular
+    value below rel times the largest are dropped)."""
+    Uo, sv, _ = np.linalg.svd(A, full_matrices=False)
+    if sv.size == 0 or sv[0] == 0:
+        return Uo[:, :0]
+    return Uo[:, sv > rel * sv[0]]
+
+
+def certificate_bound(Q, U):
+    """Lower bound on the whole spectrum of Zs = D^{-1/2} Z D^{-1/2} from the
+    deflated block, valid at any U (not only at critical points).
+
+    W: orthonormal basis of D^{1/2} rows(U).  For unit v = x + y with x in
+    span W and y orthogonal to it, v^T Zs v >= a|x|^2 + b|y|^2 - 2e|x||y|,
+    with a = lambda_min(W^T Zs W), b = lambda_min of Zs on the complement and
+    e = |(I - W W^T) Zs W|; minimising over |x|^2 + |y|^2 = 1 gives
+    (a + b)/2 - sqrt(((a - b)/2)^2 + e^2).  Returns a, b, e (spectral norm),
+    e_fro (Frobenius norm, an upper bound on e), the bound with each, the
+    bound on v^T Z v for unit v it implies (d_min or d_max scaling, with the
+    Frobenius form), and the exact smallest eigenvalue of Zs (dense)."""
+    Lam = dual_lambda(Q, U, mf.from_U(U)[1])
+    Z = dual_matrix(Q, Lam)
+    Dh, Dm, dmin, dmax = block_sqrt(Q)
+    Dmh = _blkdiag(Dm)
+    Zs = Dmh @ Z @ Dmh
+    Zs = 0.5 * (Zs + Zs.T)
+    W = _orth_basis(_blkdiag(Dh) @ U.T)
+    ZW = Zs @ W
+    Mw = W.T @ ZW
+    a = float(np.linalg.eigvalsh(0.5 * (Mw + Mw.T))[0])
+    E = ZW - W @ Mw
+    e = float(np.linalg.norm(E, 2))
+    e_fro = float(np.linalg.norm(E))
+    n = Zs.shape[0]
+    Qf, _ = np.linalg.qr(W, mode="complete")
+    C = Qf[:, W.shape[1]:]
+    b = float(np.linalg.eigvalsh(C.T @ Zs @ C)[0])
+
+    def comb(ee):
+        return 0.5 * (a + b) - np.sqrt(0.25 * (a - b) ** 2 + ee * ee)
+
+    full = comb(e_fro)
+    return {"defl_min": a, "complement_min": b, "cross": e, "cross_fro": e_fro,
+            "bound_scaled": float(comb(e)), "bound_scaled_fro": float(full),
+            "lambda_bound": float(full * (dmin if full >= 0 else dmax)),
+            "lambda_min_scaled_full": float(np.linalg.eigvalsh(Zs)[0]), "dmin": dmin, "dmax": dmax, "n": n}
+
+
 def certify(Q, R, s, tau):
     """Certificate at (R, s): dict with lambda_min (complement), lambda_min_full,
     primal tr(Q U^T U), dual tr(Lambda_0), certified flag and escape vector."""
@@ -118,13 +173,16 @@ def certify(Q, R, s, tau):
     Z = dual_matrix(Q, Lam)
     lam, v, full = min_eig(Z, U)
     lam_s, bound, dmin, dmax = min_eig_scaled(Q, Z, U)
+    cb = certificate_bound(Q, U)
     N = R.shape[0]
     qbar = float(np.trace(Q)) / (3 * N)
     primal = float(np.sum(U * (U @ Q)))
     dual = float(np.trace(Lam[0]))
     return {"lambda_min": lam, "lambda_min_full": full, "v": v, "primal": primal,
             "dual": dual, "certified": bool(lam >= -tau * qbar), "qbar": qbar, "Lambda": Lam,
-            "lambda_min_scaled": lam_s, "lambda_bound": bound, "dmin": dmin, "dmax": dmax}
+            "lambda_min_scaled": lam_s, "lambda_bound": bound, "dmin": dmin, "dmax": dmax,
+            "defl_min": cb["defl_min"], "defl_cross": cb["cross_fro"], "lambda_bound_full": cb["lambda_bound"],
+            "stat_res": float(np.linalg.norm(Z @ U.T))}
 
 
 def suboptimality(rho_hat, rho_sdp):

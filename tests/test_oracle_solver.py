@@ -268,3 +268,51 @@ def test_scaled_certificate_inertia_and_bound(case):
         v = P @ rng.standard_normal(Q.shape[0])
         v /= np.linalg.norm(v)
         assert v @ Z @ v >= c["lambda_bound"] - 1e-9 * c["qbar"]
+
+
+@pytest.mark.parametrize("case", ["optimum", "near", "perturbed", "random"])
+def test_full_spectrum_bound_holds_at_any_point(case):
+    # certificate_bound bounds the smallest eigenvalue of Zs over the whole space
+    # (the exact one from a dense eigvalsh) at any point, with the spectral and the
+    # (larger) Frobenius cross norm; at a critical point the deflated block
+    # contributes ~0 and the bound is that smallest eigenvalue itself
+    sc = scenes.make_scene("tiny", 1)
+    Q = _Q(sc)
+    R, s, info = st.staircase(Q, grad_tol=1e-11)
+    rng = np.random.default_rng(3)
+    eps = {"optimum": 0.0, "near": 1e-4, "perturbed": 0.05}.get(case)
+    if case == "random":
+        R, s = _rand_point(rng, sc.N, 3)
+    elif eps:
+        R = mf.gram_schmidt(R + eps * rng.standard_normal(R.shape))
+        s = s * np.exp(eps * rng.standard_normal(s.shape))
+        s[0] = 1.0
+    U = mf.to_U(R, s)
+    cb = ce.certificate_bound(Q, U)
+    full = cb["lambda_min_scaled_full"]
+    assert cb["bound_scaled"] <= full + 1e-12 * max(1.0, abs(full))
+    assert cb["bound_scaled_fro"] <= cb["bound_scaled"] + 1e-15
+    Z = ce.dual_matrix(Q, ce.dual_lambda(Q, U, s))
+    lam_Z = float(np.linalg.eigvalsh(Z)[0])
+    assert cb["lambda_bound"] <= lam_Z + 1e-10 * info["qbar"]
+    if case == "optimum":
+        assert abs(cb["bound_scaled_fro"] - full) <= 1e-10
+        assert cb["cross_fro"] <= 1e-9 and abs(cb["defl_min"]) <= 1e-12
+
+
+def test_complement_alone_would_certify_a_non_critical_point():
+    # A perturbed optimum: Zs is positive on the complement of D^{1/2} rows(U)
+    # (the complement-only bound says "certified"), yet Z has a negative
+    # eigenvalue well below the tolerance; the full-spectrum bound rejects it.
+    sc = scenes.make_scene("tiny", 1)
+    Q = _Q(sc)
+    R, s, info = st.staircase(Q, grad_tol=1e-11)
+    rng = np.random.default_rng(3)
+    R = mf.gram_schmidt(R + 0.05 * rng.standard_normal(R.shape))
+    s = s * np.exp(0.05 * rng.standard_normal(s.shape))
+    s[0] = 1.0
+    c = ce.certify(Q, R, s, 1e-7)
+    tol = 1e-7 * c["qbar"]
+    assert c["lambda_bound"] >= -tol                      # complement alone: PSD
+    assert c["lambda_min_full"] < -1e3 * tol              # Z is not PSD
+    assert c["lambda_bound_full"] < -tol                  # the full bound says so
