@@ -101,8 +101,28 @@ xm_status xm_build_Q(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame,
                      const void* w, xm_dtype w_dtype, uint32_t copies, void* stream,
                      xm_problem** out);
 
-/* Release a handle and all device memory it owns.  NULL is allowed. */
+/* Release a handle and all device memory it owns.  NULL is allowed.  The
+ * memory goes back to the library's device pool (below), not to the runtime. */
 void xm_free(xm_problem* p);
+
+/*
+ * Device memory of the library.  Every buffer the library allocates (problem
+ * handles, solver and certificate workspaces) comes from a per-device pool:
+ * freed blocks are kept and handed out again to requests of about the same
+ * size (at most 1.25x), so repeated builds and solves of one problem shape take
+ * no memory from the runtime after the first.  A freed block is recycled only
+ * after the device has finished its queued work (the ordering hipFree gives).
+ * Cached blocks are capped at 64 GiB over all devices (environment variable
+ * XM_POOL_CACHE_GB overrides; the largest are released first); an allocation
+ * that fails releases the device's cached blocks and retries once.
+ *
+ * xm_memory_info  bytes in live blocks and in cached (free) blocks, over all
+ *                 devices (host outputs; either may be NULL, not both).
+ * xm_memory_trim  wait for the devices to go idle and release every cached
+ *                 block to the runtime; returns the bytes released.
+ */
+xm_status xm_memory_info(int64_t* live_bytes, int64_t* cached_bytes);
+int64_t xm_memory_trim(void);
 
 typedef struct {
   int32_t N, M;
@@ -274,17 +294,28 @@ xm_status xm_bm_solve(xm_problem* p, const xm_solve_opts* opts, const double* Y0
                       double* Y_out, xm_solve_info* info, void* stream);
 
 typedef struct {
-  double lambda_min;     /* minimum eigenvalue of the block-Jacobi scaled dual
-                            D^{-1/2} Z D^{-1/2} (D = blkdiag(Q_kk)) on the
-                            complement of D^{1/2} rows(Y); same sign as that of Z */
+  double lambda_min;     /* smallest Ritz value of the block-Jacobi scaled dual
+                            Zs = D^{-1/2} Z D^{-1/2} (D = blkdiag(Q_kk)) on the
+                            complement of D^{1/2} rows(Y) */
   double ritz_residual;  /* residual norm of the Ritz pair of lambda_min */
-  double lambda_bound;   /* lower bound on v^T Z v over unit v D-orthogonal to rows(Y):
-                            (lambda_min - ritz_residual) * (d_min or d_max of the Q_kk);
-                            exact given that Lanczos found the smallest eigenvalue */
-  double primal;         /* tr(Q Y^T Y) */
+  double lambda_bound;   /* lower bound on v^T Z v over ALL unit v:
+                            b * (d_min if b >= 0 else d_max), d_min/d_max the
+                            extreme eigenvalues of the Q_kk, with
+                            b = (a + c)/2 - sqrt(((a - c)/2)^2 + e^2),
+                            c = lambda_min - ritz_residual, a = defl_min,
+                            e = defl_cross; exact given that Lanczos found the
+                            smallest eigenvalue on the complement */
+  double primal;         /* tr(Q Y^T Y), the relaxation's value at Y (rho_SDP) */
   double dual;           /* tr(Lambda_0), the dual objective b^T y */
   double qbar;           /* tr(Q) / 3N */
   double grad_norm;      /* || Z Y^T ||_F, the stationarity residual */
+  double defl_min;       /* smallest eigenvalue of W^T Zs W, W an orthonormal basis
+                            of D^{1/2} rows(Y) (0 at a critical point) */
+  double defl_cross;     /* || (I - W W^T) Zs W ||_F (0 at a critical point) */
+  double rho_hat;        /* cost tr(Q Uhat^T Uhat) of the rounded point (xm_round);
+                            NaN when r < 3 */
+  double eta;            /* eq. suboptimality: (rho_hat - primal) /
+                            (1 + |rho_hat| + |primal|); NaN when r < 3 */
   int32_t certified;     /* lambda_bound >= -tol * qbar */
   int32_t iters;         /* Lanczos iterations */
 } xm_cert;
@@ -294,8 +325,11 @@ typedef struct {
  * Lambda_k = sym((Q Y^T)_k Y_k) / alpha_k (traceless for k >= 1),
  * Z = Q - blkdiag(Lambda).  PSD-ness of Z is decided by FP64 Lanczos with full
  * reorthogonalisation on the congruent D^{-1/2} Z D^{-1/2} (same inertia,
- * narrower spectrum), deflated against D^{1/2} rows(Y); certified iff the
- * lower bound lambda_bound >= -tol * qbar.
+ * narrower spectrum), deflated against D^{1/2} rows(Y), with the deflated block
+ * and its coupling to the complement folded into a bound on the whole spectrum
+ * (so a Y that is not a critical point is not certified by its complement
+ * alone); certified iff lambda_bound >= -tol * qbar.  Also rounds Y (r >= 3)
+ * for rho_hat and eta (eq. suboptimality).
  * Y      device [r][3N], 1 <= r <= 8;  tol: relative tolerance (<= 0: 1e-7)
  * v_min  device [3N] unit direction D^{-1/2} x of the Ritz vector x of lambda_min
  *        (v^T Z v < 0 when lambda_min < 0), or NULL.
@@ -352,6 +386,9 @@ typedef struct {
  * dtype g_dtype (XM_F64 or XM_F32).  cg_tol (<= 0: 1e-10) is relative to
  * |grad l|; cg_max <= 0 means 4N.  For callers that differentiate through the
  * solver (the torch autograd Function of the Python binding).
+ * Returns XM_ENOCONV (outputs written from the last CG iterate) when CG meets a
+ * direction of non-positive curvature (the point is not a tight certified
+ * optimum) or stops at cg_max above cg_tol; info->cg_residual tells which.
  */
 xm_status xm_adjoint(xm_problem* p, const double* R, const double* s, const double* gR,
                      const double* gs, double gcost, void* gu, void* gw, xm_dtype g_dtype,

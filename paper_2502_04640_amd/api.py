@@ -61,7 +61,8 @@ class _Cert(ctypes.Structure):
     _fields_ = [("lambda_min", ctypes.c_double), ("ritz_residual", ctypes.c_double),
                 ("lambda_bound", ctypes.c_double), ("primal", ctypes.c_double),
                 ("dual", ctypes.c_double), ("qbar", ctypes.c_double), ("grad_norm", ctypes.c_double),
-                ("certified", ctypes.c_int32), ("iters", ctypes.c_int32)]
+                ("defl_min", ctypes.c_double), ("defl_cross", ctypes.c_double), ("rho_hat", ctypes.c_double),
+                ("eta", ctypes.c_double), ("certified", ctypes.c_int32), ("iters", ctypes.c_int32)]
 
 
 class _AdjInfo(ctypes.Structure):
@@ -124,6 +125,10 @@ def load_library() -> ctypes.CDLL:
     lib.xm_spmm_timing.restype = ctypes.c_int
     lib.xm_spmm_stats.argtypes = [P, ctypes.POINTER(_SpmmStats), I32]
     lib.xm_spmm_stats.restype = ctypes.c_int
+    lib.xm_memory_info.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.xm_memory_info.restype = ctypes.c_int
+    lib.xm_memory_trim.argtypes = []
+    lib.xm_memory_trim.restype = ctypes.c_int64
     lib.xm_last_error.argtypes = []
     lib.xm_last_error.restype = ctypes.c_char_p
     _LIB = lib
@@ -317,24 +322,52 @@ class Problem:
         return gu, gw, {f: getattr(inf, f) for f, _ in _AdjInfo._fields_}
 
 
+def memory_info() -> dict:
+    """Bytes of the library's device pool in live and in cached (free) blocks."""
+    live, cached = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(load_library().xm_memory_info(ctypes.byref(live), ctypes.byref(cached)))
+    return {"live": live.value, "cached": cached.value}
+
+
+def memory_trim() -> int:
+    """Return the pool's cached blocks to the runtime; the bytes released."""
+    return int(load_library().xm_memory_trim())
+
+
+class NotTightError(RuntimeError):
+    """The solve did not reach a certified optimum at which the relaxation is
+    tight, so the implicit-function gradient of the rotations is not defined."""
+
+
 class XMSolve(torch.autograd.Function):
     """(R [N,3,3], s [N], f*) = certified SBA optimum of (u, w); differentiable in u and w.
 
     forward: xm_build_Q -> xm_bm_solve -> xm_round (f* is the cost of the
     rounded, anchored solution); backward: xm_adjoint (envelope theorem for f*,
-    implicit-function theorem for R and s).  Valid at tight certified optima.
+    implicit-function theorem for R and s).  The gradients are those of a tight
+    certified optimum, so forward raises NotTightError when the solve is not
+    certified, did not converge, or rounding loses more than `eta_tol`
+    (eq. suboptimality: the relaxation is not tight there), and backward raises
+    XMError when the adjoint's CG does not converge.
     """
 
     @staticmethod
-    def forward(ctx, u, w, frame, landmark, N, M, opts=None):
-        P = build_Q(N, M, frame, landmark, u, w, keep=("f32",) if (opts and opts.compute != "f64") else ())
-        Y, info = P.solve(opts or SolveOptions())
+    def forward(ctx, u, w, frame, landmark, N, M, opts=None, eta_tol=1e-6):
+        opts = opts or SolveOptions()
+        keep = {"f64": (), "f32": ("f32",), "bf16": ("f32", "bf16")}[opts.compute]
+        P = build_Q(N, M, frame, landmark, u, w, keep=keep)
+        Y, info = P.solve(opts)
         R, s, rho = P.round(Y)
+        eta = (rho - info["cost"]) / (1.0 + abs(rho) + abs(info["cost"]))
+        if info["status"] != XM_OK or not info["certified"] or eta > eta_tol:
+            P.close()
+            raise NotTightError(f"solve status={info['status']} certified={info['certified']} "
+                                f"rank={info['r']} eta={eta:.3e} (tol {eta_tol:.1e}): the gradient of the "
+                                "optimum is defined at tight certified optima only")
         ctx.problem = P
-        ctx.info = info
+        ctx.info = dict(info, eta=eta)
         ctx.u_dtype, ctx.w_dtype = u.dtype, w.dtype
         ctx.save_for_backward(R, s)
-        ctx.mark_non_differentiable(R.new_empty(0))
         return R, s, torch.tensor(rho, dtype=torch.float64, device=R.device)
 
     @staticmethod
@@ -342,7 +375,7 @@ class XMSolve(torch.autograd.Function):
         R, s = ctx.saved_tensors
         gc = 0.0 if gcost is None else float(gcost)
         gu, gw, _ = ctx.problem.adjoint(R, s, gR, gs, gc, dtype=torch.float64)
-        return gu.to(ctx.u_dtype), gw.to(ctx.w_dtype), None, None, None, None, None
+        return gu.to(ctx.u_dtype), gw.to(ctx.w_dtype), None, None, None, None, None, None
 
 
 def build_Q(N: int, M: int, frame: torch.Tensor, landmark: torch.Tensor, u: torch.Tensor,

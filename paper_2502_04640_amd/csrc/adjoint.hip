@@ -300,6 +300,13 @@ AdjointResult adjoint(xm_problem* p, const double* R, const double* s, const dou
         mf.hess(3, Rt.ptr, sv.ptr, G.ptr, Sc.ptr, ec.ptr, dR.ptr, ds.ptr, Gd.ptr, etaR.ptr, etas.ptr, HdR.ptr,
                 Hds.ptr, part.ptr, st, true);
         read_partials(part.ptr, nb, 4, sums, st);
+        // the Hessian of a certified, tight optimum is positive definite in the
+        // anchored chart; a direction of non-positive curvature means the point
+        // is not one, and CG cannot continue
+        if (!(sums[0] > 0.0)) {
+          res.negative_curvature = true;
+          break;
+        }
         const double alpha = r_r / sums[0];
         mf.tcg_update(3, sv.ptr, alpha, 0, dR.ptr, ds.ptr, HdR.ptr, Hds.ptr, etaR.ptr, etas.ptr, HetaR.ptr,
                       Hetas.ptr, resR.ptr, ress.ptr, part.ptr, st);
@@ -313,6 +320,7 @@ AdjointResult adjoint(xm_problem* p, const double* R, const double* s, const dou
       }
     }
     res.cg_iters = std::min(j, cg_max);
+    res.converged = !res.negative_curvature && (b2 == 0.0 || res.cg_residual <= cg_tol);
     // lam = -eta; the direction passed on is eta itself: Ueta = eta_s R + s eta_R = -Udot
     mf.ydot(3, Rt.ptr, sv.ptr, resR.ptr, ress.ptr, etaR.ptr, etas.ptr, 0.0, 2, Ydot.ptr, st);
     recover(p, Ydot.ptr, mirror.ptr, recl, st);

@@ -1,4 +1,5 @@
 // C ABI of libxm (declared and documented in include/xm.h).
+#include <cmath>
 #include <cstdio>
 #include <string>
 
@@ -52,6 +53,18 @@ xm_status xm_build_Q(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame, 
 }
 
 void xm_free(xm_problem* p) { delete p; }
+
+xm_status xm_memory_info(int64_t* live_bytes, int64_t* cached_bytes) {
+  if (!live_bytes && !cached_bytes) return fail(XM_EINVAL, "NULL argument");
+  size_t live = 0, cached = 0;
+  xm::pool_usage(&live, &cached);
+  if (live_bytes) *live_bytes = static_cast<int64_t>(live);
+  if (cached_bytes) *cached_bytes = static_cast<int64_t>(cached);
+  g_err.clear();
+  return XM_OK;
+}
+
+int64_t xm_memory_trim(void) { return static_cast<int64_t>(xm::pool_trim()); }
 
 xm_status xm_get_info(const xm_problem* p, xm_problem_info* info) {
   if (!p || !info) return fail(XM_EINVAL, "NULL argument");
@@ -168,8 +181,19 @@ xm_status xm_certify(xm_problem* p, const double* Y, int32_t r, double tol, int3
   cert->dual = c.dual;
   cert->qbar = p->qbar;
   cert->grad_norm = c.stat_res;
+  cert->defl_min = c.defl_min;
+  cert->defl_cross = c.defl_cross;
   cert->certified = c.certified ? 1 : 0;
   cert->iters = c.iters;
+  // eq. suboptimality: the rounded point's cost against the relaxation's value at Y
+  cert->rho_hat = cert->eta = std::nan("");
+  if (r >= 3) {
+    xm::DevBuf<double> R(9 * static_cast<size_t>(p->N)), sc(p->N);
+    double rho = 0.0;
+    xm::round_yt(p, Y, r, R.ptr, sc.ptr, &rho, s);
+    cert->rho_hat = rho;
+    cert->eta = (rho - c.primal) / (1.0 + std::fabs(rho) + std::fabs(c.primal));
+  }
   return XM_OK;
   XM_API_CATCH
 }
@@ -270,6 +294,14 @@ xm_status xm_adjoint(xm_problem* p, const double* R, const double* s, const doub
     info->cg_iters = r.cg_iters;
     info->cg_residual = r.cg_residual;
     info->cost = r.cost;
+  }
+  if (r.negative_curvature) {
+    g_err = "adjoint: the Hessian has a direction of non-positive curvature (not a tight certified optimum)";
+    return XM_ENOCONV;
+  }
+  if (!r.converged) {
+    g_err = "adjoint: CG stopped above its tolerance (cg_residual > cg_tol)";
+    return XM_ENOCONV;
   }
   return XM_OK;
   XM_API_CATCH

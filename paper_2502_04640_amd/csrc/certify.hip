@@ -10,11 +10,15 @@
 //   Zs = D^{-1/2} Z D^{-1/2},   D = blkdiag(Q_kk)   (3x3 SPD diagonal blocks of Q),
 // which by Sylvester's law of inertia has the same signature as Z but a much
 // narrower spectrum (block-Jacobi scaling), so Lanczos needs far fewer
-// products.  Its smallest eigenvalue ls with Ritz residual res bounds
-// v^T Z v >= (ls - res) * (d_min if ls - res >= 0, else d_max) for unit v
-// D-orthogonal to rows(Y), d_min/d_max the extreme eigenvalues of the Q_kk
+// products.  Its smallest eigenvalue ls with Ritz residual res bounds the
+// spectrum of Zs on the complement of D^{1/2} rows(Y) from below by ls - res
 // (given that the Ritz value belongs to the smallest eigenvalue, which the
-// stop rule below guards); certified iff that bound is >= -tol * qbar.
+// stop rule below guards).  The deflated block itself (its smallest eigenvalue
+// and its coupling to the complement, both zero at a critical point) extends
+// that to a bound b on the whole spectrum of Zs, so the point need not be
+// stationary for the test to be sound; then
+// v^T Z v >= b * (d_min if b >= 0, else d_max) for every unit v, d_min/d_max
+// the extreme eigenvalues of the Q_kk; certified iff that is >= -tol * qbar.
 //
 // Lanczos runs on the orthogonal complement of D^{1/2} rows(Y) (Zs D^{1/2} Y^T
 // = D^{-1/2} Z Y^T = 0 at a critical point): the first r basis vectors are an
@@ -263,6 +267,40 @@ std::vector<double> tridiag_min_vec(const std::vector<double>& d, const std::vec
   return y;
 }
 
+// smallest eigenvalue of a small symmetric matrix (cyclic Jacobi rotations)
+double small_sym_min_eig(std::vector<double> A, int n) {
+  if (n == 0) return 0.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < n; ++i) {
+      diag += A[i * n + i] * A[i * n + i];
+      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+    }
+    if (off <= 1e-30 * (diag + 1e-300)) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (apq == 0.0) continue;
+        const double th = 0.5 * (A[q * n + q] - A[p * n + p]) / apq;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - sn * akq;
+          A[k * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - sn * aqk;
+          A[q * n + k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  double m = A[0];
+  for (int i = 1; i < n; ++i) m = std::min(m, A[i * n + i]);
+  return m;
+}
+
 template <int R>
 void launch_lambda(int32_t N, const double* Yt, const double* G, double* Lam, double* part, hipStream_t s) {
   hipLaunchKernelGGL((lambda_kernel<R>), dim3(cdiv(N, kB)), dim3(kB), 0, s, N, Yt, G, Lam, part);
@@ -356,6 +394,52 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
     XM_HIP(hipStreamSynchronize(s));
     if (bn > 1e-10 * std::sqrt(static_cast<double>(N) * p->dmax)) ++nb;  // skip a dependent row
   }
+  // The deflated block.  W = V[0..nb) is an orthonormal basis of D^{1/2} rows(Y).
+  // With a = lambda_min(W^T Zs W), e = |(I - W W^T) Zs W| and b the smallest
+  // eigenvalue of Zs on the complement of W (the Lanczos run below), every unit
+  // vector v = x + y (x in span W, y orthogonal to it) has
+  //   v^T Zs v >= a |x|^2 + b |y|^2 - 2 e |x| |y| >= (a+b)/2 - sqrt(((a-b)/2)^2 + e^2),
+  // a lower bound on the whole spectrum of Zs.  At a critical point Z Y^T = 0, so
+  // a = e = 0 and the bound is min(0, b); away from one, e carries the
+  // stationarity residual into the bound (the complement alone would not
+  // decide PSD-ness).  Each column of Zs W costs one FP64 product in the
+  // residual role (the accurate one: Zs W cancels heavily near the optimum).
+  double defl_min = 0.0, defl_cross = 0.0;
+  if (nb > 0) {
+    std::vector<double> Mw(static_cast<size_t>(nb) * nb);
+    double fro2 = 0.0;
+    for (int a = 0; a < nb; ++a) {
+      const double* x = V.ptr + static_cast<int64_t>(a) * n;
+      hipLaunchKernelGGL(blockmul_kernel, dim3(gb), dim3(kB), 0, s, N, p->Dmhalf.ptr, x, yv.ptr);
+      XM_LAUNCH_CHECK("blockmul_kernel");
+      spmm_yt<double>(p, XM_F64, yv.ptr, 1, Qx.ptr, s, XM_ROLE_RESIDUAL);
+      hipLaunchKernelGGL(zapply_scaled_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, N, Lam.ptr, p->Dmhalf.ptr, yv.ptr,
+                         Qx.ptr, w.ptr);
+      XM_LAUNCH_CHECK("zapply_scaled_kernel");
+      multidot(nb, c1.ptr);
+      hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w.ptr, n, c1.ptr, c2.ptr, 0,
+                         static_cast<double*>(nullptr), beta.ptr, 0, Qx.ptr);
+      XM_LAUNCH_CHECK("normalize_kernel");
+      double bn = 0.0;
+      XM_HIP(hipMemcpyAsync(Mw.data() + static_cast<size_t>(a) * nb, c1.ptr, nb * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+      XM_HIP(hipMemcpyAsync(&bn, beta.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
+      XM_HIP(hipStreamSynchronize(s));
+      fro2 += bn * bn;
+    }
+    double m2 = 0.0;
+    std::vector<double> Ms(Mw.size());
+    for (int a = 0; a < nb; ++a)
+      for (int b = 0; b < nb; ++b) {
+        m2 += Mw[a * nb + b] * Mw[a * nb + b];
+        Ms[a * nb + b] = 0.5 * (Mw[a * nb + b] + Mw[b * nb + a]);
+      }
+    defl_min = small_sym_min_eig(Ms, nb);
+    defl_cross = std::sqrt(std::max(0.0, fro2 - m2));
+  }
+  out.defl_min = defl_min;
+  out.defl_cross = defl_cross;
+
   hipLaunchKernelGGL(random_kernel, dim3(gb), dim3(kB), 0, s, n, static_cast<uint64_t>(12345), w.ptr);
   orthogonalize(nb);
   hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w.ptr, n, c1.ptr, c2.ptr, 0,
@@ -410,7 +494,13 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
   out.lambda_min = theta;
   out.ritz_residual = res;
   const double lo = theta - res;
-  out.lambda_bound = lo * (lo >= 0.0 ? p->dmin : p->dmax);
+  double full = lo;
+  if (nb > 0) {
+    const double h = 0.5 * (defl_min - lo);
+    full = 0.5 * (defl_min + lo) - std::sqrt(h * h + defl_cross * defl_cross);
+  }
+  // v^T Z v = (D^{1/2} v)^T Zs (D^{1/2} v) and d_min |v|^2 <= |D^{1/2} v|^2 <= d_max |v|^2
+  out.lambda_bound = full * (full >= 0.0 ? p->dmin : p->dmax);
   out.certified = out.lambda_bound >= -tol * qbar;
   if (v_out) {
     const int m = static_cast<int>(y.size());

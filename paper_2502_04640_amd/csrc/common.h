@@ -31,7 +31,23 @@ inline void require(bool ok, xm_status code, const std::string& msg) {
 }
 
 // ---------------------------------------------------------------------------
-// Owning device buffer.
+// Device memory of the library (pool.cpp).  Freed blocks are kept per device
+// and handed out again to requests of about their size, so that repeated
+// builds and solves of one problem shape allocate nothing from the runtime
+// once the first has run.  pool_free waits for the device to go idle before
+// it recycles the block (the same ordering hipFree gives), so a block is never
+// handed out while a kernel may still use it.  pool_alloc throws XM_ENOMEM
+// (after releasing the cached blocks and retrying once).
+void* pool_alloc(size_t bytes);
+void pool_free(void* ptr);
+// Return every cached (free) block of every device to the runtime; the
+// number of bytes released.
+size_t pool_trim();
+// Bytes held in live blocks and in cached blocks, over all devices.
+void pool_usage(size_t* live, size_t* cached);
+
+// ---------------------------------------------------------------------------
+// Owning device buffer (memory from the pool above).
 template <typename T>
 struct DevBuf {
   T* ptr = nullptr;
@@ -49,13 +65,7 @@ struct DevBuf {
   void alloc(size_t count) {
     release();
     if (count == 0) return;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&ptr), count * sizeof(T));
-    if (e != hipSuccess) {
-      ptr = nullptr;
-      (void)hipGetLastError();
-      throw Error(XM_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) +
-                                 " bytes failed: " + hipGetErrorString(e));
-    }
+    ptr = static_cast<T*>(pool_alloc(count * sizeof(T)));
     n = count;
   }
   // grow-only reallocation (contents are not kept)
@@ -63,7 +73,7 @@ struct DevBuf {
     if (count > n) alloc(count);
   }
   void release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) pool_free(ptr);
     ptr = nullptr;
     n = 0;
   }

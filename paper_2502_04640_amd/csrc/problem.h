@@ -103,6 +103,7 @@ void transpose_rows(const Ts* in, int rows, int cols, Td* out, hipStream_t s);
 // certify.hip: certificate at Yt (FP64, [3N][r]).
 struct CertResult {
   double lambda_min = 0, ritz_residual = 0, lambda_bound = 0, primal = 0, dual = 0, stat_res = 0;
+  double defl_min = 0, defl_cross = 0;
   int iters = 0;
   bool certified = false;
 };
@@ -121,6 +122,7 @@ void round_yt(xm_problem* p, const double* Y, int r, double* R_out, double* s_ou
 struct AdjointResult {
   int cg_iters = 0;
   double cg_residual = 0.0, cost = 0.0;
+  bool converged = true, negative_curvature = false;
 };
 void recover_tp(xm_problem* p, const double* R, const double* s, double* t_out, double* p_out, hipStream_t st);
 AdjointResult adjoint(xm_problem* p, const double* R, const double* s, const double* gR, const double* gs,

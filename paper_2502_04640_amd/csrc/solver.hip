@@ -30,10 +30,23 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <type_traits>
 #include <vector>
 
 #include "manifold.h"
 #include "problem.h"
+
+// Refinement pass of reduced-precision solves (compile-time constants):
+// passes, trust-region steps per pass, products per truncated-CG solve.
+#ifndef XM_REFINE_PASSES
+#define XM_REFINE_PASSES 1
+#endif
+#ifndef XM_REFINE_STEPS
+#define XM_REFINE_STEPS 8
+#endif
+#ifndef XM_REFINE_INNER
+#define XM_REFINE_INNER 25
+#endif
 
 namespace xm {
 namespace {
@@ -376,7 +389,7 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   }
   // refinement target: the FP32 stage stops at grad_tol (its products' own
   // rounding allows little more), the FP64-referenced passes go 30x further
-  const int max_refine = 1;
+  const int max_refine = XM_REFINE_PASSES;
   const double refine_tol = grad_tol / 30.0;
 
   int r;
@@ -411,9 +424,9 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
       // a refinement pass is a short polish from a converged point: at most 8
       // steps, starting from a radius 64x below the default
       xm_solve_opts oref = o;
-      oref.max_outer = (o.max_outer > 0) ? std::min(o.max_outer, 8) : 8;
+      oref.max_outer = (o.max_outer > 0) ? std::min(o.max_outer, XM_REFINE_STEPS) : XM_REFINE_STEPS;
       if (oref.delta0 <= 0) oref.delta0 = std::sqrt(3.0 * N) / 8.0 / 64.0;
-      oref.max_inner = (o.max_inner > 0) ? std::min(o.max_inner, 25) : 25;  // truncated Newton steps
+      oref.max_inner = (o.max_inner > 0) ? std::min(o.max_inner, XM_REFINE_INNER) : XM_REFINE_INNER;
       const RtrOut r2 = rtr<T>(p, V, r, qg, qh, oref, refine_tol,
                                Rebase<T>{Yref.ptr, Gref.ptr, Rtmp.ptr, G64a.ptr, G64b.ptr}, st);
       ro.outer += r2.outer;
@@ -444,18 +457,26 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
       std::fprintf(stderr, "[xm] rank %d: f=%.12e |g|=%.3e lambda_s=%.6e (res %.2e, %d it) %s\n", r, ro.f,
                    ro.gnorm, cr.lambda_min, cr.ritz_residual, cr.iters, cr.certified ? "certified" : "not certified");
     if (cr.certified || r >= rmax) break;
-    // escape to rank r + 1 with step halving
-    const double f0 = ro.f;
+    // escape to rank r + 1 with step halving.  The costs before and after are
+    // both taken with FP64 products at the FP64 copies of the points: the
+    // decrease of Theorem "Descent Direction" is of order alpha^2 |lambda_min|,
+    // which a reduced-precision product's rounding near the optimum can exceed.
+    const int nblk = static_cast<int>(std::min<unsigned>(mf.blocks(), 8));
+    DevBuf<double> Y2_64(static_cast<size_t>(n3) * (r + 1)), G2_64(static_cast<size_t>(n3) * (r + 1));
+    spmm_yt<double>(p, XM_F64, Yt64.ptr, r, G2_64.ptr, st);
+    ++info->spmm_count;
+    const double f0 = vec_dot<double>(Yt64.ptr, G2_64.ptr, static_cast<int64_t>(n3) * r, V.part.ptr, nblk, st);
     bool moved = false;
     double alpha = 1.0;
-    DevBuf<T> Gtmp(static_cast<size_t>(n3) * (r + 1));
     for (int h = 0; h <= 40; ++h, alpha *= 0.5) {
       mf.escape(r, V.Rt.ptr, V.s.ptr, vmin.ptr, alpha, V.Rt2.ptr, V.Yt2.ptr, st);
-      spmm_yt<T>(p, qg, V.Yt2.ptr, r + 1, Gtmp.ptr, st);
+      const double* y2 = Y2_64.ptr;
+      if constexpr (std::is_same<T, double>::value) y2 = V.Yt2.ptr;
+      else transpose_rows<T, double>(V.Yt2.ptr, 1, static_cast<int>(n3 * (r + 1)), Y2_64.ptr, st);
+      spmm_yt<double>(p, XM_F64, y2, r + 1, G2_64.ptr, st);
       ++info->spmm_count;
       // f(Y+) = <Yt2, Q Yt2>
-      const double fn = vec_dot<T>(V.Yt2.ptr, Gtmp.ptr, static_cast<int64_t>(n3) * (r + 1), V.part.ptr,
-                                   static_cast<int>(std::min<unsigned>(mf.blocks(), 8)), st);
+      const double fn = vec_dot<double>(y2, G2_64.ptr, static_cast<int64_t>(n3) * (r + 1), V.part.ptr, nblk, st);
       if (fn < f0) {
         moved = true;
         break;

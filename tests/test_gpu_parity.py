@@ -245,10 +245,44 @@ def test_certificate_matches_dense_eigenvalue():
     assert c["certified"] == 1
     # the Lanczos runs on the block-Jacobi scaled dual D^{-1/2} Z D^{-1/2}
     assert abs(c["lambda_min"] - c_o["lambda_min_scaled"]) <= 1e-6 * max(1.0, abs(c_o["lambda_min_scaled"]))
-    assert abs(c["lambda_bound"] - c_o["lambda_bound"]) <= 1e-6 * c_o["dmax"]
+    # the deflated block at a critical point: ~0 eigenvalue, ~0 coupling
+    assert abs(c["defl_min"] - c_o["defl_min"]) <= 1e-9 and abs(c["defl_cross"] - c_o["defl_cross"]) <= 1e-9
+    assert abs(c["lambda_bound"] - c_o["lambda_bound_full"]) <= 1e-6 * c_o["dmax"]
+    assert c["lambda_bound"] <= c_o["lambda_min_full"] + 1e-9 * qbar
     # primal and dual are small differences of O(qbar |Y|^2) terms: FP64 noise ~1e-16 * 3N * qbar
     assert _gap(c["primal"], c_o["primal"]) <= 1e-9
     assert _gap(c["dual"], c_o["dual"]) <= 1e-9
+    assert abs(c["grad_norm"] - c_o["stat_res"]) <= 1e-9 * qbar
+    # eq. suboptimality: the oracle's rounding of the same Y, its cost, and eta
+    Rh, sh = ord_.round_solution(U)
+    Uh = ord_.rounded_U(Rh, sh)
+    rho_o = float(np.sum(Uh * (Uh @ Qo)))
+    assert _gap(c["rho_hat"], rho_o) <= 1e-10
+    assert abs(c["eta"] - oce.suboptimality(rho_o, c_o["primal"])) <= 1e-10
+
+
+def test_certificate_rejects_a_non_critical_point():
+    # A perturbed optimum whose complement of D^{1/2} rows(Y) is positive (the
+    # complement alone would certify it) while Z has a negative eigenvalue: the
+    # full-spectrum bound must reject it and stay below the oracle's lambda_min(Z)
+    _say("case: certificate at a perturbed (non-critical) point")
+    sc = scenes.make_scene("tiny", 1)
+    Qo = _oracle_Q(sc)
+    R, s, _ = ost.staircase(Qo, grad_tol=1e-11)
+    rng = np.random.default_rng(3)
+    R = omf.gram_schmidt(R + 0.05 * rng.standard_normal(R.shape))
+    s = s * np.exp(0.05 * rng.standard_normal(s.shape))
+    s[0] = 1.0
+    c_o = oce.certify(Qo, R, s, 1e-7)
+    assert c_o["lambda_bound"] >= -1e-7 * c_o["qbar"] and c_o["lambda_min_full"] < -1e-4 * c_o["qbar"]
+    P = _build(sc)
+    c = P.certify(torch.from_numpy(omf.to_U(R, s)).cuda(), tol=1e-7, max_iter=300)
+    _say(f"  gpu bound {c['lambda_bound']:.4e} oracle lambda_min(Z) {c_o['lambda_min_full']:.4e} "
+         f"defl_min {c['defl_min']:.3e} cross {c['defl_cross']:.3e}")
+    assert c["certified"] == 0
+    assert c["lambda_bound"] <= c_o["lambda_min_full"] + 1e-9 * c_o["qbar"]
+    assert abs(c["defl_min"] - c_o["defl_min"]) <= 1e-8 * max(1.0, abs(c_o["defl_min"]))
+    assert abs(c["defl_cross"] - c_o["defl_cross"]) <= 1e-8 * max(1.0, c_o["defl_cross"])
 
 
 def test_round_matches_oracle_on_rank5_input():

@@ -78,3 +78,40 @@ def test_stats_struct_matches_header():
     slots = int(re.search(r"#define XM_STATS_SLOTS (\d+)", text).group(1))
     from paper_2502_04640_amd.api import _SpmmStats
     assert len(_SpmmStats().launches) == slots == len(_SpmmStats().total_ms) == len(_SpmmStats().bytes_per_launch)
+
+
+def _struct_fields(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", text).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        typ, names = decl.split(None, 1)
+        fields += [(n.strip(), typ) for n in names.split(",")]
+    return fields
+
+
+@pytest.mark.parametrize("cname,pyname", [("xm_cert", "_Cert"), ("xm_solve_info", "_SolveInfo"),
+                                          ("xm_solve_opts", "_SolveOpts"), ("xm_adjoint_info", "_AdjInfo")])
+def test_ctypes_structs_match_header(cname, pyname):
+    # field names, order and C types of the ctypes mirrors follow the header
+    from paper_2502_04640_amd import api
+    cmap = {"double": ctypes.c_double, "int32_t": ctypes.c_int32, "xm_dtype": ctypes.c_int32}
+    fields = _struct_fields(cname)
+    mirror = getattr(api, pyname)._fields_
+    assert [n for n, _ in fields] == [n for n, _ in mirror]
+    for (n, t), (_, pt) in zip(fields, mirror):
+        assert ctypes.sizeof(cmap[t]) == ctypes.sizeof(pt), (n, t, pt)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libxm.so not built")
+def test_memory_pool_calls_without_gpu():
+    # the pool's accounting needs no device: nothing is live or cached before any call
+    lib = ctypes.CDLL(LIB)
+    lib.xm_memory_info.restype = ctypes.c_int
+    live, cached = ctypes.c_int64(-1), ctypes.c_int64(-1)
+    assert lib.xm_memory_info(ctypes.byref(live), ctypes.byref(cached)) == 0
+    assert live.value == 0 and cached.value == 0
+    assert lib.xm_memory_info(None, None) == -1
