@@ -125,11 +125,15 @@ def _orth_basis(A, rel=1e-10):
     return Uo[:, sv > rel * sv[0]]
 
 
-def certificate_bound(Q, U):
+def certificate_bound(Q, U, rel=1e-3):
     """Lower bound on the whole spectrum of Zs = D^{-1/2} Z D^{-1/2} from the
     deflated block, valid at any U (not only at critical points).
 
-    W: orthonormal basis of D^{1/2} rows(U).  For unit v = x + y with x in
+    W: orthonormal basis of the part of D^{1/2} rows(U) whose singular values
+    are at least `rel` times the largest (rows that are numerically
+    combinations of the others, as a rank-5 factor of a rank-3 optimum
+    carries, would add directions with a large coupling term; left out, they
+    are part of the complement).  The bound holds for any W.  For unit v = x + y with x in
     span W and y orthogonal to it, v^T Zs v >= a|x|^2 + b|y|^2 - 2e|x||y|,
     with a = lambda_min(W^T Zs W), b = lambda_min of Zs on the complement and
     e = |(I - W W^T) Zs W|; minimising over |x|^2 + |y|^2 = 1 gives
@@ -143,7 +147,7 @@ def certificate_bound(Q, U):
     Dmh = _blkdiag(Dm)
     Zs = Dmh @ Z @ Dmh
     Zs = 0.5 * (Zs + Zs.T)
-    W = _orth_basis(_blkdiag(Dh) @ U.T)
+    W = _orth_basis(_blkdiag(Dh) @ U.T, rel)
     ZW = Zs @ W
     Mw = W.T @ ZW
     a = float(np.linalg.eigvalsh(0.5 * (Mw + Mw.T))[0])

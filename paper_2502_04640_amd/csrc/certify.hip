@@ -41,6 +41,9 @@ namespace xm {
 namespace {
 
 constexpr int kB = 256;
+// rows of D^{1/2} Y kept in the deflation basis: residual above this fraction
+// of the largest row norm
+constexpr double kDeflRel = 1e-3;
 
 template <int R>
 __global__ __launch_bounds__(kB) void lambda_kernel(int32_t N, const double* __restrict__ Yt,
@@ -381,18 +384,37 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
     hipLaunchKernelGGL(multiaxpy_kernel, dim3(gb), dim3(kB), 0, s, V.ptr, nv, n, c2.ptr, -1.0, w.ptr);
     XM_LAUNCH_CHECK("orthogonalize");
   };
-  int nb = 0;
-  for (int a = 0; a < r; ++a) {
+  // Deflation basis: the rows of D^{1/2} Y by Gram-Schmidt, keeping a row only
+  // if what is left of it exceeds kDeflRel times the largest row norm.  Rows of
+  // Y that are (numerically) combinations of the others -- a rank-5 factor of a
+  // rank-3 optimum carries two such rows at the level of the solver's gradient --
+  // would add directions that are neither null vectors of Z nor small in the
+  // coupling term below; they stay in the complement, where Lanczos sees them.
+  auto scaled_row = [&](int a) {
     hipLaunchKernelGGL(column_kernel, dim3(gb), dim3(kB), 0, s, Yt, r, a, n, yv.ptr);
     hipLaunchKernelGGL(blockmul_kernel, dim3(gb), dim3(kB), 0, s, N, p->Dhalf.ptr, yv.ptr, w.ptr);
-    orthogonalize(nb);
+    XM_LAUNCH_CHECK("blockmul_kernel");
+  };
+  auto norm_of_w = [&](double* out_vec) {
     hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w.ptr, n, c1.ptr, c2.ptr, 0,
-                       static_cast<double*>(nullptr), beta.ptr, 0, V.ptr + static_cast<int64_t>(nb) * n);
+                       static_cast<double*>(nullptr), beta.ptr, 0, out_vec);
     XM_LAUNCH_CHECK("normalize_kernel");
     double bn = 0.0;
     XM_HIP(hipMemcpyAsync(&bn, beta.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
     XM_HIP(hipStreamSynchronize(s));
-    if (bn > 1e-10 * std::sqrt(static_cast<double>(N) * p->dmax)) ++nb;  // skip a dependent row
+    return bn;
+  };
+  double rmax = 0.0;
+  for (int a = 0; a < r; ++a) {
+    scaled_row(a);
+    rmax = std::max(rmax, norm_of_w(Qx.ptr));
+  }
+  const double keep_min = std::max(kDeflRel * rmax, 1e-10 * std::sqrt(static_cast<double>(N) * p->dmax));
+  int nb = 0;
+  for (int a = 0; a < r; ++a) {
+    scaled_row(a);
+    orthogonalize(nb);
+    if (norm_of_w(V.ptr + static_cast<int64_t>(nb) * n) > keep_min) ++nb;
   }
   // The deflated block.  W = V[0..nb) is an orthonormal basis of D^{1/2} rows(Y).
   // With a = lambda_min(W^T Zs W), e = |(I - W W^T) Zs W| and b the smallest

@@ -19,7 +19,8 @@
 // within 30 grad_tol qbar |Y|.  A reduced-precision solve then checks the
 // gradient with FP64 products and, if it is above grad_tol / 30, runs one
 // short trust-region pass (at most 8 steps toward that tolerance; truncated-CG
-// steps of at most 25 products) whose gradient products
+// steps of at most 100 products, enough to resolve the flat scale modes of
+// weakly linked frames) whose gradient products
 // are taken relative to the current point, with the FP64 product at that point
 // as reference (see Rebase).  The
 // cost decrease is evaluated as <Y+ - Y, Q (Y+ + Y)> from the two products
@@ -45,7 +46,7 @@
 #define XM_REFINE_STEPS 8
 #endif
 #ifndef XM_REFINE_INNER
-#define XM_REFINE_INNER 25
+#define XM_REFINE_INNER 100
 #endif
 
 namespace xm {

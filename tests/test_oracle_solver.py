@@ -270,7 +270,7 @@ def test_scaled_certificate_inertia_and_bound(case):
         assert v @ Z @ v >= c["lambda_bound"] - 1e-9 * c["qbar"]
 
 
-@pytest.mark.parametrize("case", ["optimum", "near", "perturbed", "random"])
+@pytest.mark.parametrize("case", ["optimum", "near", "perturbed", "random", "rank5"])
 def test_full_spectrum_bound_holds_at_any_point(case):
     # certificate_bound bounds the smallest eigenvalue of Zs over the whole space
     # (the exact one from a dense eigvalsh) at any point, with the spectral and the
@@ -288,6 +288,12 @@ def test_full_spectrum_bound_holds_at_any_point(case):
         s = s * np.exp(eps * rng.standard_normal(s.shape))
         s[0] = 1.0
     U = mf.to_U(R, s)
+    if case == "rank5":
+        # a rank-5 factor of the rank-3 optimum whose two extra rows carry only
+        # gradient-level residue (mixed in by a random orthogonal 5x5)
+        O, _ = np.linalg.qr(rng.standard_normal((5, 5)))
+        U = O @ np.vstack([U, 1e-8 * rng.standard_normal((2, U.shape[1]))])
+        s = mf.from_U(U)[1]
     cb = ce.certificate_bound(Q, U)
     full = cb["lambda_min_scaled_full"]
     assert cb["bound_scaled"] <= full + 1e-12 * max(1.0, abs(full))
@@ -295,9 +301,13 @@ def test_full_spectrum_bound_holds_at_any_point(case):
     Z = ce.dual_matrix(Q, ce.dual_lambda(Q, U, s))
     lam_Z = float(np.linalg.eigvalsh(Z)[0])
     assert cb["lambda_bound"] <= lam_Z + 1e-10 * info["qbar"]
-    if case == "optimum":
+    if case in ("optimum", "rank5"):
         assert abs(cb["bound_scaled_fro"] - full) <= 1e-10
-        assert cb["cross_fro"] <= 1e-9 and abs(cb["defl_min"]) <= 1e-12
+        assert cb["cross_fro"] <= 1e-7 and abs(cb["defl_min"]) <= 1e-12
+    if case == "rank5":
+        # keeping the residue rows in the basis would wreck the bound
+        bad = ce.certificate_bound(Q, U, rel=1e-14)
+        assert bad["bound_scaled_fro"] < -1e-3 and bad["bound_scaled_fro"] <= bad["lambda_min_scaled_full"]
 
 
 def test_complement_alone_would_certify_a_non_critical_point():
