@@ -40,10 +40,12 @@ import numpy as np
 from . import manifold as mf
 
 
-def dual_lambda(Q, U, s):
-    """Lambda [N, 3, 3]: Lambda_k = sym((Q U^T)_k U_k) / s_k^2, traceless for k >= 1."""
+def dual_lambda(Q, U, s, QU=None):
+    """Lambda [N, 3, 3]: Lambda_k = sym((Q U^T)_k U_k) / s_k^2, traceless for k >= 1.
+    QU (3N x r) may be given instead of Q (matrix-free callers)."""
     N = U.shape[1] // 3
-    QU = (Q @ U.T)                                  # 3N x r
+    if QU is None:
+        QU = (Q @ U.T)                              # 3N x r
     L = np.empty((N, 3, 3))
     for k in range(N):
         Uk = U[:, 3 * k:3 * k + 3]                  # r x 3
@@ -192,3 +194,119 @@ def certify(Q, R, s, tau):
 def suboptimality(rho_hat, rho_sdp):
     """eta = (rho_hat - rho_sdp) / (1 + |rho_hat| + |rho_sdp|)   (eq. suboptimality)."""
     return (rho_hat - rho_sdp) / (1.0 + abs(rho_hat) + abs(rho_sdp))
+
+
+# ---------------------------------------------------------------------------
+# Matrix-free certificate for scenes whose dense Q does not fit: Q enters only
+# through products (data_matrix.QOperator) and its diagonal blocks.
+
+def _blk_apply(B, x):
+    """blkdiag(B) x for B [N, 3, 3] and x (3N,) or (3N, k)."""
+    N = B.shape[0]
+    if x.ndim == 1:
+        return np.einsum("nab,nb->na", B, x.reshape(N, 3)).reshape(-1)
+    k = x.shape[1]
+    return np.einsum("nab,nbk->nak", B, x.reshape(N, 3, k)).reshape(3 * N, k)
+
+
+def _sqrt_blocks(D):
+    """D_k^{1/2}, D_k^{-1/2} per 3x3 block and the extreme eigenvalues (eigh)."""
+    lam, V = np.linalg.eigh(0.5 * (D + np.swapaxes(D, 1, 2)))
+    lam = np.maximum(lam, 1e-12 * lam[:, -1:])
+    Dh = np.einsum("nab,nb,ncb->nac", V, np.sqrt(lam), V)
+    Dm = np.einsum("nab,nb,ncb->nac", V, 1.0 / np.sqrt(lam), V)
+    return Dh, Dm, float(lam[:, 0].min()), float(lam[:, -1].max())
+
+
+def certify_op(op, U, tau, rel=1e-3, tol=1e-10, plain=False, log=None):
+    """Certificate at U with Q given as an operator (op.matmat, op.diag_blocks).
+
+    The quantities of certify / certificate_bound, with every eigenvalue on
+    the complement taken by scipy.sparse.linalg.eigsh (ARPACK Lanczos,
+    smallest algebraic) on a LinearOperator:
+      Lambda, Z = Q - blkdiag(Lambda), ||Z U^T|| (stationarity), primal and dual;
+      the block-Jacobi scaled Zs = D^{-1/2} Z D^{-1/2}, D = blkdiag(Q_kk);
+      W an orthonormal basis of D^{1/2} rows(U) (rows above `rel` of the
+      largest singular value), a = lambda_min(W^T Zs W), the coupling
+      e = ||(I - W W^T) Zs W||_F, b = lambda_min of Zs on the complement of W;
+      the whole-spectrum bound (a + b)/2 - sqrt(((a - b)/2)^2 + e^2) and the
+      bound on v^T Z v for unit v it implies (d_min / d_max scaling).
+    On the complement the operator is P Zs P + sigma W W^T (P = I - W W^T) with
+    sigma above the spectrum of Zs, so the deflated directions are not the
+    smallest.  plain=True also takes lambda_min of Z itself on the orthogonal
+    complement of rows(U) (the quantity of Theorem "Dual Optimality
+    Certificate"; slower: the unscaled spectrum is wider)."""
+    from scipy.sparse.linalg import LinearOperator, eigsh
+
+    N = U.shape[1] // 3
+    n = 3 * N
+    s = mf.from_U(U)[1]
+    QU = op.matmat(U.T)
+    Lam = dual_lambda(None, U, s, QU=QU)
+    primal = float(np.sum(U.T * QU))
+    dual = float(np.trace(Lam[0]))
+    ZU = QU - _blk_apply(Lam, U.T)
+    D = op.diag_blocks()
+    qbar = float(np.trace(D, axis1=1, axis2=2).sum()) / n
+    Dh, Dm, dmin, dmax = _sqrt_blocks(D)
+
+    def zs(x):
+        y = _blk_apply(Dm, x)
+        return _blk_apply(Dm, op.matmat(y) - _blk_apply(Lam, y))
+
+    W = _orth_basis(_blk_apply(Dh, U.T), rel)
+    ZW = zs(W)
+    Mw = W.T @ ZW
+    a = float(np.linalg.eigvalsh(0.5 * (Mw + Mw.T))[0])
+    e = float(np.linalg.norm(ZW - W @ Mw))
+    count = [0]
+
+    def top(fn):
+        A = LinearOperator((n, n), matvec=lambda x: (count.__setitem__(0, count[0] + 1), fn(x))[1],
+                           dtype=np.float64)
+        return float(eigsh(A, k=1, which="LA", tol=1e-3, return_eigenvectors=False)[0])
+
+    sigma = 1.05 * top(zs) + 1.0
+
+    def zc(x):
+        x = x.reshape(-1)
+        px = x - W @ (W.T @ x)
+        y = zs(px)
+        return (y - W @ (W.T @ y)) + sigma * (W @ (W.T @ x))
+
+    A = LinearOperator((n, n), matvec=lambda x: (count.__setitem__(0, count[0] + 1), zc(x))[1],
+                       dtype=np.float64)
+    v0 = np.ones(n) - W @ (W.T @ np.ones(n))
+    vals, vecs = eigsh(A, k=1, which="SA", tol=tol, v0=v0, ncv=40)
+    b = float(vals[0])
+    x = vecs[:, 0]
+    res = float(np.linalg.norm(zc(x) - b * x))
+    full = 0.5 * (a + b) - np.sqrt(0.25 * (a - b) ** 2 + e * e)
+    out = {"primal": primal, "dual": dual, "qbar": qbar, "Lambda": Lam,
+           "stat_res": float(np.linalg.norm(ZU)), "defl_min": a, "defl_cross": e,
+           "lambda_min_scaled": b, "ritz_residual": res, "bound_scaled": float(full),
+           "lambda_bound_full": float(full * (dmin if full >= 0 else dmax)),
+           "dmin": dmin, "dmax": dmax, "deflated_rank": int(W.shape[1]), "matvecs": count[0]}
+    out["certified"] = bool(out["lambda_bound_full"] >= -tau * qbar)
+    if plain:
+        Wp = _orth_basis(U.T, 1e-10)
+
+        def zp(x):
+            x = x.reshape(-1)
+            px = x - Wp @ (Wp.T @ x)
+            y = op.matmat(px) - _blk_apply(Lam, px)
+            return y - Wp @ (Wp.T @ y)
+
+        sig_p = 1.05 * top(zp) + 1.0
+
+        def zpc(x):
+            x = x.reshape(-1)
+            return zp(x) + sig_p * (Wp @ (Wp.T @ x))
+
+        Ap = LinearOperator((n, n), matvec=lambda x: (count.__setitem__(0, count[0] + 1), zpc(x))[1],
+                            dtype=np.float64)
+        v0 = np.ones(n) - Wp @ (Wp.T @ np.ones(n))
+        out["lambda_min_plain"] = float(eigsh(Ap, k=1, which="SA", tol=tol, v0=v0, ncv=40,
+                                              return_eigenvectors=False)[0])
+        out["matvecs"] = count[0]
+    return out

@@ -23,6 +23,13 @@ q_block_elimination   Q by eliminating p (Q3 diagonal) and then t (frame 0
 recover_tp            [t; p] = (A kron I3) vec(U)   (eq. tpstar), any r.
 sba_cost              the SBA objective of eq. sba evaluated directly.
 brute_force_cost      min over t, p of the SBA cost for fixed U by least squares.
+q_rows                selected rows of Q (sparse elimination, any size).
+sparse_parts          A_rr, A_rt, A_tt kept sparse (landmarks eliminated).
+QOperator             Q V without forming Q (sparse parts + one Cholesky of
+                      the grounded Laplacian); its diagonal blocks; tr(Q U^T U).
+recover_tp_sparse     eq. tpstar with the sparse parts.
+sba_cost_at           min over t, p of the SBA cost at fixed U, evaluated from
+                      the per-observation residuals (any size).
 """
 from __future__ import annotations
 
@@ -178,3 +185,101 @@ def brute_force_cost(N, M, frame, landmark, u, w, Y):
         res = A @ sol - b
         total += float(res @ res)
     return total
+
+
+# ---------------------------------------------------------------------------
+# Matrix-free forms for scenes whose dense Q does not fit (tens of thousands of
+# rows): the same block elimination, with A_rr, A_rt, A_tt kept sparse and the
+# grounded Laplacian factored once.
+
+def sparse_parts(N, M, frame, landmark, u, w):
+    """A_rr (3N x 3N), A_rt (3N x N), A_tt (N x N) as scipy CSR matrices:
+    the landmark elimination of block_parts, without densifying."""
+    Q1, Q2, Q3, V1, V2, V3 = paper_matrices(N, M, frame, landmark, u, w)
+    q3 = Q3.diagonal()
+    inv = sp.diags(np.where(q3 > 0, 1.0 / np.where(q3 > 0, q3, 1.0), 0.0))
+    A_rr = (Q1 - V2 @ inv @ V2.T).tocsr()
+    A_rt = (V1 - V2 @ inv @ V3.T).tocsr()
+    A_tt = (Q2 - V3 @ inv @ V3.T).tocsr()
+    return A_rr, A_rt, A_tt
+
+
+class QOperator:
+    """Q V = A_rr V - B (G^{-1} (B^T V)),  B = A_rt[:, 1:],  G = A_tt[1:, 1:].
+
+    The formula of q_block_elimination applied to a block of vectors instead
+    of formed: one dense Cholesky of the grounded Laplacian (N - 1 squared),
+    sparse products with A_rr and B.  Exact up to rounding order."""
+
+    def __init__(self, N, M, frame, landmark, u, w):
+        self.N, self.M = N, M
+        self.A_rr, self.A_rt, self.A_tt = sparse_parts(N, M, frame, landmark, u, w)
+        self.B = self.A_rt[:, 1:].tocsr()
+        self.Bt = self.B.T.tocsr()
+        self.cf = sla.cho_factor(self.A_tt[1:, 1:].toarray(), lower=True, overwrite_a=True)
+        self.n = 3 * N
+        self._diag = None
+
+    def matmat(self, V):
+        """Q V for V of shape (3N,) or (3N, k)."""
+        return self.A_rr @ V - self.B @ sla.cho_solve(self.cf, self.Bt @ V)
+
+    def trace(self):
+        """tr(Q) = sum of the diagonal 3x3 blocks."""
+        return float(sum(np.trace(b) for b in self.diag_blocks()))
+
+    def diag_blocks(self):
+        """Q_kk [N, 3, 3]: A_rr's diagonal block minus B_k G^{-1} B_k^T, B_k the
+        three rows of frame k (sparse), with G^{-1} from the Cholesky factor."""
+        if self._diag is None:
+            import scipy.linalg.lapack as lap
+            L = np.tril(self.cf[0])
+            Ginv, info = lap.dpotri(L, lower=1)
+            assert info == 0
+            Ginv = np.tril(Ginv) + np.tril(Ginv, -1).T
+            D = np.empty((self.N, 3, 3))
+            ip, ix, dv = self.B.indptr, self.B.indices, self.B.data
+            C = self.A_rr.tocoo()
+            on = (C.row // 3) == (C.col // 3)
+            Arr = np.zeros((self.N, 3, 3))
+            np.add.at(Arr, (C.row[on] // 3, C.row[on] % 3, C.col[on] % 3), C.data[on])
+            for k in range(self.N):
+                lo, hi = ip[3 * k], ip[3 * k + 3]
+                cols, pos = np.unique(ix[lo:hi], return_inverse=True)
+                Bd = np.zeros((3, cols.size))
+                rows = np.repeat(np.arange(3), np.diff(ip[3 * k:3 * k + 4]))
+                np.add.at(Bd, (rows, pos), dv[lo:hi])
+                D[k] = Arr[k] - Bd @ Ginv[np.ix_(cols, cols)] @ Bd.T
+                D[k] = 0.5 * (D[k] + D[k].T)
+            self._diag = D
+        return self._diag
+
+    def cost(self, U):
+        """tr(Q U^T U) = sum over rows y of U of y Q y^T."""
+        return float(np.sum(U.T * self.matmat(U.T)))
+
+
+def recover_tp_sparse(op, frame, landmark, u, w, Y):
+    """eq. tpstar with the sparse parts (any size): t from the grounded
+    Laplacian, t_0 = 0, then each landmark the weighted mean of Y_i u + t_i.
+    Returns t (N x r), p (M x r)."""
+    r = Y.shape[0]
+    N, M = op.N, op.M
+    rhs = -(op.A_rt.T @ Y.T)
+    t = np.zeros((N, r))
+    t[1:] = sla.cho_solve(op.cf, rhs[1:])
+    Yb = Y.reshape(r, N, 3).transpose(1, 0, 2)
+    x = np.einsum("nab,nb->na", Yb[frame], u) + t[frame]         # Y_i u + t_i per observation
+    W = np.bincount(landmark, weights=w, minlength=M)
+    p = np.stack([np.bincount(landmark, weights=w * x[:, a], minlength=M) for a in range(r)], axis=1)
+    p = p / np.where(W > 0, W, 1.0)[:, None]
+    return t, p
+
+
+def sba_cost_at(op, frame, landmark, u, w, Y):
+    """min over t, p (t_0 = 0) of the SBA cost at fixed U = Y (eq. sba),
+    evaluated from the residuals of every observation at the minimiser of
+    eq. tpstar.  Equals tr(Q Y^T Y) (Prop. "Scaled-Rotation-Only Formulation");
+    the two are computed by different routes."""
+    t, p = recover_tp_sparse(op, frame, landmark, u, w, Y)
+    return sba_cost(frame, landmark, u, w, Y, t, p)

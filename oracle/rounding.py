@@ -13,13 +13,15 @@ from __future__ import annotations
 import numpy as np
 
 
-def top3_factor(U):
+def top3_factor(U, method="auto"):
     """Ubar (3 x 3N) with Ubar^T Ubar the best rank-3 approximation of X = U^T U.
 
-    Dense eigendecomposition of X for 3N <= 6000; above that the same
-    eigenpairs come from the r x r Gram U U^T (identical nonzero spectrum)."""
+    method "dense": eigendecomposition of X itself (3N x 3N); "gram": the same
+    eigenpairs from the r x r Gram U U^T (identical nonzero spectrum: if
+    U U^T v = mu v then X (U^T v) = mu U^T v, and |U^T v|^2 = mu for unit v);
+    "auto": dense for 3N <= 6000, gram above."""
     n = U.shape[1]
-    if n <= 6000:
+    if method == "dense" or (method == "auto" and n <= 6000):
         mu, E = np.linalg.eigh(U.T @ U)
         idx = np.argsort(mu)[::-1][:3]
         return np.sqrt(np.maximum(mu[idx], 0.0))[:, None] * E[:, idx].T
@@ -38,10 +40,10 @@ def project_scaled_rotation(M):
     return R, s
 
 
-def round_solution(U):
+def round_solution(U, method="auto"):
     """Rounded, anchored rotations R_hat [N,3,3] and scales s_hat [N]."""
     N = U.shape[1] // 3
-    Ub = top3_factor(U)
+    Ub = top3_factor(U, method)
     dets = np.array([np.linalg.det(Ub[:, 3 * k:3 * k + 3]) for k in range(N)])
     if np.sum(dets < 0) > N / 2:
         Ub[2, :] = -Ub[2, :]
