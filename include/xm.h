@@ -232,17 +232,21 @@ typedef struct {
                           by a seeded uniform [-lift, lift] and re-orthonormalised
                           per block; 0 gives the paper's U^0 exactly */
   xm_dtype compute;    /* XM_F64: FP64 everywhere; XM_F32: FP32 products and
-                          manifold arithmetic; XM_BF16: BF16-stored Q for the
-                          Hessian products, FP32 Q for gradient and cost */
+                          manifold arithmetic, then the FP64 stage (grad_tol);
+                          XM_BF16: as XM_F32 with the BF16-stored Q for the
+                          first stage's Hessian products */
   double grad_tol;     /* stop when ||grad|| <= grad_tol * qbar * ||Y||_F
-                          (<= 0: 1e-9 for XM_F64, 3e-7 otherwise); also stop,
-                          counted as converged at the arithmetic's floor, after
-                          6 consecutive rejected trust-region steps while
-                          ||grad|| <= 30 grad_tol * qbar * ||Y||_F.  XM_F32 /
-                          XM_BF16 then check the gradient with FP64 products
-                          and refine toward grad_tol / 30 (one pass of at most
-                          8 steps; gradient products taken relative to the
-                          current point with its FP64 product as reference) */
+                          (<= 0: 1e-9 for XM_F64, 3e-7 otherwise); a reduced-
+                          precision stage also stops at the arithmetic's floor
+                          (6 consecutive rejected trust-region steps while
+                          ||grad|| <= 30 grad_tol * qbar * ||Y||_F).  XM_F32 /
+                          XM_BF16 solves then continue in an FP64 stage (FP64
+                          iterate, manifold arithmetic and gradient products;
+                          truncated-CG products with the FP32 Q)
+                          down to grad_tol / 300, the FP64 default: the dual
+                          certificate needs a point that close to stationary,
+                          which a reduced-precision iterate's own rounding does
+                          not allow */
   double cert_tol;     /* certified iff the lower bound on lambda_min(Z) >= -cert_tol * qbar
                           (<= 0: 1e-7 for XM_F64, 1e-5 otherwise) */
   int32_t max_outer;   /* trust-region iterations per rank (<= 0: 1000) */

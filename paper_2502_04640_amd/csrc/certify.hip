@@ -270,9 +270,11 @@ std::vector<double> tridiag_min_vec(const std::vector<double>& d, const std::vec
   return y;
 }
 
-// smallest eigenvalue of a small symmetric matrix (cyclic Jacobi rotations)
-double small_sym_min_eig(std::vector<double> A, int n) {
-  if (n == 0) return 0.0;
+// eigenvalues (returned) and eigenvectors (columns of V, row-major n x n) of a
+// small symmetric matrix by cyclic Jacobi rotations
+std::vector<double> small_sym_eig(std::vector<double> A, int n, std::vector<double>* V) {
+  std::vector<double> E(static_cast<size_t>(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) E[i * n + i] = 1.0;
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, diag = 0.0;
     for (int i = 0; i < n; ++i) {
@@ -291,6 +293,9 @@ double small_sym_min_eig(std::vector<double> A, int n) {
           const double akp = A[k * n + p], akq = A[k * n + q];
           A[k * n + p] = c * akp - sn * akq;
           A[k * n + q] = sn * akp + c * akq;
+          const double ekp = E[k * n + p], ekq = E[k * n + q];
+          E[k * n + p] = c * ekp - sn * ekq;
+          E[k * n + q] = sn * ekp + c * ekq;
         }
         for (int k = 0; k < n; ++k) {  // rows p, q
           const double apk = A[p * n + k], aqk = A[q * n + k];
@@ -299,9 +304,16 @@ double small_sym_min_eig(std::vector<double> A, int n) {
         }
       }
   }
-  double m = A[0];
-  for (int i = 1; i < n; ++i) m = std::min(m, A[i * n + i]);
-  return m;
+  std::vector<double> lam(n);
+  for (int i = 0; i < n; ++i) lam[i] = A[i * n + i];
+  if (V) *V = E;
+  return lam;
+}
+
+double small_sym_min_eig(const std::vector<double>& A, int n) {
+  if (n == 0) return 0.0;
+  const std::vector<double> lam = small_sym_eig(A, n, nullptr);
+  return *std::min_element(lam.begin(), lam.end());
 }
 
 template <int R>
@@ -384,37 +396,59 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
     hipLaunchKernelGGL(multiaxpy_kernel, dim3(gb), dim3(kB), 0, s, V.ptr, nv, n, c2.ptr, -1.0, w.ptr);
     XM_LAUNCH_CHECK("orthogonalize");
   };
-  // Deflation basis: the rows of D^{1/2} Y by Gram-Schmidt, keeping a row only
-  // if what is left of it exceeds kDeflRel times the largest row norm.  Rows of
-  // Y that are (numerically) combinations of the others -- a rank-5 factor of a
-  // rank-3 optimum carries two such rows at the level of the solver's gradient --
-  // would add directions that are neither null vectors of Z nor small in the
-  // coupling term below; they stay in the complement, where Lanczos sees them.
-  auto scaled_row = [&](int a) {
-    hipLaunchKernelGGL(column_kernel, dim3(gb), dim3(kB), 0, s, Yt, r, a, n, yv.ptr);
-    hipLaunchKernelGGL(blockmul_kernel, dim3(gb), dim3(kB), 0, s, N, p->Dhalf.ptr, yv.ptr, w.ptr);
-    XM_LAUNCH_CHECK("blockmul_kernel");
-  };
-  auto norm_of_w = [&](double* out_vec) {
+  // Deflation basis: the left singular vectors of D^{1/2} Y^T (3N x r) whose
+  // singular values exceed kDeflRel times the largest, from the eigenpairs of
+  // the r x r Gram matrix (sigma_j^2, e_j): w_j = D^{1/2} Y^T e_j / sigma_j.
+  // Directions of Y's row space that are (numerically) combinations of the
+  // others -- a rank-5 factor of a rank-3 optimum carries two such at the level
+  // of the solver's gradient -- would add directions that are neither null
+  // vectors of Z nor small in the coupling term below; they stay in the
+  // complement, where Lanczos sees them.
+  auto norm_of_w = [&](double* out_vec) {  // out_vec = w / |w|
     hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w.ptr, n, c1.ptr, c2.ptr, 0,
                        static_cast<double*>(nullptr), beta.ptr, 0, out_vec);
     XM_LAUNCH_CHECK("normalize_kernel");
-    double bn = 0.0;
-    XM_HIP(hipMemcpyAsync(&bn, beta.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
-    XM_HIP(hipStreamSynchronize(s));
-    return bn;
   };
-  double rmax = 0.0;
+  DevBuf<double> rows(static_cast<size_t>(r) * n);
   for (int a = 0; a < r; ++a) {
-    scaled_row(a);
-    rmax = std::max(rmax, norm_of_w(Qx.ptr));
+    hipLaunchKernelGGL(column_kernel, dim3(gb), dim3(kB), 0, s, Yt, r, a, n, yv.ptr);
+    hipLaunchKernelGGL(blockmul_kernel, dim3(gb), dim3(kB), 0, s, N, p->Dhalf.ptr, yv.ptr,
+                       rows.ptr + static_cast<int64_t>(a) * n);
+    XM_LAUNCH_CHECK("blockmul_kernel");
   }
-  const double keep_min = std::max(kDeflRel * rmax, 1e-10 * std::sqrt(static_cast<double>(N) * p->dmax));
-  int nb = 0;
+  std::vector<double> gram(static_cast<size_t>(r) * r);
   for (int a = 0; a < r; ++a) {
-    scaled_row(a);
-    orthogonalize(nb);
-    if (norm_of_w(V.ptr + static_cast<int64_t>(nb) * n) > keep_min) ++nb;
+    hipLaunchKernelGGL(multidot_kernel, dim3(r, kDotSeg), dim3(kB), 0, s, rows.ptr, n,
+                       rows.ptr + static_cast<int64_t>(a) * n, dpart.ptr);
+    hipLaunchKernelGGL(multidot_sum_kernel, dim3(1), dim3(kB), 0, s, dpart.ptr, r, c1.ptr);
+    XM_LAUNCH_CHECK("multidot_kernel");
+    XM_HIP(hipMemcpyAsync(gram.data() + static_cast<size_t>(a) * r, c1.ptr, r * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+  }
+  XM_HIP(hipStreamSynchronize(s));
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < a; ++b) gram[a * r + b] = gram[b * r + a] = 0.5 * (gram[a * r + b] + gram[b * r + a]);
+  std::vector<double> E;
+  const std::vector<double> sig2 = small_sym_eig(gram, r, &E);
+  std::vector<int> idx(r);
+  for (int a = 0; a < r; ++a) idx[a] = a;
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return sig2[x] > sig2[y]; });
+  const double smax = std::sqrt(std::max(0.0, sig2[idx[0]]));
+  const double keep_min = std::max(kDeflRel * smax, 1e-10 * std::sqrt(static_cast<double>(N) * p->dmax));
+  int nb = 0;
+  std::vector<double> coef(r);
+  for (int jj = 0; jj < r; ++jj) {
+    const int j = idx[jj];
+    const double sj = std::sqrt(std::max(0.0, sig2[j]));
+    if (!(sj > keep_min)) break;
+    for (int a = 0; a < r; ++a) coef[a] = E[a * r + j] / sj;
+    XM_HIP(hipMemcpyAsync(c1.ptr, coef.data(), r * sizeof(double), hipMemcpyHostToDevice, s));
+    XM_HIP(hipMemsetAsync(w.ptr, 0, n * sizeof(double), s));
+    hipLaunchKernelGGL(multiaxpy_kernel, dim3(gb), dim3(kB), 0, s, rows.ptr, r, n, c1.ptr, 1.0, w.ptr);
+    XM_LAUNCH_CHECK("multiaxpy_kernel");
+    orthogonalize(nb);  // exact up to rounding; keeps the basis orthonormal to machine precision
+    norm_of_w(V.ptr + static_cast<int64_t>(nb) * n);
+    ++nb;
   }
   // The deflated block.  W = V[0..nb) is an orthonormal basis of D^{1/2} rows(Y).
   // With a = lambda_min(W^T Zs W), e = |(I - W W^T) Zs W| and b the smallest

@@ -22,9 +22,7 @@ struct Manifold {
 
   // G = Q Yt.  part: [blocks][5] = {cost, |grad|^2 (metric), |Y|_F^2, sum s^2 q_kk,
   //                                 pscale * <grad, P grad>}
-  // G may be FP64 with an FP32 point: the projection is then formed in FP64
-  template <typename TG>
-  void grad(int r, const T* Rt, const T* s, const TG* G, T* gR, T* gs, T* Sc, T* ec, double* part,
+  void grad(int r, const T* Rt, const T* s, const T* G, T* gR, T* gs, T* Sc, T* ec, double* part,
             hipStream_t st) const;
   // mode 0: d = -res; 1: d = -res + beta d; 2: d unchanged.  Ydot = ds R + s dR.
   void ydot(int r, const T* Rt, const T* s, const T* resR, const T* ress, T* dR, T* ds, double beta, int mode,
@@ -40,11 +38,8 @@ struct Manifold {
   void retract(int r, const T* Rt, const T* s, const T* etaR, const T* etas, T* Rt2, T* s2, T* Yt2,
                hipStream_t st) const;
   // part: [blocks][3] = {<g,eta>, <eta,Heta>, <Y2-Y, G2+G> (the cost change)}
-  // lagr: subtract the Lagrangian correction of the cost change (small steps
-  // near the optimum in reduced precision)
-  template <typename TG>
   void model(int r, const T* s, const T* gR, const T* gs, const T* etaR, const T* etas, const T* HetaR,
-             const T* Hetas, const T* Yt, const TG* G, const T* Yt2, const TG* G2, bool lagr, double* part,
+             const T* Hetas, const T* Yt, const T* G, const T* Yt2, const T* G2, double* part,
              hipStream_t st) const;
   // rank r -> r + 1 along [0; v^T] with step alpha; Rt2 / Yt2 have rank r + 1
   void escape(int r, const T* Rt, const T* s, const double* v, double alpha, T* Rt2, T* Yt2, hipStream_t st) const;

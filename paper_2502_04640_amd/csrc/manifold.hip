@@ -43,22 +43,6 @@ struct Blk {
 #pragma unroll
       for (int a = 0; a < R; ++a) q[c * R + a] = v[c][a];
   }
-  template <typename U>
-  __device__ void load_cvt(const U* p, int k) {
-    const U* q = p + static_cast<int64_t>(k) * 3 * R;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int a = 0; a < R; ++a) v[c][a] = static_cast<T>(q[c * R + a]);
-  }
-  template <typename U>
-  __device__ void store_cvt(U* p, int k) const {
-    U* q = p + static_cast<int64_t>(k) * 3 * R;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int a = 0; a < R; ++a) q[c * R + a] = static_cast<U>(v[c][a]);
-  }
 };
 
 template <typename T, int R>
@@ -131,40 +115,39 @@ __device__ __forceinline__ void write_partials(double (&v)[NQ], double* part) {
 }
 
 // ---------------------------------------------------------------------------
-// TG: type of G and of the arithmetic (FP64 G with an FP32 point forms the
-// projection E - R S, whose terms cancel near the optimum, in FP64).
-template <typename T, int R, typename TG>
+// Riemannian gradient: E_k = s_k Gamma_k projected on the tangent space of
+// the Stiefel factor, e_k = <R_k, Gamma_k> for the scale (Gamma = 2 Q Y).
+template <typename T, int R>
 __global__ __launch_bounds__(kB) void grad_kernel(int32_t N, const T* __restrict__ Rt, const T* __restrict__ s,
-                                                  const TG* __restrict__ G, T* __restrict__ gR, T* __restrict__ gs,
+                                                  const T* __restrict__ G, T* __restrict__ gR, T* __restrict__ gs,
                                                   T* __restrict__ Sc, T* __restrict__ ec, const double* qkk,
                                                   double* part) {
   const int k = blockIdx.x * kB + threadIdx.x;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (k < N) {
-    Blk<TG, R> Rk, Gam;
-    Rk.load_cvt(Rt, k);
+    Blk<T, R> Rk, Gam;
+    Rk.load(Rt, k);
     Gam.load(G, k);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int a = 0; a < R; ++a) Gam.v[c][a] *= TG(2);
-    const TG sk = static_cast<TG>(s[k]);
+      for (int a = 0; a < R; ++a) Gam.v[c][a] *= T(2);
+    const T sk = s[k];
     const double e = dotb(Rk, Gam);
-    TG M[3][3];
+    T M[3][3];
     xty(Rk, Gam, M);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int d = 0; d < 3; ++d) M[c][d] *= sk;
     symm(M);
-    Blk<TG, R> g;
+    Blk<T, R> g;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int a = 0; a < R; ++a) g.v[c][a] = sk * Gam.v[c][a];
     sub_xs(g, Rk, M);
-    Blk<T, R> gt;
-    gt.load_cvt(&g.v[0][0], 0);
+    const Blk<T, R>& gt = g;
     gt.store(gR, k);
     const T gsk = (k == 0) ? T(0) : static_cast<T>(static_cast<double>(sk) * sk * e);
     gs[k] = gsk;
@@ -396,18 +379,17 @@ __global__ __launch_bounds__(kB) void retract_kernel(int32_t N, const T* __restr
 }
 
 // partials: <g, eta>, <eta, Heta>, <Y2 - Y, G2 + G>
-template <typename T, int R, typename TG>
+template <typename T, int R>
 __global__ __launch_bounds__(kB) void model_kernel(int32_t N, const T* __restrict__ s, const T* __restrict__ gR,
                                                    const T* __restrict__ gs, const T* __restrict__ etaR,
                                                    const T* __restrict__ etas, const T* __restrict__ HetaR,
                                                    const T* __restrict__ Hetas, const T* __restrict__ Yt,
-                                                   const TG* __restrict__ G, const T* __restrict__ Yt2,
-                                                   const TG* __restrict__ G2, int lagr, double* part) {
+                                                   const T* __restrict__ G, const T* __restrict__ Yt2,
+                                                   const T* __restrict__ G2, double* part) {
   const int k = blockIdx.x * kB + threadIdx.x;
   double v[3] = {0.0, 0.0, 0.0};
   if (k < N) {
-    Blk<T, R> g, e, he, y, y2;
-    Blk<TG, R> gg, g2;
+    Blk<T, R> g, e, he, y, y2, gg, g2;
     g.load(gR, k);
     e.load(etaR, k);
     he.load(HetaR, k);
@@ -426,37 +408,6 @@ __global__ __launch_bounds__(kB) void model_kernel(int32_t N, const T* __restric
       for (int a = 0; a < R; ++a)
         df += (static_cast<double>(y2.v[c][a]) - static_cast<double>(y.v[c][a])) *
               (static_cast<double>(g2.v[c][a]) + static_cast<double>(gg.v[c][a]));
-    // Lagrangian correction (lagr != 0): - <Lambda_k, Y2_k^T Y2_k - Y_k^T Y_k>
-    // with the multiplier estimate Lambda_k = sym(Y_k^T G_k) / s_k^2 (traceless
-    // for k >= 1).  It vanishes for points exactly on the manifold and cancels
-    // the first-order cost change of their rounding off it, which otherwise
-    // hides the true decrease near the optimum in reduced precision.  Meant for
-    // small steps: frames whose scale changes by more than 1% are left out.
-    if (lagr) {
-      double L[3][3], C[3][3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          double yg = 0.0, c1 = 0.0, c2 = 0.0;
-#pragma unroll
-          for (int a = 0; a < R; ++a) {
-            yg += static_cast<double>(y.v[c][a]) * static_cast<double>(gg.v[d][a]);
-            c1 += static_cast<double>(y.v[c][a]) * static_cast<double>(y.v[d][a]);
-            c2 += static_cast<double>(y2.v[c][a]) * static_cast<double>(y2.v[d][a]);
-          }
-          L[c][d] = yg / (sd * sd);
-          C[c][d] = c2 - c1;
-        }
-      double corr = 0.0;
-      const double tr3 = (k == 0) ? 0.0 : (L[0][0] + L[1][1] + L[2][2]) / 3.0;
-      const double t1 = 3.0 * sd * sd, t2 = t1 + C[0][0] + C[1][1] + C[2][2];  // tr(C1), tr(C2)
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) corr += (0.5 * (L[c][d] + L[d][c]) - (c == d ? tr3 : 0.0)) * C[c][d];
-      if (fabs(t2 / t1 - 1.0) < 0.02) df -= corr;
-    }
     v[2] = df;
   }
   write_partials<3>(v, part);
@@ -586,10 +537,9 @@ template double vec_dot<double>(const double*, const double*, int64_t, double*, 
   }
 
 template <typename T>
-template <typename TG>
-void Manifold<T>::grad(int r, const T* Rt, const T* s, const TG* G, T* gR, T* gs, T* Sc, T* ec, double* part,
+void Manifold<T>::grad(int r, const T* Rt, const T* s, const T* G, T* gR, T* gs, T* Sc, T* ec, double* part,
                        hipStream_t st) const {
-  XM_DISPATCH_R(r, hipLaunchKernelGGL((grad_kernel<T, R, TG>), dim3(blocks()), dim3(kB), 0, st, N, Rt, s, G, gR,
+  XM_DISPATCH_R(r, hipLaunchKernelGGL((grad_kernel<T, R>), dim3(blocks()), dim3(kB), 0, st, N, Rt, s, G, gR,
                                       gs, Sc, ec, qkk, part));
   XM_LAUNCH_CHECK("grad_kernel");
 }
@@ -630,12 +580,11 @@ void Manifold<T>::retract(int r, const T* Rt, const T* s, const T* etaR, const T
 }
 
 template <typename T>
-template <typename TG>
 void Manifold<T>::model(int r, const T* s, const T* gR, const T* gs, const T* etaR, const T* etas, const T* HetaR,
-                        const T* Hetas, const T* Yt, const TG* G, const T* Yt2, const TG* G2, bool lagr,
-                        double* part, hipStream_t st) const {
-  XM_DISPATCH_R(r, hipLaunchKernelGGL((model_kernel<T, R, TG>), dim3(blocks()), dim3(kB), 0, st, N, s, gR, gs, etaR,
-                                      etas, HetaR, Hetas, Yt, G, Yt2, G2, lagr ? 1 : 0, part));
+                        const T* Hetas, const T* Yt, const T* G, const T* Yt2, const T* G2, double* part,
+                        hipStream_t st) const {
+  XM_DISPATCH_R(r, hipLaunchKernelGGL((model_kernel<T, R>), dim3(blocks()), dim3(kB), 0, st, N, s, gR, gs, etaR,
+                                      etas, HetaR, Hetas, Yt, G, Yt2, G2, part));
   XM_LAUNCH_CHECK("model_kernel");
 }
 
@@ -674,21 +623,5 @@ void Manifold<T>::init(int r, double lift, T* Rt, T* s, hipStream_t st) const {
 
 template struct Manifold<float>;
 template struct Manifold<double>;
-template void Manifold<float>::grad<float>(int, const float*, const float*, const float*, float*, float*, float*,
-                                           float*, double*, hipStream_t) const;
-template void Manifold<float>::grad<double>(int, const float*, const float*, const double*, float*, float*, float*,
-                                            float*, double*, hipStream_t) const;
-template void Manifold<double>::grad<double>(int, const double*, const double*, const double*, double*, double*,
-                                             double*, double*, double*, hipStream_t) const;
-template void Manifold<float>::model<float>(int, const float*, const float*, const float*, const float*,
-                                            const float*, const float*, const float*, const float*, const float*,
-                                            const float*, const float*, bool, double*, hipStream_t) const;
-template void Manifold<float>::model<double>(int, const float*, const float*, const float*, const float*,
-                                             const float*, const float*, const float*, const float*, const double*,
-                                             const float*, const double*, bool, double*, hipStream_t) const;
-template void Manifold<double>::model<double>(int, const double*, const double*, const double*, const double*,
-                                              const double*, const double*, const double*, const double*,
-                                              const double*, const double*, const double*, bool, double*,
-                                              hipStream_t) const;
 
 }  // namespace xm

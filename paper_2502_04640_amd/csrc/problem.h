@@ -47,6 +47,7 @@ struct xm_problem {
   xm::DevBuf<double> fac;
   xm::DevBuf<double> fact_scratch;   // padded Y^T, W and V of the factored product
   xm::DevBuf<double> perm_scratch;   // Y^T and Y^T Q in the frame order (dense products)
+  xm::DevBuf<float> mixed_scratch;   // FP32 copies of an FP64 operand and result (mixed products)
   // FP32 copies of the factors (with XM_KEEP_F32): fac as above, -G^{-1}
   xm::DevBuf<float> fac32, Gm32;
   xm::DevBuf<double> Att;            // [nnzb]:    A_tt[i][j]
@@ -82,6 +83,33 @@ struct xm_problem {
 
 namespace xm {
 
+// Temporary device memory of one Y Q product.  Without a fixed region (the
+// normal entry points) the handle's grow-only buffers serve, allocated on
+// first use; with one (xm_spmm_noalloc) every temporary is carved from it in
+// order, 256-byte aligned, and nothing is allocated: a request beyond its end
+// throws XM_EINVAL.
+struct Scratch {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+
+template <typename T, typename B>
+T* take(Scratch* sc, DevBuf<B>& own, size_t count, hipStream_t s) {
+  const size_t bytes = count * sizeof(T);
+  if (sc && sc->base) {
+    const size_t off = (sc->used + 255) & ~static_cast<size_t>(255);
+    require(off + bytes <= sc->cap, XM_EINVAL, "the product needs more temporary memory than the fixed scratch holds");
+    sc->used = off + bytes;
+    return reinterpret_cast<T*>(sc->base + off);
+  }
+  const size_t n = (bytes + sizeof(B) - 1) / sizeof(B);
+  if (own.n < n) {
+    XM_HIP(hipStreamSynchronize(s));
+    own.alloc(n);
+  }
+  return reinterpret_cast<T*>(own.ptr);
+}
+
 // build_q.hip
 std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame,
                                           const int32_t* landmark, const void* u, xm_dtype u_dtype,
@@ -92,9 +120,13 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
 // Yt is [3N][r] (row i holds Y[0..r)[i]).  T is the vector precision.
 // role: XM_ROLE_RESIDUAL (gradient, cost, multipliers: accuracy at the optimum)
 // or XM_ROLE_CURVATURE (Hessian-vector and Lanczos products of directions).
+// sc: temporaries from a fixed region (NULL: the handle's buffers).
 template <typename T>
 void spmm_yt(const xm_problem* p, xm_dtype qtype, const T* Yt, int r, T* out, hipStream_t s,
-             int role = XM_ROLE_RESIDUAL);
+             int role = XM_ROLE_RESIDUAL, Scratch* sc = nullptr);
+// Bytes of temporaries spmm_yt<T> takes from a fixed region for this product
+// (alignment included).
+size_t product_scratch_bytes(const xm_problem* p, xm_dtype qtype, int r, int role, bool fp64_vectors);
 
 // layout conversions between the ABI layout Y[r][3N] and the internal Yt[3N][r]
 template <typename Ts, typename Td>

@@ -16,38 +16,28 @@
 // sqrt(3N)/8; rho carries the usual max(1,|f|) 1e3 eps regularisation.
 // Stop when |grad| <= grad_tol qbar |Y|, or, at the precision floor of
 // reduced-precision products, after 6 rejected steps in a row with |grad|
-// within 30 grad_tol qbar |Y|.  A reduced-precision solve then checks the
-// gradient with FP64 products and, if it is above grad_tol / 30, runs one
-// short trust-region pass (at most 8 steps toward that tolerance; truncated-CG
-// steps of at most 100 products, enough to resolve the flat scale modes of
-// weakly linked frames) whose gradient products
-// are taken relative to the current point, with the FP64 product at that point
-// as reference (see Rebase).  The
-// cost decrease is evaluated as <Y+ - Y, Q (Y+ + Y)> from the two products
-// already computed, which stays accurate in FP32 where f(Y+) - f(Y) would
-// cancel.  The staircase escape follows Theorem "Descent Direction": block k of
-// [Y; alpha v^T] is re-orthonormalised (scale kept), alpha halved until the
-// cost drops, at most 40 times.
+// within 30 grad_tol qbar |Y|.  A reduced-precision solve then continues from
+// that point in an FP64 stage: the iterate, the manifold arithmetic and the
+// gradient products in FP64, the truncated-CG Hessian-vector products in
+// FP32 (an inexact-Newton / iterative-refinement split:
+// the model only steers the step, the FP64 gradient decides where it ends),
+// down to the FP64 tolerance.  An FP32 iterate cannot get closer to the
+// optimum than its own rounding, whose gradient (about |Q| 6e-8 |Y|) is far
+// above what the dual certificate needs.  The candidate's cost change is
+// evaluated as <Y+ - Y, Q (Y+ + Y)> from the two products already computed,
+// which stays accurate where f(Y+) - f(Y) would cancel.  The staircase escape
+// follows Theorem "Descent Direction": block k of [Y; alpha v^T] is
+// re-orthonormalised (scale kept), alpha halved until the cost drops, at most
+// 40 times.
 #include <chrono>
 #include <cmath>
+#include <memory>
 #include <cstdio>
 #include <type_traits>
 #include <vector>
 
 #include "manifold.h"
 #include "problem.h"
-
-// Refinement pass of reduced-precision solves (compile-time constants):
-// passes, trust-region steps per pass, products per truncated-CG solve.
-#ifndef XM_REFINE_PASSES
-#define XM_REFINE_PASSES 1
-#endif
-#ifndef XM_REFINE_STEPS
-#define XM_REFINE_STEPS 8
-#endif
-#ifndef XM_REFINE_INNER
-#define XM_REFINE_INNER 100
-#endif
 
 namespace xm {
 namespace {
@@ -68,33 +58,13 @@ struct Vecs {
   }
 };
 
-// Gradient products relative to a reference point (reduced precision only):
-// G(Y) = Gref + Q (Y - Yref) with Gref = Q Yref from the FP64 Q, kept in FP64.
-// The reduced-precision product then only carries the rounding error of the
-// small difference Y - Yref, not of Q Y itself, whose entries cancel heavily
-// near the optimum (Y is close to the null space of the dual matrix).  G is
-// kept in FP64 (G64), and the Riemannian gradient and the cost change are
-// formed from it in FP64, so that the cancellation in the projection
-// E - R sym(R^T E) loses nothing either; the Hessian products use the rounded
-// copy.  This is what lets an FP32 solve converge below the rounding noise
-// of its own products.
-template <typename T>
-struct Rebase {
-  const T* Yref = nullptr;
-  const double* Gref = nullptr;  // Q Yref, FP64
-  T* tmp = nullptr;
-  double* G64 = nullptr;         // G(Y) at the current point, FP64
-  double* G2_64 = nullptr;       // G(Y) at the candidate, FP64
-  bool on() const { return Yref != nullptr; }
-};
-
 template <typename T>
 __global__ void sub_kernel(int64_t n, const T* __restrict__ a, const T* __restrict__ b, T* __restrict__ out) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (i < n) out[i] = a[i] - b[i];
 }
 
-// G64 = Gref + G (FP64); G <- G64 rounded
+// G64 = Gref + G (FP64); G <- G64 rounded (candidate products chained through the step)
 template <typename T>
 __global__ void combine_kernel(int64_t n, const double* __restrict__ Gref, T* __restrict__ G,
                                double* __restrict__ G64) {
@@ -130,33 +100,15 @@ __global__ void widen_kernel(int64_t n, const T* __restrict__ a, double* __restr
   if (i < n) out[i] = static_cast<double>(a[i]);
 }
 
-template <typename T>
-void grad_product(xm_problem* p, xm_dtype qg, const T* Yt, int r, T* G, double* G64, const Rebase<T>& rb,
-                  hipStream_t st) {
-  const int64_t n = p->n3 * static_cast<int64_t>(r);
-  if (!rb.on()) {
-    spmm_yt<T>(p, qg, Yt, r, G, st);
-    return;
-  }
-  hipLaunchKernelGGL(sub_kernel<T>, dim3(cdiv(n, 256)), dim3(256), 0, st, n, Yt, rb.Yref, rb.tmp);
-  XM_LAUNCH_CHECK("sub_kernel");
-  // the product of the small difference Y - Yref: no cancellation at the scale
-  // of Q Y, so the curvature-role product (the factored form on large
-  // problems) is accurate enough
-  spmm_yt<T>(p, qg, rb.tmp, r, G, st, XM_ROLE_CURVATURE);
-  hipLaunchKernelGGL(combine_kernel<T>, dim3(cdiv(n, 256)), dim3(256), 0, st, n, rb.Gref, G, G64);
-  XM_LAUNCH_CHECK("combine_kernel");
-}
-
 struct RtrOut {
-  double f = 0, gnorm = 0, ynorm = 0;
+  double f = 0, gnorm = 0, ynorm = 0, Delta = 0;
   int outer = 0, inner = 0, spmm = 0, accepted = 0;
   bool converged = false, floor = false;
 };
 
 template <typename T>
 RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_solve_opts& o, double grad_tol,
-           const Rebase<T>& rb, hipStream_t st) {
+           hipStream_t st) {
   const int N = p->N;
   Manifold<T> mf(N);
   if (o.precondition) mf.qkk = p->qkk.ptr;
@@ -176,8 +128,6 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
   double sums[5];
 
   mf.scale(r, V.Rt.ptr, V.s.ptr, V.Yt.ptr, st);
-  double* G64 = rb.G64;
-  double* G2_64 = rb.G2_64;
   // Candidate products from the step (when the curvature products are
   // factored): G(Y+) = G(Y) + Q (Y+ - Y), the product of the small difference
   // taken in the curvature role and added in FP64.  Its rounding scales with
@@ -186,7 +136,7 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
   // product; past that, a full product restarts the chain.
   constexpr double kChainFrac = 0.05;
   const size_t nvr0 = static_cast<size_t>(3) * N * r;
-  const bool chain = !rb.on() && p->spmm_kind[XM_ROLE_CURVATURE][qg] == XM_SPMM_FACTORED;
+  const bool chain = p->spmm_kind[XM_ROLE_CURVATURE][qg] == XM_SPMM_FACTORED;
   DevBuf<T> dY;
   DevBuf<double> C64a, C64b;  // FP64 G at the current point and at the candidate
   double* Gc64 = nullptr;
@@ -200,12 +150,9 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
     Gc2_64 = C64b.ptr;
   }
   auto form_grad = [&]() {
-    if (rb.on()) mf.grad(r, V.Rt.ptr, V.s.ptr, static_cast<const double*>(G64), V.gR.ptr, V.gs.ptr, V.Sc.ptr,
-                         V.ec.ptr, V.part.ptr, st);
-    else mf.grad(r, V.Rt.ptr, V.s.ptr, static_cast<const T*>(V.G.ptr), V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr,
-                 V.part.ptr, st);
+    mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
   };
-  grad_product<T>(p, qg, V.Yt.ptr, r, V.G.ptr, G64, rb, st);
+  spmm_yt<T>(p, qg, V.Yt.ptr, r, V.G.ptr, st);
   ++out.spmm;
   if (chain) {
     hipLaunchKernelGGL(widen_kernel<T>, dim3(cdiv(nvr0, 256)), dim3(256), 0, st, static_cast<int64_t>(nvr0),
@@ -280,7 +227,7 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
       }
     }
     if (!chained) {
-      grad_product<T>(p, qg, V.Yt2.ptr, r, V.G2.ptr, G2_64, rb, st);
+      spmm_yt<T>(p, qg, V.Yt2.ptr, r, V.G2.ptr, st);
       if (chain) {
         hipLaunchKernelGGL(widen_kernel<T>, dim3(cdiv(nvr0, 256)), dim3(256), 0, st, static_cast<int64_t>(nvr0),
                            V.G2.ptr, Gc2_64);
@@ -288,12 +235,8 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
       }
     }
     ++out.spmm;
-    if (rb.on())
-      mf.model(r, V.s.ptr, V.gR.ptr, V.gs.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr, V.Yt.ptr,
-               static_cast<const double*>(G64), V.Yt2.ptr, static_cast<const double*>(G2_64), true, V.part.ptr, st);
-    else
-      mf.model(r, V.s.ptr, V.gR.ptr, V.gs.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr, V.Yt.ptr,
-               static_cast<const T*>(V.G.ptr), V.Yt2.ptr, static_cast<const T*>(V.G2.ptr), false, V.part.ptr, st);
+    mf.model(r, V.s.ptr, V.gR.ptr, V.gs.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr, V.Yt.ptr, V.G.ptr,
+             V.Yt2.ptr, V.G2.ptr, V.part.ptr, st);
     read_partials(V.part.ptr, nb, 3, sums, st);
     const double mdec = -(sums[0] + 0.5 * sums[1]);
     const double df = sums[2];
@@ -322,7 +265,6 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
       std::swap(V.s.ptr, V.s2.ptr);
       std::swap(V.Yt.ptr, V.Yt2.ptr);
       std::swap(V.G.ptr, V.G2.ptr);
-      std::swap(G64, G2_64);
       if (chain) {
         std::swap(Gc64, Gc2_64);
         chain_dist = chained ? chain_dist + step : 0.0;
@@ -342,16 +284,16 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
   out.f = f;
   out.gnorm = gnorm;
   out.ynorm = ynorm;
+  out.Delta = Delta;
   return out;
 }
 
-// cost, gradient norm and |Y|_F of the current point from FP64 products (for
-// reduced-precision solves); optionally the FP64 product Q Y, rounded to T
+// cost, gradient norm and |Y|_F of a point from an FP64 product
 struct Check {
   double f, gnorm, ynorm;
 };
 
-Check fp64_check(xm_problem* p, const double* Yt64, int r, hipStream_t st, double* G_out = nullptr) {
+Check fp64_check(xm_problem* p, const double* Yt64, int r, hipStream_t st) {
   const int N = p->N;
   Vecs<double> V(N, r);
   Manifold<double> mf(N);
@@ -360,8 +302,51 @@ Check fp64_check(xm_problem* p, const double* Yt64, int r, hipStream_t st, doubl
   mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);
   double sums[5];
   read_partials(V.part.ptr, static_cast<int>(mf.blocks()), 5, sums, st);
-  if (G_out) XM_HIP(hipMemcpyAsync(G_out, V.G.ptr, p->n3 * r * sizeof(double), hipMemcpyDeviceToDevice, st));
   return {sums[0], std::sqrt(sums[1]), std::sqrt(sums[2])};
+}
+
+// Escape to rank r + 1 from the FP64 point X (Rt, s at rank r, Yt = s Rt in
+// Yt64) along v: the cost before and after each trial step from FP64
+// products, since the decrease Theorem "Descent Direction" guarantees is of
+// order alpha^2 |lambda_min|.  On success X.Rt holds the rank-(r + 1) point.
+bool escape_fp64(xm_problem* p, Vecs<double>& X, const double* Yt64, int r, const double* vmin, int* spmm_count,
+                 hipStream_t st) {
+  const int64_t n3 = p->n3;
+  Manifold<double> mf(p->N);
+  const int nblk = static_cast<int>(std::min<unsigned>(mf.blocks(), 8));
+  spmm_yt<double>(p, XM_F64, Yt64, r, X.G2.ptr, st);
+  ++*spmm_count;
+  const double f0 = vec_dot<double>(Yt64, X.G2.ptr, n3 * r, X.part.ptr, nblk, st);
+  double alpha = 1.0;
+  for (int h = 0; h <= 40; ++h, alpha *= 0.5) {
+    mf.escape(r, X.Rt.ptr, X.s.ptr, vmin, alpha, X.Rt2.ptr, X.Yt2.ptr, st);
+    spmm_yt<double>(p, XM_F64, X.Yt2.ptr, r + 1, X.G2.ptr, st);
+    ++*spmm_count;
+    const double fn = vec_dot<double>(X.Yt2.ptr, X.G2.ptr, n3 * (r + 1), X.part.ptr, nblk, st);
+    if (fn < f0) {
+      std::swap(X.Rt.ptr, X.Rt2.ptr);
+      return true;
+    }
+  }
+  return false;
+}
+
+template <typename T>
+__global__ void narrow_kernel(int64_t n, const double* __restrict__ a, T* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) out[i] = static_cast<T>(a[i]);
+}
+
+void add_stats(RtrOut& a, const RtrOut& b) {
+  a.outer += b.outer;
+  a.inner += b.inner;
+  a.spmm += b.spmm;
+  a.f = b.f;
+  a.gnorm = b.gnorm;
+  a.ynorm = b.ynorm;
+  a.Delta = b.Delta;
+  a.converged = b.converged;
+  a.floor = b.floor;
 }
 
 template <typename T>
@@ -369,29 +354,21 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
                     xm_solve_info* info, hipStream_t st) {
   const int N = p->N;
   const int64_t n3 = p->n3;
-  const bool f64 = std::is_same<T, double>::value;
+  constexpr bool f64 = std::is_same<T, double>::value;
   const xm_dtype qg = f64 ? XM_F64 : XM_F32;
   const xm_dtype qh = f64 ? XM_F64 : (o.compute == XM_BF16 ? XM_BF16 : XM_F32);
   const double grad_tol = (o.grad_tol > 0) ? o.grad_tol : (f64 ? 1e-9 : 3e-7);
+  // tolerance of the FP64 stage of a reduced-precision solve: that of an FP64 solve
+  const double grad_tol64 = f64 ? grad_tol : grad_tol / 300.0;
   const double cert_tol = (o.cert_tol > 0) ? o.cert_tol : (f64 ? 1e-7 : 1e-5);
   const int rmax = o.r_max;
   Vecs<T> V(N, rmax + 1);
   Manifold<T> mf(N);
+  Manifold<double> mf64(N);
   DevBuf<double> Yt64(static_cast<size_t>(n3) * (rmax + 1)), vmin(n3);
-  // reduced precision: reference point and FP64 products for the refinement passes
-  DevBuf<T> Yref, Rtmp;
-  DevBuf<double> Gref, G64a, G64b;
-  if (!f64) {
-    Yref.alloc(static_cast<size_t>(n3) * rmax);
-    Rtmp.alloc(static_cast<size_t>(n3) * rmax);
-    Gref.alloc(static_cast<size_t>(n3) * rmax);
-    G64a.alloc(static_cast<size_t>(n3) * rmax);
-    G64b.alloc(static_cast<size_t>(n3) * rmax);
-  }
-  // refinement target: the FP32 stage stops at grad_tol (its products' own
-  // rounding allows little more), the FP64-referenced passes go 30x further
-  const int max_refine = XM_REFINE_PASSES;
-  const double refine_tol = grad_tol / 30.0;
+  // the FP64 stage's vectors (reduced precision only; an FP64 solve works in V)
+  std::unique_ptr<Vecs<double>> W;
+  if (!f64) W.reset(new Vecs<double>(N, rmax + 1));
 
   int r;
   if (Y0) {
@@ -409,88 +386,55 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   CertResult cr;
   while (true) {
     auto t0 = std::chrono::steady_clock::now();
-    ro = rtr<T>(p, V, r, qg, qh, o, grad_tol, Rebase<T>{}, st);
-    // Reduced precision: check the gradient with FP64 products; while it is
-    // above the tolerance, continue from the current point with gradient
-    // products taken relative to it (Rebase), the FP64 product as reference.
-    for (int pass = 0; !f64 && pass < max_refine; ++pass) {
+    ro = rtr<T>(p, V, r, qg, qh, o, grad_tol, st);
+    Vecs<double>* X = nullptr;
+    if constexpr (f64) {
+      X = &V;
+    } else {
+      // FP64 stage from the reduced-precision point (re-orthonormalised in
+      // FP64), starting with the radius the first stage ended with; its
+      // truncated-CG products use the FP32 Q (or factors) also in a BF16
+      // solve, whose coarser Hessian would slow the final Newton steps
       transpose_rows<T, double>(V.Yt.ptr, 1, static_cast<int>(n3 * r), Yt64.ptr, st);
-      const Check ck = fp64_check(p, Yt64.ptr, r, st, Gref.ptr);
-      ++info->spmm_count;
+      X = W.get();
+      mf64.split(r, Yt64.ptr, X->Rt.ptr, X->s.ptr, X->Yt.ptr, st);
+      xm_solve_opts o2 = o;
+      o2.delta0 = std::max(ro.Delta, std::sqrt(3.0 * N) / 512.0);
+      const RtrOut r2 = rtr<double>(p, *X, r, XM_F64, XM_F32, o2, grad_tol64, st);
       if (o.verbose)
-        std::fprintf(stderr, "[xm] rank %d: FP64 check |g|=%.3e (tol %.3e)%s\n", r, ck.gnorm,
-                     refine_tol * p->qbar * ck.ynorm, ck.gnorm <= refine_tol * p->qbar * ck.ynorm ? "" : ", refining");
-      if (ck.gnorm <= refine_tol * p->qbar * ck.ynorm) break;
-      XM_HIP(hipMemcpyAsync(Yref.ptr, V.Yt.ptr, n3 * r * sizeof(T), hipMemcpyDeviceToDevice, st));
-      // a refinement pass is a short polish from a converged point: at most 8
-      // steps, starting from a radius 64x below the default
-      xm_solve_opts oref = o;
-      oref.max_outer = (o.max_outer > 0) ? std::min(o.max_outer, XM_REFINE_STEPS) : XM_REFINE_STEPS;
-      if (oref.delta0 <= 0) oref.delta0 = std::sqrt(3.0 * N) / 8.0 / 64.0;
-      oref.max_inner = (o.max_inner > 0) ? std::min(o.max_inner, XM_REFINE_INNER) : XM_REFINE_INNER;
-      const RtrOut r2 = rtr<T>(p, V, r, qg, qh, oref, refine_tol,
-                               Rebase<T>{Yref.ptr, Gref.ptr, Rtmp.ptr, G64a.ptr, G64b.ptr}, st);
-      ro.outer += r2.outer;
-      ro.inner += r2.inner;
-      ro.spmm += r2.spmm;
-      ro.f = r2.f;
-      ro.gnorm = r2.gnorm;
-      ro.ynorm = r2.ynorm;
-      // convergence is judged at grad_tol: the refinement target is a bonus
-      if (r2.converged && !r2.floor) ro.floor = false;
-      ro.converged = ro.converged || r2.converged;
-      if (r2.accepted == 0) break;  // the iterate's own rounding is the floor: no further progress
+        std::fprintf(stderr, "[xm] rank %d: FP64 stage from |g|=%.3e: %d steps, %d products -> |g|=%.3e\n", r,
+                     ro.gnorm, r2.outer, r2.spmm, r2.gnorm);
+      add_stats(ro, r2);
     }
+    XM_HIP(hipMemcpyAsync(Yt64.ptr, X->Yt.ptr, n3 * r * sizeof(double), hipMemcpyDeviceToDevice, st));
     XM_HIP(hipStreamSynchronize(st));
     auto t1 = std::chrono::steady_clock::now();
     solve_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
     info->outer_iters += ro.outer;
     info->inner_iters += ro.inner;
     info->spmm_count += ro.spmm;
-    // FP64 copy of the factor for the certificate
-    if (f64) XM_HIP(hipMemcpyAsync(Yt64.ptr, V.Yt.ptr, n3 * r * sizeof(double), hipMemcpyDeviceToDevice, st));
-    else transpose_rows<T, double>(V.Yt.ptr, 1, static_cast<int>(n3 * r), Yt64.ptr, st);
     cr = certify_yt(p, Yt64.ptr, r, cert_tol, o.lanczos_max, o.lanczos_tol, vmin.ptr, st);
     auto t2 = std::chrono::steady_clock::now();
     cert_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
     info->lanczos_iters += cr.iters;
     if (o.verbose)
-      std::fprintf(stderr, "[xm] rank %d: f=%.12e |g|=%.3e lambda_s=%.6e (res %.2e, %d it) %s\n", r, ro.f,
-                   ro.gnorm, cr.lambda_min, cr.ritz_residual, cr.iters, cr.certified ? "certified" : "not certified");
+      std::fprintf(stderr, "[xm] rank %d: f=%.12e |g|=%.3e lambda_s=%.6e (res %.2e, %d it) bound %.3e %s\n", r, ro.f,
+                   ro.gnorm, cr.lambda_min, cr.ritz_residual, cr.iters, cr.lambda_bound,
+                   cr.certified ? "certified" : "not certified");
     if (cr.certified || r >= rmax) break;
-    // escape to rank r + 1 with step halving.  The costs before and after are
-    // both taken with FP64 products at the FP64 copies of the points: the
-    // decrease of Theorem "Descent Direction" is of order alpha^2 |lambda_min|,
-    // which a reduced-precision product's rounding near the optimum can exceed.
-    const int nblk = static_cast<int>(std::min<unsigned>(mf.blocks(), 8));
-    DevBuf<double> Y2_64(static_cast<size_t>(n3) * (r + 1)), G2_64(static_cast<size_t>(n3) * (r + 1));
-    spmm_yt<double>(p, XM_F64, Yt64.ptr, r, G2_64.ptr, st);
-    ++info->spmm_count;
-    const double f0 = vec_dot<double>(Yt64.ptr, G2_64.ptr, static_cast<int64_t>(n3) * r, V.part.ptr, nblk, st);
-    bool moved = false;
-    double alpha = 1.0;
-    for (int h = 0; h <= 40; ++h, alpha *= 0.5) {
-      mf.escape(r, V.Rt.ptr, V.s.ptr, vmin.ptr, alpha, V.Rt2.ptr, V.Yt2.ptr, st);
-      const double* y2 = Y2_64.ptr;
-      if constexpr (std::is_same<T, double>::value) y2 = V.Yt2.ptr;
-      else transpose_rows<T, double>(V.Yt2.ptr, 1, static_cast<int>(n3 * (r + 1)), Y2_64.ptr, st);
-      spmm_yt<double>(p, XM_F64, y2, r + 1, G2_64.ptr, st);
-      ++info->spmm_count;
-      // f(Y+) = <Yt2, Q Yt2>
-      const double fn = vec_dot<double>(y2, G2_64.ptr, static_cast<int64_t>(n3) * (r + 1), V.part.ptr, nblk, st);
-      if (fn < f0) {
-        moved = true;
-        break;
-      }
-    }
-    if (!moved) break;
-    std::swap(V.Rt.ptr, V.Rt2.ptr);
+    if (!escape_fp64(p, *X, Yt64.ptr, r, vmin.ptr, &info->spmm_count, st)) break;
     ++r;
     ++info->stair_steps;
+    if constexpr (!f64) {
+      // back to the reduced-precision stage at the new rank
+      const int64_t nr = n3 * r;
+      hipLaunchKernelGGL(narrow_kernel<T>, dim3(cdiv(nr, 256)), dim3(256), 0, st, nr, X->Rt.ptr, V.Rt.ptr);
+      hipLaunchKernelGGL(narrow_kernel<T>, dim3(cdiv(N, 256)), dim3(256), 0, st, static_cast<int64_t>(N), X->s.ptr,
+                         V.s.ptr);
+      XM_LAUNCH_CHECK("narrow_kernel");
+    }
   }
-  // final FP64 quantities
-  if (f64) XM_HIP(hipMemcpyAsync(Yt64.ptr, V.Yt.ptr, n3 * r * sizeof(double), hipMemcpyDeviceToDevice, st));
-  else transpose_rows<T, double>(V.Yt.ptr, 1, static_cast<int>(n3 * r), Yt64.ptr, st);
+  // final FP64 quantities (the certified point is in Yt64)
   const Check ck = fp64_check(p, Yt64.ptr, r, st);
   XM_HIP(hipMemsetAsync(Y_out, 0, static_cast<size_t>(rmax) * n3 * sizeof(double), st));
   transpose_rows<double, double>(Yt64.ptr, static_cast<int>(n3), r, Y_out, st);

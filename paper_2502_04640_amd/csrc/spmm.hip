@@ -372,17 +372,11 @@ Split choose_split(int32_t n3, int32_t ld, int V) {
 }
 
 template <typename TQ, typename TV, typename TA, int R>
-void launch(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStream_t s) {
+void launch(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStream_t s, Scratch* sc) {
   const Split sp = choose_split(p->n3, p->ld, QVec<TQ>::V);
-  auto& scratch = const_cast<xm_problem*>(p)->spmm_scratch;
-  const size_t need = static_cast<size_t>(sp.splits) * p->n3 * R * sizeof(TA);
-  if (scratch.n < need) {
-    XM_HIP(hipStreamSynchronize(s));
-    scratch.alloc(need);
-  }
-  TA* part = reinterpret_cast<TA*>(scratch.ptr);
+  TA* part = take<TA>(sc, const_cast<xm_problem*>(p)->spmm_scratch, static_cast<size_t>(sp.splits) * p->n3 * R, s);
   xm_problem::TimedLaunch* ev = nullptr;
-  if (p->timing) {
+  if (p->timing && !(sc && sc->base)) {
     auto* mp = const_cast<xm_problem*>(p);
     if (mp->events_used == mp->events.size()) {
       xm_problem::TimedLaunch t{};
@@ -414,18 +408,13 @@ int64_t sym_active_blocks(int32_t n, int32_t ld, int C, int RS) {
 
 template <typename TQ, typename TV, typename TA, int R, int RS>
 void sym_product_rs(const TQ* M, int32_t ld, int32_t n, const TV* Yt, TV* out, DevBuf<char>& scratch,
-                    xm_problem::TimedLaunch* ev, hipStream_t s) {
+                    Scratch* sc, xm_problem::TimedLaunch* ev, hipStream_t s) {
   constexpr int V = QVec<TQ>::V;
   constexpr int C = kB * V;
   const int nchunks = static_cast<int>(cdiv(ld, C));
   const int nslabs = static_cast<int>(cdiv(n, RS));
   const size_t per = static_cast<size_t>(n) * R;
-  const size_t need = (static_cast<size_t>(nslabs) + nchunks) * per * sizeof(TA);
-  if (scratch.n < need) {
-    XM_HIP(hipStreamSynchronize(s));
-    scratch.alloc(need);
-  }
-  TA* colpart = reinterpret_cast<TA*>(scratch.ptr);
+  TA* colpart = take<TA>(sc, scratch, (static_cast<size_t>(nslabs) + nchunks) * per, s);
   TA* rowpart = colpart + static_cast<size_t>(nslabs) * per;
   if (ev) XM_HIP(hipEventRecord(ev->start, s));
   hipLaunchKernelGGL((spmm_sym_kernel<TQ, TV, TA, R, RS>), dim3(nchunks, nslabs), dim3(kB), 0, s, M, ld, n, Yt,
@@ -440,20 +429,22 @@ void sym_product_rs(const TQ* M, int32_t ld, int32_t n, const TV* Yt, TV* out, D
 // out (n x R) = M Yt for a symmetric n x n matrix M (row-major, leading
 // dimension ld, zero padding columns) read through its upper triangle.
 template <typename TQ, typename TV, typename TA, int R>
-void sym_product(const TQ* M, int32_t ld, int32_t n, const TV* Yt, TV* out, DevBuf<char>& scratch,
+void sym_product(const TQ* M, int32_t ld, int32_t n, const TV* Yt, TV* out, DevBuf<char>& scratch, Scratch* sc,
                  xm_problem::TimedLaunch* ev, hipStream_t s) {
   constexpr int C = kB * QVec<TQ>::V;
   const int64_t kSymMinBlocks = sizeof(TQ) == 8 ? XM_SYM_MIN_BLOCKS : XM_SYM_MIN_BLOCKS / 2;
   if (sym_active_blocks(n, ld, C, 256) >= kSymMinBlocks)
-    sym_product_rs<TQ, TV, TA, R, 256>(M, ld, n, Yt, out, scratch, ev, s);
+    sym_product_rs<TQ, TV, TA, R, 256>(M, ld, n, Yt, out, scratch, sc, ev, s);
   else if (sym_active_blocks(n, ld, C, 128) >= kSymMinBlocks)
-    sym_product_rs<TQ, TV, TA, R, 128>(M, ld, n, Yt, out, scratch, ev, s);
+    sym_product_rs<TQ, TV, TA, R, 128>(M, ld, n, Yt, out, scratch, sc, ev, s);
   else
-    sym_product_rs<TQ, TV, TA, R, 64>(M, ld, n, Yt, out, scratch, ev, s);
+    sym_product_rs<TQ, TV, TA, R, 64>(M, ld, n, Yt, out, scratch, sc, ev, s);
 }
 
-xm_problem::TimedLaunch* timed_launch(const xm_problem* p, int dtype, double bytes) {
-  if (!p->timing) return nullptr;
+// HIP events around a launch when timing is on (never inside a fixed-scratch
+// call, which creates nothing)
+xm_problem::TimedLaunch* timed_launch(const xm_problem* p, int dtype, double bytes, const Scratch* sc) {
+  if (!p->timing || (sc && sc->base)) return nullptr;
   auto* mp = const_cast<xm_problem*>(p);
   if (mp->events_used == mp->events.size()) {
     xm_problem::TimedLaunch t{};
@@ -468,10 +459,10 @@ xm_problem::TimedLaunch* timed_launch(const xm_problem* p, int dtype, double byt
 }
 
 template <typename TQ, typename TV, typename TA, int R>
-void launch_sym(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStream_t s) {
+void launch_sym(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStream_t s, Scratch* sc) {
   xm_problem::TimedLaunch* ev =
-      timed_launch(p, QVec<TQ>::dtype, 0.5 * static_cast<double>(p->n3) * (p->n3 + 1) * sizeof(TQ));
-  sym_product<TQ, TV, TA, R>(Q, p->ld, p->n3, Yt, out, const_cast<xm_problem*>(p)->spmm_scratch, ev, s);
+      timed_launch(p, QVec<TQ>::dtype, 0.5 * static_cast<double>(p->n3) * (p->n3 + 1) * sizeof(TQ), sc);
+  sym_product<TQ, TV, TA, R>(Q, p->ld, p->n3, Yt, out, const_cast<xm_problem*>(p)->spmm_scratch, sc, ev, s);
 }
 
 // ---- factored product: Q = A_rr + B Gm B^T, Gm = -G^{-1} --------------------
@@ -648,25 +639,36 @@ Factors<float> factors(const xm_problem* p, float*) {
   return {p->fac32.ptr, p->Gm32.ptr};
 }
 
+// doubles of the factored product's own temporaries (padded Yt, W, V)
+size_t factored_scratch_doubles(int32_t N) { return 24 * static_cast<size_t>(N) + 16 * static_cast<size_t>(N - 1); }
+
+// bytes of the partial sums of sym_product for an n x n matrix, value size b,
+// accumulator size a (the slab height it would choose)
+size_t sym_scratch_bytes(int32_t n, int32_t ld, int V, size_t a, int R) {
+  const int C = kB * V;
+  const int64_t kSymMinBlocks = V == 2 ? XM_SYM_MIN_BLOCKS : XM_SYM_MIN_BLOCKS / 2;
+  int RS = 64;
+  if (sym_active_blocks(n, ld, C, 256) >= kSymMinBlocks) RS = 256;
+  else if (sym_active_blocks(n, ld, C, 128) >= kSymMinBlocks) RS = 128;
+  const size_t nchunks = cdiv(ld, C), nslabs = cdiv(n, RS);
+  return (nslabs + nchunks) * static_cast<size_t>(n) * R * a;
+}
+
 template <typename T, int R>
-void launch_factored(const xm_problem* p, const T* Yt, T* out, hipStream_t s) {
+void launch_factored(const xm_problem* p, const T* Yt, T* out, hipStream_t s, Scratch* sc) {
   auto* mp = const_cast<xm_problem*>(p);
   const Factors<T> f = factors(p, static_cast<T*>(nullptr));
   const int32_t N = p->N, ng = N - 1;
   constexpr int RP = padded_row<T, R>();
   // scratch, in doubles: padded Yt (N rows of at most 24 values), W, V (ng x 8 each)
-  const size_t cap = 24 * static_cast<size_t>(N) + 16 * static_cast<size_t>(ng);
-  if (mp->fact_scratch.n < cap) {
-    XM_HIP(hipStreamSynchronize(s));
-    mp->fact_scratch.alloc(cap);
-  }
-  T* Ytp = reinterpret_cast<T*>(mp->fact_scratch.ptr);
-  T* W = reinterpret_cast<T*>(mp->fact_scratch.ptr + 24 * static_cast<size_t>(N));
+  double* base = take<double>(sc, mp->fact_scratch, factored_scratch_doubles(N), s);
+  T* Ytp = reinterpret_cast<T*>(base);
+  T* W = reinterpret_cast<T*>(base + 24 * static_cast<size_t>(N));
   T* Vv = W + static_cast<size_t>(ng) * R;
   const int64_t S = p->nnzb;
   xm_problem::TimedLaunch* ev =
       timed_launch(p, sizeof(T) == 8 ? XM_STATS_FACTORED : XM_STATS_FACTORED + 1,
-                   (0.5 * static_cast<double>(ng) * (ng + 1) + static_cast<double>(S) * 15.0) * sizeof(T));
+                   (0.5 * static_cast<double>(ng) * (ng + 1) + static_cast<double>(S) * 15.0) * sizeof(T), sc);
   if (ev) XM_HIP(hipEventRecord(ev->start, s));
   hipLaunchKernelGGL((pad_rows_kernel<T, R>), dim3(cdiv(static_cast<size_t>(N) * RP, kB)), dim3(kB), 0, s, Yt, N,
                      Ytp);
@@ -676,8 +678,8 @@ void launch_factored(const xm_problem* p, const T* Yt, T* out, hipStream_t s) {
                      Ytp, out, W);
   XM_LAUNCH_CHECK("fact_rows_kernel");
   xm_problem::TimedLaunch* evg = timed_launch(p, sizeof(T) == 8 ? XM_STATS_GINV : XM_STATS_GINV + 1,
-                                              0.5 * static_cast<double>(ng) * (ng + 1) * sizeof(T));
-  sym_product<T, T, T, R>(f.Gm, p->ldg, ng, W, Vv, mp->spmm_scratch, evg, s);
+                                              0.5 * static_cast<double>(ng) * (ng + 1) * sizeof(T), sc);
+  sym_product<T, T, T, R>(f.Gm, p->ldg, ng, W, Vv, mp->spmm_scratch, sc, evg, s);
   hipLaunchKernelGGL((fact_cols_kernel<T, R>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr, f.fac,
                      Vv, out);
   XM_LAUNCH_CHECK("fact_cols_kernel");
@@ -685,16 +687,16 @@ void launch_factored(const xm_problem* p, const T* Yt, T* out, hipStream_t s) {
 }
 
 template <typename T>
-void dispatch_factored(const xm_problem* p, const T* Yt, int r, T* out, hipStream_t s) {
+void dispatch_factored(const xm_problem* p, const T* Yt, int r, T* out, hipStream_t s, Scratch* sc) {
   switch (r) {
-    case 1: launch_factored<T, 1>(p, Yt, out, s); return;
-    case 2: launch_factored<T, 2>(p, Yt, out, s); return;
-    case 3: launch_factored<T, 3>(p, Yt, out, s); return;
-    case 4: launch_factored<T, 4>(p, Yt, out, s); return;
-    case 5: launch_factored<T, 5>(p, Yt, out, s); return;
-    case 6: launch_factored<T, 6>(p, Yt, out, s); return;
-    case 7: launch_factored<T, 7>(p, Yt, out, s); return;
-    case 8: launch_factored<T, 8>(p, Yt, out, s); return;
+    case 1: launch_factored<T, 1>(p, Yt, out, s, sc); return;
+    case 2: launch_factored<T, 2>(p, Yt, out, s, sc); return;
+    case 3: launch_factored<T, 3>(p, Yt, out, s, sc); return;
+    case 4: launch_factored<T, 4>(p, Yt, out, s, sc); return;
+    case 5: launch_factored<T, 5>(p, Yt, out, s, sc); return;
+    case 6: launch_factored<T, 6>(p, Yt, out, s, sc); return;
+    case 7: launch_factored<T, 7>(p, Yt, out, s, sc); return;
+    case 8: launch_factored<T, 8>(p, Yt, out, s, sc); return;
     default: throw Error(XM_EINVAL, "rank must be in [1, 8]");
   }
 }
@@ -711,29 +713,30 @@ __global__ void permute_frames_kernel(const T* __restrict__ in, const int32_t* _
 }
 
 template <typename TQ, typename TV, typename TA>
-void dispatch_r_ordered(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, hipStream_t s, int role) {
+void dispatch_r_ordered(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, hipStream_t s, int role,
+                        Scratch* sc) {
   if (p->spmm_kind[role][QVec<TQ>::dtype] == XM_SPMM_UPPER) {
     switch (r) {
-      case 1: launch_sym<TQ, TV, TA, 1>(p, Q, Yt, out, s); return;
-      case 2: launch_sym<TQ, TV, TA, 2>(p, Q, Yt, out, s); return;
-      case 3: launch_sym<TQ, TV, TA, 3>(p, Q, Yt, out, s); return;
-      case 4: launch_sym<TQ, TV, TA, 4>(p, Q, Yt, out, s); return;
-      case 5: launch_sym<TQ, TV, TA, 5>(p, Q, Yt, out, s); return;
-      case 6: launch_sym<TQ, TV, TA, 6>(p, Q, Yt, out, s); return;
-      case 7: launch_sym<TQ, TV, TA, 7>(p, Q, Yt, out, s); return;
-      case 8: launch_sym<TQ, TV, TA, 8>(p, Q, Yt, out, s); return;
+      case 1: launch_sym<TQ, TV, TA, 1>(p, Q, Yt, out, s, sc); return;
+      case 2: launch_sym<TQ, TV, TA, 2>(p, Q, Yt, out, s, sc); return;
+      case 3: launch_sym<TQ, TV, TA, 3>(p, Q, Yt, out, s, sc); return;
+      case 4: launch_sym<TQ, TV, TA, 4>(p, Q, Yt, out, s, sc); return;
+      case 5: launch_sym<TQ, TV, TA, 5>(p, Q, Yt, out, s, sc); return;
+      case 6: launch_sym<TQ, TV, TA, 6>(p, Q, Yt, out, s, sc); return;
+      case 7: launch_sym<TQ, TV, TA, 7>(p, Q, Yt, out, s, sc); return;
+      case 8: launch_sym<TQ, TV, TA, 8>(p, Q, Yt, out, s, sc); return;
       default: throw Error(XM_EINVAL, "rank must be in [1, 8]");
     }
   }
   switch (r) {
-    case 1: launch<TQ, TV, TA, 1>(p, Q, Yt, out, s); break;
-    case 2: launch<TQ, TV, TA, 2>(p, Q, Yt, out, s); break;
-    case 3: launch<TQ, TV, TA, 3>(p, Q, Yt, out, s); break;
-    case 4: launch<TQ, TV, TA, 4>(p, Q, Yt, out, s); break;
-    case 5: launch<TQ, TV, TA, 5>(p, Q, Yt, out, s); break;
-    case 6: launch<TQ, TV, TA, 6>(p, Q, Yt, out, s); break;
-    case 7: launch<TQ, TV, TA, 7>(p, Q, Yt, out, s); break;
-    case 8: launch<TQ, TV, TA, 8>(p, Q, Yt, out, s); break;
+    case 1: launch<TQ, TV, TA, 1>(p, Q, Yt, out, s, sc); break;
+    case 2: launch<TQ, TV, TA, 2>(p, Q, Yt, out, s, sc); break;
+    case 3: launch<TQ, TV, TA, 3>(p, Q, Yt, out, s, sc); break;
+    case 4: launch<TQ, TV, TA, 4>(p, Q, Yt, out, s, sc); break;
+    case 5: launch<TQ, TV, TA, 5>(p, Q, Yt, out, s, sc); break;
+    case 6: launch<TQ, TV, TA, 6>(p, Q, Yt, out, s, sc); break;
+    case 7: launch<TQ, TV, TA, 7>(p, Q, Yt, out, s, sc); break;
+    case 8: launch<TQ, TV, TA, 8>(p, Q, Yt, out, s, sc); break;
     default: throw Error(XM_EINVAL, "rank must be in [1, 8]");
   }
 }
@@ -741,22 +744,18 @@ void dispatch_r_ordered(const xm_problem* p, const TQ* Q, const TV* Yt, int r, T
 // The stored Q is in the frame order (that of the assembly): Yt goes into that
 // order, the product is taken there, and its rows come back to frame order.
 template <typename TQ, typename TV, typename TA>
-void dispatch_r(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, hipStream_t s, int role) {
+void dispatch_r(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, hipStream_t s, int role,
+                Scratch* sc) {
   require(r >= 1 && r <= 8, XM_EINVAL, "rank must be in [1, 8]");
   auto* mp = const_cast<xm_problem*>(p);
   const int32_t N = p->N;
   const int w = 3 * r;
   const size_t n = static_cast<size_t>(N) * w;
-  const size_t cap = 48 * static_cast<size_t>(N);  // doubles: two [N][3r] arrays, r <= 8, values <= 8 bytes
-  if (mp->perm_scratch.n < cap) {
-    XM_HIP(hipStreamSynchronize(s));
-    mp->perm_scratch.alloc(cap);
-  }
-  TV* Yp = reinterpret_cast<TV*>(mp->perm_scratch.ptr);
+  TV* Yp = take<TV>(sc, mp->perm_scratch, 2 * n, s);  // two [N][3r] arrays
   TV* Op = Yp + n;
   hipLaunchKernelGGL((permute_frames_kernel<TV>), dim3(cdiv(n, kB)), dim3(kB), 0, s, Yt, p->order.ptr, N, w, Yp);
   XM_LAUNCH_CHECK("permute_frames_kernel");
-  dispatch_r_ordered<TQ, TV, TA>(p, Q, Yp, r, Op, s, role);
+  dispatch_r_ordered<TQ, TV, TA>(p, Q, Yp, r, Op, s, role, sc);
   hipLaunchKernelGGL((permute_frames_kernel<TV>), dim3(cdiv(n, kB)), dim3(kB), 0, s, Op, p->pos.ptr, N, w, out);
   XM_LAUNCH_CHECK("permute_frames_kernel");
 }
@@ -764,35 +763,77 @@ void dispatch_r(const xm_problem* p, const TQ* Q, const TV* Yt, int r, TV* out, 
 }  // namespace
 
 template <>
+void spmm_yt<float>(const xm_problem* p, xm_dtype qtype, const float* Yt, int r, float* out, hipStream_t s,
+                    int role, Scratch* sc);
+
+template <>
 void spmm_yt<double>(const xm_problem* p, xm_dtype qtype, const double* Yt, int r, double* out, hipStream_t s,
-                     int role) {
-  require(qtype == XM_F64, XM_EINVAL, "FP64 vectors are multiplied with the FP64 Q");
+                     int role, Scratch* sc) {
   require(role == XM_ROLE_RESIDUAL || role == XM_ROLE_CURVATURE, XM_EINVAL, "unknown product role");
+  if (qtype != XM_F64) {
+    // FP64 vectors with a reduced-precision Q (the truncated-CG products of the
+    // FP64 stage of a reduced-precision solve): rounded to FP32, multiplied
+    // with FP32 accumulation, widened back
+    require(r >= 1 && r <= 8, XM_EINVAL, "rank must be in [1, 8]");
+    auto* mp = const_cast<xm_problem*>(p);
+    const size_t n = static_cast<size_t>(p->n3) * r;
+    float* a = take<float>(sc, mp->mixed_scratch, 2 * n, s);
+    float* b = a + n;
+    transpose_rows<double, float>(Yt, 1, static_cast<int>(n), a, s);
+    spmm_yt<float>(p, qtype, a, r, b, s, role, sc);
+    transpose_rows<float, double>(b, 1, static_cast<int>(n), out, s);
+    return;
+  }
   if (p->spmm_kind[role][XM_F64] == XM_SPMM_FACTORED) {
-    dispatch_factored<double>(p, Yt, r, out, s);
+    dispatch_factored<double>(p, Yt, r, out, s, sc);
     return;
   }
   require(p->Q64.ptr != nullptr, XM_EINVAL, "the dense FP64 Q was not kept");
-  dispatch_r<double, double, double>(p, p->Q64.ptr, Yt, r, out, s, role);
+  dispatch_r<double, double, double>(p, p->Q64.ptr, Yt, r, out, s, role, sc);
 }
 
 template <>
 void spmm_yt<float>(const xm_problem* p, xm_dtype qtype, const float* Yt, int r, float* out, hipStream_t s,
-                    int role) {
+                    int role, Scratch* sc) {
   require(role == XM_ROLE_RESIDUAL || role == XM_ROLE_CURVATURE, XM_EINVAL, "unknown product role");
   if (qtype == XM_F32 && p->spmm_kind[role][XM_F32] == XM_SPMM_FACTORED) {
-    dispatch_factored<float>(p, Yt, r, out, s);
+    dispatch_factored<float>(p, Yt, r, out, s, sc);
     return;
   }
   if (qtype == XM_F32) {
     require(p->Q32.ptr != nullptr, XM_EINVAL, "the FP32 copy of Q was not kept (XM_KEEP_F32)");
-    dispatch_r<float, float, float>(p, p->Q32.ptr, Yt, r, out, s, role);
+    dispatch_r<float, float, float>(p, p->Q32.ptr, Yt, r, out, s, role, sc);
   } else if (qtype == XM_BF16) {
     require(p->Q16.ptr != nullptr, XM_EINVAL, "the BF16 copy of Q was not kept (XM_KEEP_BF16)");
-    dispatch_r<uint16_t, float, float>(p, p->Q16.ptr, Yt, r, out, s, role);
+    dispatch_r<uint16_t, float, float>(p, p->Q16.ptr, Yt, r, out, s, role, sc);
   } else {
     throw Error(XM_EINVAL, "FP32 vectors are multiplied with the FP32 or BF16 Q");
   }
+}
+
+size_t product_scratch_bytes(const xm_problem* p, xm_dtype qtype, int r, int role, bool fp64_vectors) {
+  require(r >= 1 && r <= 8, XM_EINVAL, "rank must be in [1, 8]");
+  require(role == XM_ROLE_RESIDUAL || role == XM_ROLE_CURVATURE, XM_EINVAL, "unknown product role");
+  require(qtype == XM_F64 || qtype == XM_F32 || qtype == XM_BF16, XM_EINVAL, "unknown dtype");
+  constexpr size_t kAlign = 256;  // worst-case padding of one take()
+  size_t total = 0;
+  if (fp64_vectors && qtype != XM_F64) total += 2 * static_cast<size_t>(p->n3) * r * sizeof(float) + kAlign;
+  const int kind = p->spmm_kind[role][qtype];
+  const size_t vb = (qtype == XM_F64) ? 8 : 4;  // vector and accumulator size
+  if (kind == XM_SPMM_FACTORED && qtype != XM_BF16) {
+    total += factored_scratch_doubles(p->N) * sizeof(double) + kAlign;
+    total += sym_scratch_bytes(p->N - 1, p->ldg, qtype == XM_F64 ? 2 : 4, vb, r) + kAlign;
+    return total;
+  }
+  total += 2 * static_cast<size_t>(p->N) * 3 * r * vb + kAlign;
+  const int V = (qtype == XM_F64) ? 2 : (qtype == XM_F32 ? 4 : 8);
+  if (kind == XM_SPMM_UPPER) {
+    total += sym_scratch_bytes(p->n3, p->ld, V, vb, r) + kAlign;
+  } else {
+    const Split sp = choose_split(p->n3, p->ld, V);
+    total += static_cast<size_t>(sp.splits) * p->n3 * r * vb + kAlign;
+  }
+  return total;
 }
 
 template <typename Ts, typename Td>

@@ -66,12 +66,35 @@ def test_adjoint_matches_oracle_small():
 
 
 def test_recover_tp_matches_oracle():
+    # eq. tpstar at the rounded optimum: noise-free (ground truth) and noisy
+    # (the oracle's recovery at the same rotations and scales)
     _say("case: recover t, p")
     sc = scenes.random_scene(15, 300, L=4, sigma=0.0, seed=42, weights=(0.5, 1.5))
     P, R, s, _ = _gpu_solution(sc, sc.u, sc.w)
     t, p = P.recover_tp(R, s)
     assert np.abs(t.cpu().numpy() - sc.gt["t"]).max() <= 1e-7
     assert np.abs(p.cpu().numpy() - sc.gt["p"]).max() <= 1e-7
+    sc = scenes.random_scene(40, 1500, L=4, sigma=0.05, seed=44, weights=(0.5, 1.5))
+    P, R, s, _ = _gpu_solution(sc, sc.u, sc.w)
+    t, p = P.recover_tp(R, s)
+    U = ord_.rounded_U(R.cpu().numpy(), s.cpu().numpy())
+    t_o, p_o = odm.recover_tp(sc.N, sc.M, sc.frame, sc.landmark, sc.u, sc.w, U)
+    assert np.abs(t.cpu().numpy() - t_o).max() <= 1e-9 * np.abs(t_o).max()
+    assert np.abs(p.cpu().numpy() - p_o).max() <= 1e-9 * np.abs(p_o).max()
+
+
+def test_autograd_refuses_a_non_tight_optimum():
+    # the benchmark scene (5% outlier observations): certified, but its optimum
+    # has rank 4 and rounding loses eta ~ 0.08, so the implicit-function
+    # gradient of the rotations is undefined: forward must refuse
+    _say("case: XMSolve on the N=10155 outlier workload (rank-4 optimum)")
+    xm = _xm()
+    sc = scenes.make_scene("large", 0)
+    u = torch.from_numpy(sc.u).cuda().requires_grad_(True)
+    w = torch.from_numpy(sc.w).cuda().requires_grad_(True)
+    with pytest.raises(xm.NotTightError, match="eta"):
+        xm.XMSolve.apply(u, w, torch.from_numpy(sc.frame).cuda(), torch.from_numpy(sc.landmark).cuda(),
+                         sc.N, sc.M, xm.SolveOptions(compute="f32"))
 
 
 def test_autograd_function_backward():
