@@ -177,6 +177,31 @@ xm_status xm_spmm(xm_problem* p, xm_dtype dtype, const double* Y, int32_t r, dou
                   void* stream);
 
 /*
+ * The product of xm_spmm for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, kernels and result (bitwise) as xm_spmm, with
+ * every temporary taken from a fixed device array of the library
+ * (XM_NOALLOC_SCRATCH_MIB MiB per GPU, held from the library's first use on
+ * that GPU until the process ends) instead of the handle's buffers.  It calls
+ * no hipMalloc / hipFree and does not synchronise: the work is enqueued on
+ * `stream` and `out` is ready when the stream reaches that point.  Every call
+ * on one GPU uses the same array, so calls that may overlap on a GPU (other
+ * streams, other threads) race and must be serialised by the caller.  The
+ * handle's kernel choice for residual products of `dtype` applies
+ * (xm_set_product_kind).  Errors: XM_EINVAL for a NULL argument, r outside
+ * [1, 8], an unknown dtype, a precision the handle did not keep, or a product
+ * whose temporaries exceed the array (xm_spmm_noalloc_bytes tells the need);
+ * nothing is enqueued then.  HIP event timing (xm_spmm_timing) does not see
+ * these products.
+ */
+#define XM_NOALLOC_SCRATCH_MIB 128
+xm_status xm_spmm_noalloc(xm_problem* p, xm_dtype dtype, const double* Y, int32_t r, double* out,
+                          void* stream);
+/* Bytes of the fixed array that xm_spmm_noalloc(p, dtype, ., r, ...) needs
+ * (host output `bytes`); XM_EINVAL for bad arguments. */
+xm_status xm_spmm_noalloc_bytes(const xm_problem* p, xm_dtype dtype, int32_t r, int64_t* bytes);
+
+/*
  * Which kernel computes the Y Q product for the stored Q of precision `dtype`
  * (every product on the handle: solver, certificate, xm_spmm).  Q is
  * symmetric, so the product can be formed from the upper triangle alone:

@@ -19,6 +19,7 @@ _LIB = None
 XM_OK, XM_EINVAL, XM_ENOMEM, XM_EHIP, XM_EGRAPH, XM_ENOCONV = 0, -1, -2, -3, -4, -5
 XM_F64, XM_F32, XM_BF16 = 0, 1, 2
 XM_KEEP_F32, XM_KEEP_BF16 = 1 << 1, 1 << 2
+XM_NOALLOC_SCRATCH_BYTES = 128 << 20   # XM_NOALLOC_SCRATCH_MIB in include/xm.h
 _DT = {"f64": XM_F64, "f32": XM_F32, "bf16": XM_BF16}
 _STATUS = {XM_EINVAL: "XM_EINVAL", XM_ENOMEM: "XM_ENOMEM", XM_EHIP: "XM_EHIP", XM_EGRAPH: "XM_EGRAPH",
            XM_ENOCONV: "XM_ENOCONV"}
@@ -129,6 +130,10 @@ def load_library() -> ctypes.CDLL:
     lib.xm_memory_info.restype = ctypes.c_int
     lib.xm_memory_trim.argtypes = []
     lib.xm_memory_trim.restype = ctypes.c_int64
+    lib.xm_spmm_noalloc.argtypes = [P, ctypes.c_int, V, I32, V, V]
+    lib.xm_spmm_noalloc.restype = ctypes.c_int
+    lib.xm_spmm_noalloc_bytes.argtypes = [P, ctypes.c_int, I32, ctypes.POINTER(ctypes.c_int64)]
+    lib.xm_spmm_noalloc_bytes.restype = ctypes.c_int
     lib.xm_last_error.argtypes = []
     lib.xm_last_error.restype = ctypes.c_char_p
     _LIB = lib
@@ -218,6 +223,23 @@ class Problem:
         out = torch.empty_like(Y)
         _check(load_library().xm_spmm(self._h, _DT[dtype], _ptr(Y), Y.shape[0], _ptr(out), _stream()))
         return out
+
+    def spmm_noalloc(self, Y: torch.Tensor, out: torch.Tensor, dtype: str = "f64") -> torch.Tensor:
+        """xm_spmm_noalloc: Y Q into the caller's `out` (same shape as Y), enqueued
+        on the current stream with temporaries from the library's fixed scratch."""
+        Y = _dev_tensor(Y, torch.float64, "Y")
+        if not out.is_contiguous():
+            raise ValueError("out must be contiguous")
+        out = _dev_tensor(out, torch.float64, "out")
+        if out.shape != Y.shape:
+            raise ValueError("out must have the shape of Y")
+        _check(load_library().xm_spmm_noalloc(self._h, _DT[dtype], _ptr(Y), Y.shape[0], _ptr(out), _stream()))
+        return out
+
+    def spmm_noalloc_bytes(self, r: int, dtype: str = "f64") -> int:
+        n = ctypes.c_int64(0)
+        _check(load_library().xm_spmm_noalloc_bytes(self._h, _DT[dtype], r, ctypes.byref(n)))
+        return n.value
 
     def build_stats(self) -> dict:
         """Device time and algorithmic bytes / flops of the main assembly kernels."""

@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "libxm.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["sort.hip", "build_q.hip", "spmm.hip", "manifold.hip", "certify.hip", "solver.hip",
-           "round.hip", "adjoint.hip", "pool.cpp", "api.cpp"]
+           "round.hip", "adjoint.hip", "noalloc.hip", "pool.cpp", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

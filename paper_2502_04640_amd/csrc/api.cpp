@@ -135,6 +135,69 @@ xm_status xm_spmm(xm_problem* p, xm_dtype dtype, const double* Y, int32_t r, dou
   XM_API_CATCH
 }
 
+}  // extern "C"
+
+namespace {
+// temporaries of xm_spmm_noalloc: Y and the product in the kernels' layout,
+// then those of the product itself
+size_t noalloc_need(const xm_problem* p, xm_dtype dtype, int r) {
+  const size_t vb = (dtype == XM_F64) ? sizeof(double) : sizeof(float);
+  return 2 * (static_cast<size_t>(p->n3) * r * vb + 256) +
+         xm::product_scratch_bytes(p, dtype, r, XM_ROLE_RESIDUAL, false);
+}
+
+template <typename T>
+void noalloc_product(xm_problem* p, xm_dtype dtype, const double* Y, int r, double* out, hipStream_t s) {
+  xm::Scratch sc{xm::noalloc_scratch_base(), xm::kNoallocScratchBytes, 0};
+  xm::DevBuf<T> unused;  // the fixed region serves every take(): never allocated
+  const int n = p->n3;
+  T* Yt = xm::take<T>(&sc, unused, static_cast<size_t>(n) * r, s);
+  T* G = xm::take<T>(&sc, unused, static_cast<size_t>(n) * r, s);
+  xm::transpose_rows<double, T>(Y, r, n, Yt, s);
+  xm::spmm_yt<T>(p, dtype, Yt, r, G, s, XM_ROLE_RESIDUAL, &sc);
+  xm::transpose_rows<T, double>(G, n, r, out, s);
+}
+}  // namespace
+
+extern "C" {
+
+xm_status xm_spmm_noalloc_bytes(const xm_problem* p, xm_dtype dtype, int32_t r, int64_t* bytes) {
+  XM_API_TRY
+  if (!p || !bytes) return fail(XM_EINVAL, "NULL argument");
+  if (r < 1 || r > 8) return fail(XM_EINVAL, "r must be in [1, 8]");
+  if (dtype != XM_F64 && dtype != XM_F32 && dtype != XM_BF16) return fail(XM_EINVAL, "unknown dtype");
+  *bytes = static_cast<int64_t>(noalloc_need(p, dtype, r));
+  return XM_OK;
+  XM_API_CATCH
+}
+
+xm_status xm_spmm_noalloc(xm_problem* p, xm_dtype dtype, const double* Y, int32_t r, double* out,
+                          void* stream) {
+  XM_API_TRY
+  if (!p || !Y || !out) return fail(XM_EINVAL, "NULL argument");
+  if (r < 1 || r > 8) return fail(XM_EINVAL, "r must be in [1, 8]");
+  if (dtype != XM_F64 && dtype != XM_F32 && dtype != XM_BF16) return fail(XM_EINVAL, "unknown dtype");
+  const int kind = p->spmm_kind[XM_ROLE_RESIDUAL][dtype];
+  if (dtype == XM_F64 && kind != XM_SPMM_FACTORED && !p->Q64.ptr) return fail(XM_EINVAL, "the dense FP64 Q was not kept");
+  if (dtype == XM_F32 && kind != XM_SPMM_FACTORED && !p->Q32.ptr)
+    return fail(XM_EINVAL, "the FP32 copy of Q was not kept (XM_KEEP_F32)");
+  if (dtype == XM_F32 && kind == XM_SPMM_FACTORED && !p->fac32.ptr)
+    return fail(XM_EINVAL, "the FP32 factors were not kept (XM_KEEP_F32)");
+  if (dtype == XM_BF16 && !p->Q16.ptr) return fail(XM_EINVAL, "the BF16 copy of Q was not kept (XM_KEEP_BF16)");
+  const size_t need = noalloc_need(p, dtype, r);
+  if (need > xm::kNoallocScratchBytes) {
+    char msg[200];
+    std::snprintf(msg, sizeof(msg), "xm_spmm_noalloc: this product needs %zu bytes of scratch, the fixed array holds %zu",
+                  need, xm::kNoallocScratchBytes);
+    return fail(XM_EINVAL, msg);
+  }
+  hipStream_t s = as_stream(stream);
+  if (dtype == XM_F64) noalloc_product<double>(p, dtype, Y, r, out, s);
+  else noalloc_product<float>(p, dtype, Y, r, out, s);
+  return XM_OK;
+  XM_API_CATCH
+}
+
 void xm_default_opts(xm_solve_opts* o) {
   if (!o) return;
   *o = xm_solve_opts{};

@@ -128,6 +128,11 @@ void spmm_yt(const xm_problem* p, xm_dtype qtype, const T* Yt, int r, T* out, hi
 // (alignment included).
 size_t product_scratch_bytes(const xm_problem* p, xm_dtype qtype, int r, int role, bool fp64_vectors);
 
+// noalloc.hip: size and per-device address of the fixed scratch of
+// xm_spmm_noalloc (the address is looked up on the first call on a device)
+constexpr size_t kNoallocScratchBytes = static_cast<size_t>(XM_NOALLOC_SCRATCH_MIB) << 20;
+char* noalloc_scratch_base();
+
 // layout conversions between the ABI layout Y[r][3N] and the internal Yt[3N][r]
 template <typename Ts, typename Td>
 void transpose_rows(const Ts* in, int rows, int cols, Td* out, hipStream_t s);

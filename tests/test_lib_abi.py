@@ -115,3 +115,11 @@ def test_memory_pool_calls_without_gpu():
     assert lib.xm_memory_info(ctypes.byref(live), ctypes.byref(cached)) == 0
     assert live.value == 0 and cached.value == 0
     assert lib.xm_memory_info(None, None) == -1
+
+
+def test_noalloc_scratch_size_matches_header():
+    import re as _re
+    text = open(HEADER).read()
+    mib = int(_re.search(r"#define XM_NOALLOC_SCRATCH_MIB (\d+)", text).group(1))
+    from paper_2502_04640_amd import api
+    assert api.XM_NOALLOC_SCRATCH_BYTES == mib << 20
