@@ -105,13 +105,15 @@ def _distinct_choice(rng: np.random.Generator, cand: np.ndarray, L: np.ndarray) 
     return picked[mask]
 
 
-def _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=0.0, bbox=None, local=None):
+def _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=0.0, bbox=None, local=None, mask_out=None):
     """u = d_i (R_cfg[i] (x_k - c_i) + eps); a fraction of rows replaced by random points.
 
     Outlier points are uniform in ``bbox`` (lo, hi) when given, else uniform in
-    the cube of half-side ``local`` centred at the true landmark."""
+    the cube of half-side ``local`` centred at the true landmark.  ``mask_out``
+    (a list) receives the boolean outlier mask."""
     n = fr.shape[0]
     pts = x[lm]
+    bad = np.zeros(n, bool)
     if outlier_frac > 0.0:
         bad = rng.random(n) < outlier_frac
         pts = pts.copy()
@@ -123,6 +125,8 @@ def _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=0.0, bbox=None, local
     cam = np.einsum("nij,nj->ni", R_cfg[fr], pts - c[fr])
     if sigma > 0:
         cam = cam + sigma * rng.standard_normal((n, 3))
+    if mask_out is not None:
+        mask_out.append(bad)
     return d[fr][:, None] * cam
 
 
@@ -137,6 +141,8 @@ def _ground_truth(R_cfg, c, d, x) -> Dict[str, np.ndarray]:
 
 def _finish(name, N, M, fr, lm, u, w, gt) -> Scene:
     order = np.lexsort((fr, lm))
+    if "outlier" in gt:
+        gt["outlier"] = gt["outlier"][order]
     return Scene(N, M, fr[order].astype(np.int32), lm[order].astype(np.int32),
                  np.ascontiguousarray(u[order], dtype=np.float64),
                  np.ascontiguousarray(w[order], dtype=np.float64), gt, name)
@@ -173,12 +179,16 @@ def _distinct_uniform(rng: np.random.Generator, N: int, L: np.ndarray) -> np.nda
 # ---------------------------------------------------------------------------
 def random_scene(N: int, M: int, L: int = 4, sigma: float = 0.01, seed: int = 0,
                  depth=(0.5, 2.0), weights=None, center_box: float = 5.0,
-                 ball: float = 3.0, name: str = "random") -> Scene:
+                 ball: float = 3.0, name: str = "random", outlier: float = 0.0,
+                 outlier_local: float = 0.0) -> Scene:
     """Tiny-scene recipe: Haar rotations, centres U[-b,b]^3, landmarks uniform in a
     ball, each landmark seen by L distinct frames chosen uniformly.
 
     ``weights``: None for w=1, or (lo, hi) for w~U[lo,hi].  L may be >= N only
-    if L == N (every frame sees every landmark)."""
+    if L == N (every frame sees every landmark).  ``outlier``: fraction of
+    observations whose 3D point is replaced by one uniform in the box of the
+    camera centres, or, with ``outlier_local`` > 0, in the cube of that
+    half-side around the true landmark (their mask is ``gt["outlier"]``)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     R_cfg = haar_rotations(rng, N)
     c = rng.uniform(-center_box, center_box, size=(N, 3))
@@ -189,9 +199,14 @@ def random_scene(N: int, M: int, L: int = 4, sigma: float = 0.01, seed: int = 0,
     L = min(L, N)
     fr = _distinct_uniform(rng, N, np.full(M, L))
     lm = np.repeat(np.arange(M), L)
-    u = _lift(rng, R_cfg, c, d, x, fr, lm, sigma)
+    bad = []
+    u = _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=outlier,
+              bbox=None if outlier_local > 0 else (-center_box, center_box),
+              local=outlier_local, mask_out=bad)
     w = np.ones(fr.shape[0]) if weights is None else rng.uniform(weights[0], weights[1], fr.shape[0])
-    return _finish(name, N, M, fr, lm, u, w, _ground_truth(R_cfg, c, d, x))
+    gt = _ground_truth(R_cfg, c, d, x)
+    gt["outlier"] = bad[0]
+    return _finish(name, N, M, fr, lm, u, w, gt)
 
 
 def _tiny(seed, sigma=0.01):
