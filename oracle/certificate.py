@@ -127,7 +127,7 @@ def _orth_basis(A, rel=1e-10):
     return Uo[:, sv > rel * sv[0]]
 
 
-def certificate_bound(Q, U, rel=1e-3):
+def certificate_bound(Q, U, rel=1e-3, D_from=None):
     """Lower bound on the whole spectrum of Zs = D^{-1/2} Z D^{-1/2} from the
     deflated block, valid at any U (not only at critical points).
 
@@ -142,10 +142,12 @@ def certificate_bound(Q, U, rel=1e-3):
     (a + b)/2 - sqrt(((a - b)/2)^2 + e^2).  Returns a, b, e (spectral norm),
     e_fro (Frobenius norm, an upper bound on e), the bound with each, the
     bound on v^T Z v for unit v it implies (d_min or d_max scaling, with the
-    Frobenius form), and the exact smallest eigenvalue of Zs (dense)."""
+    Frobenius form), and the exact smallest eigenvalue of Zs (dense).  Q here
+    is the matrix the multipliers are taken from (Q + grad F(X) with the scale
+    regulariser); D_from (default Q) gives the scaling blocks D."""
     Lam = dual_lambda(Q, U, mf.from_U(U)[1])
     Z = dual_matrix(Q, Lam)
-    Dh, Dm, dmin, dmax = block_sqrt(Q)
+    Dh, Dm, dmin, dmax = block_sqrt(Q if D_from is None else D_from)
     Dmh = _blkdiag(Dm)
     Zs = Dmh @ Z @ Dmh
     Zs = 0.5 * (Zs + Zs.T)
@@ -171,21 +173,41 @@ def certificate_bound(Q, U, rel=1e-3):
             "lambda_min_scaled_full": float(np.linalg.eigvalsh(Zs)[0]), "dmin": dmin, "dmax": dmax, "n": n}
 
 
-def certify(Q, R, s, tau):
+def reg_gradient(s, lam):
+    """Diagonal of grad F(X) for F = lam sum_{i>=2} (X_{3i,3i} - 1)^2
+    (eq. problem-sdp-scale): 2 lam (X_{3k+2,3k+2} - 1) = 2 lam (s_k^2 - 1) at
+    index 3k+2 for frames k >= 1 (0-based; the paper's index 3i), 0 elsewhere."""
+    N = s.shape[0]
+    g = np.zeros(3 * N)
+    g[3 * np.arange(1, N) + 2] = 2.0 * lam * (s[1:] ** 2 - 1.0)
+    return g
+
+
+def certify(Q, R, s, tau, lam=0.0):
     """Certificate at (R, s): dict with lambda_min (complement), lambda_min_full,
-    primal tr(Q U^T U), dual tr(Lambda_0), certified flag and escape vector."""
+    primal, dual, certified flag and escape vector.
+
+    With the scale regulariser (lam > 0, App. "Scale Regularization") the dual
+    matrix is Z = Q + grad F(X) - blkdiag(Lambda) at X = U^T U, the multipliers
+    come from the same stationarity condition with Q + grad F(X) in place of Q,
+    the primal value is tr(Q X) + F(X) and the dual value
+    tr(Lambda_0) + F(X) - <grad F(X), X>."""
     U = mf.to_U(R, s)
-    Lam = dual_lambda(Q, U, s)
-    Z = dual_matrix(Q, Lam)
-    lam, v, full = min_eig(Z, U)
+    g = reg_gradient(s, lam)
+    Qe = Q + np.diag(g)
+    Lam = dual_lambda(Qe, U, s)
+    Z = dual_matrix(Qe, Lam)
+    lam_c, v, full = min_eig(Z, U)
     lam_s, bound, dmin, dmax = min_eig_scaled(Q, Z, U)
-    cb = certificate_bound(Q, U)
+    cb = certificate_bound(Qe, U, D_from=Q)
     N = R.shape[0]
     qbar = float(np.trace(Q)) / (3 * N)
-    primal = float(np.sum(U * (U @ Q)))
-    dual = float(np.trace(Lam[0]))
-    return {"lambda_min": lam, "lambda_min_full": full, "v": v, "primal": primal,
-            "dual": dual, "certified": bool(lam >= -tau * qbar), "qbar": qbar, "Lambda": Lam,
+    X_diag = np.repeat(s * s, 3)
+    F = mf.scale_reg(s, lam)
+    primal = float(np.sum(U * (U @ Q))) + F
+    dual = float(np.trace(Lam[0])) + F - float(g @ X_diag)
+    return {"lambda_min": lam_c, "lambda_min_full": full, "v": v, "primal": primal,
+            "dual": dual, "certified": bool(lam_c >= -tau * qbar), "qbar": qbar, "Lambda": Lam,
             "lambda_min_scaled": lam_s, "lambda_bound": bound, "dmin": dmin, "dmax": dmax,
             "defl_min": cb["defl_min"], "defl_cross": cb["cross_fro"], "lambda_bound_full": cb["lambda_bound"],
             "stat_res": float(np.linalg.norm(Z @ U.T))}
@@ -194,6 +216,14 @@ def certify(Q, R, s, tau):
 def suboptimality(rho_hat, rho_sdp):
     """eta = (rho_hat - rho_sdp) / (1 + |rho_hat| + |rho_sdp|)   (eq. suboptimality)."""
     return (rho_hat - rho_sdp) / (1.0 + abs(rho_hat) + abs(rho_sdp))
+
+
+def suboptimality_dual(rho_hat, rho_dual, lambda_min, trace_X):
+    """eq. suboptimality_new (App. "Suboptimality for SDP"): the lower bound
+    lb = max(0, lambda_min(Z)) tr(X) + rho_dual on the SDP optimum replaces
+    rho_SDP, eta = (rho_hat - lb) / (1 + |rho_hat| + |lb|)."""
+    lb = max(0.0, lambda_min) * trace_X + rho_dual
+    return (rho_hat - lb) / (1.0 + abs(rho_hat) + abs(lb))
 
 
 # ---------------------------------------------------------------------------

@@ -22,6 +22,14 @@ the design notes):
 A point is (R [N, r, 3], s [N]); a tangent vector is (Rd [N, r, 3], sd [N])
 with sd[0] = 0.  U (the paper's flat r x 3N matrix) has column 3k+c equal to
 s_k R_k[:, c].
+
+Scale regularisation (App. "Scale Regularization", eq. problem-sdp-scale):
+the objective gains lam sum_{i>=2} (X_{3i,3i} - 1)^2.  On the manifold every
+diagonal block of X = U^T U is s_k^2 I, so the term is
+F(s) = lam sum_{k>=1} (s_k^2 - 1)^2, a function of the scales alone: its
+Euclidean derivative is dF/ds_k = 4 lam s_k (s_k^2 - 1) and its second
+derivative 4 lam (3 s_k^2 - 1).  Every function below takes `lam` (0: the
+plain problem).
 """
 from __future__ import annotations
 
@@ -44,10 +52,15 @@ def blocks(G, N):
     return G.reshape(r, N, 3).transpose(1, 0, 2)
 
 
-def cost(Q, R, s):
-    """f = tr(Q U^T U)."""
+def scale_reg(s, lam):
+    """F = lam sum_{k>=1} (s_k^2 - 1)^2."""
+    return lam * float(np.sum((s[1:] ** 2 - 1.0) ** 2))
+
+
+def cost(Q, R, s, lam=0.0):
+    """f = tr(Q U^T U) + F(s)."""
     U = to_U(R, s)
-    return float(np.sum(U * (U @ Q)))
+    return float(np.sum(U * (U @ Q))) + scale_reg(s, lam)
 
 
 def euclid_parts(Q, R, s):
@@ -65,16 +78,16 @@ def proj(R, Z):
     return Z - R @ sym(np.swapaxes(R, 1, 2) @ Z)
 
 
-def rgrad(Q, R, s):
+def rgrad(Q, R, s, lam=0.0):
     """Riemannian gradient (gR [N,r,3], gs [N]) with gs[0] = 0 (s_0 anchored)."""
     Gam, E, e = euclid_parts(Q, R, s)
     gR = proj(R, E)
-    gs = s * s * e
+    gs = s * s * (e + 4.0 * lam * s * (s * s - 1.0))
     gs[0] = 0.0
     return gR, gs
 
 
-def hess(Q, R, s, Rd, sd):
+def hess(Q, R, s, Rd, sd, lam=0.0):
     """Riemannian Hessian applied to the tangent vector (Rd, sd)."""
     N = R.shape[0]
     Gam, E, e = euclid_parts(Q, R, s)
@@ -84,6 +97,8 @@ def hess(Q, R, s, Rd, sd):
     ed = np.einsum("nab,nab->n", Rd, Gam) + np.einsum("nab,nab->n", R, Gd)
     HR = proj(R, Ed - Rd @ sym(np.swapaxes(R, 1, 2) @ E))
     Hs = s * s * ed + s * e * sd
+    # F(s): s^2 F'' sd + s F' sd
+    Hs = Hs + (s * s * 4.0 * lam * (3.0 * s * s - 1.0) + s * 4.0 * lam * s * (s * s - 1.0)) * sd
     Hs[0] = 0.0
     return HR, Hs
 

@@ -20,7 +20,7 @@ import numpy as np
 from . import manifold as mf
 
 
-def tcg(Q, R, s, gR, gs, Delta, kappa=0.1, theta=1.0, max_inner=None):
+def tcg(Q, R, s, gR, gs, Delta, kappa=0.1, theta=1.0, max_inner=None, lam=0.0):
     """Steihaug-Toint truncated CG on the trust-region subproblem.
 
     Returns (eta, Heta, reason, n_inner).  Inner products are the manifold
@@ -38,7 +38,7 @@ def tcg(Q, R, s, gR, gs, Delta, kappa=0.1, theta=1.0, max_inner=None):
     reason = "maxiter"
     j = 0
     for j in range(1, max_inner + 1):
-        Hd = mf.hess(Q, R, s, delta[0], delta[1])
+        Hd = mf.hess(Q, R, s, delta[0], delta[1], lam)
         d_Hd = ip(delta, Hd)
         alpha = r_r / d_Hd if d_Hd != 0 else np.inf
         e_Pe = ip(eta, eta)
@@ -65,15 +65,16 @@ def tcg(Q, R, s, gR, gs, Delta, kappa=0.1, theta=1.0, max_inner=None):
 
 
 def rtr(Q, R, s, grad_tol=1e-10, max_outer=500, max_inner=None, Delta_bar=None,
-        Delta0=None, rho_prime=0.1, log=None):
-    """Minimise tr(Q U^T U) from (R, s).  Returns (R, s, info)."""
+        Delta0=None, rho_prime=0.1, log=None, lam=0.0):
+    """Minimise tr(Q U^T U) (+ the scale regulariser lam sum_{k>=1} (s_k^2 - 1)^2)
+    from (R, s).  Returns (R, s, info)."""
     N = R.shape[0]
     qbar = float(np.trace(Q)) / (3 * N)
     if Delta_bar is None:
         Delta_bar = np.sqrt(3.0 * N)
     Delta = Delta_bar / 8.0 if Delta0 is None else Delta0
-    f = mf.cost(Q, R, s)
-    gR, gs = mf.rgrad(Q, R, s)
+    f = mf.cost(Q, R, s, lam)
+    gR, gs = mf.rgrad(Q, R, s, lam)
     gnorm = np.sqrt(mf.inner(s, gR, gs, gR, gs))
     total_inner = 0
     k = 0
@@ -81,10 +82,10 @@ def rtr(Q, R, s, grad_tol=1e-10, max_outer=500, max_inner=None, Delta_bar=None,
         Unorm = np.linalg.norm(mf.to_U(R, s))
         if gnorm <= grad_tol * qbar * Unorm:
             break
-        eta, Heta, reason, nin = tcg(Q, R, s, gR, gs, Delta, max_inner=max_inner)
+        eta, Heta, reason, nin = tcg(Q, R, s, gR, gs, Delta, max_inner=max_inner, lam=lam)
         total_inner += nin
         Rn, sn = mf.retract(R, s, eta[0], eta[1])
-        fn = mf.cost(Q, Rn, sn)
+        fn = mf.cost(Q, Rn, sn, lam)
         mdec = -(mf.inner(s, gR, gs, eta[0], eta[1]) + 0.5 * mf.inner(s, eta[0], eta[1], Heta[0], Heta[1]))
         reg = max(1.0, abs(f)) * np.finfo(float).eps * 1e3
         rho = (f - fn + reg) / (mdec + reg)
@@ -98,7 +99,7 @@ def rtr(Q, R, s, grad_tol=1e-10, max_outer=500, max_inner=None, Delta_bar=None,
             log.append((k, f, gnorm, Delta, rho, reason, nin))
         if finite and mdec > 0 and rho > rho_prime:
             R, s, f = Rn, sn, fn
-            gR, gs = mf.rgrad(Q, R, s)
+            gR, gs = mf.rgrad(Q, R, s, lam)
             gnorm = np.sqrt(mf.inner(s, gR, gs, gR, gs))
     info = {"cost": f, "grad_norm": gnorm, "outer": k, "inner": total_inner, "qbar": qbar}
     return R, s, info
