@@ -101,6 +101,23 @@ xm_status xm_build_Q(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame,
                      const void* w, xm_dtype w_dtype, uint32_t copies, void* stream,
                      xm_problem** out);
 
+/*
+ * xm_build_Q on the observations whose mask byte is nonzero (mask: device
+ * uint8 [n_obs], or NULL for all): the rebuild step of the XM^2 loop
+ * (Section "Structure from Motion with XM": after the first solve, the
+ * measurements with the largest residuals are deleted and the solver runs
+ * again).  Every input array keeps its full length n_obs; observations with
+ * mask 0 are validated but left out of Q.  Per-observation outputs of the
+ * handle (xm_residuals, xm_adjoint) keep the caller's full indexing and give 0
+ * for the left-out observations.  Errors as xm_build_Q, plus XM_EINVAL when the
+ * mask keeps nothing; XM_EGRAPH when what is kept leaves a frame without a
+ * shared landmark or the view graph disconnected.
+ */
+xm_status xm_build_Q_masked(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame,
+                            const int32_t* landmark, const void* u, xm_dtype u_dtype, const void* w,
+                            xm_dtype w_dtype, const uint8_t* mask, uint32_t copies, void* stream,
+                            xm_problem** out);
+
 /* Release a handle and all device memory it owns.  NULL is allowed.  The
  * memory goes back to the library's device pool (below), not to the runtime. */
 void xm_free(xm_problem* p);
@@ -126,14 +143,29 @@ int64_t xm_memory_trim(void);
 
 typedef struct {
   int32_t N, M;
-  int64_t n_obs;
+  int64_t n_obs;         /* observations in Q (those the mask kept) */
+  int64_t n_in;          /* observations passed in (the length of per-observation outputs) */
   int64_t nnz_blocks;    /* co-visibility blocks (frame pairs sharing a landmark, incl. diagonal) */
   int64_t n_pairs;       /* per-landmark observation pairs reduced into the blocks */
   int32_t ld;            /* leading dimension (elements) of the dense row-major Q copies */
   int32_t copies;        /* bitmask: 1 (FP64) | XM_KEEP_F32 | XM_KEEP_BF16 */
   double qbar;           /* tr(Q) / 3N, the scale used by the relative tolerances */
   double build_ms;       /* device time of the last xm_build_Q, milliseconds */
+  double scale_reg;      /* lambda of xm_set_scale_reg (0: the plain objective) */
 } xm_problem_info;
+
+/*
+ * Scale regularisation (App. "Scale Regularization", eq. problem-sdp-scale):
+ * the objective becomes tr(Q X) + lambda sum_{i>=2} (X_{3i,3i} - 1)^2, which
+ * keeps the scales of frames 2..N from collapsing toward 0 on data where the
+ * plain optimum shrinks them.  On the Burer-Monteiro manifold the term is
+ * lambda sum_{k>=1} (s_k^2 - 1)^2.  Applies to every later xm_bm_solve,
+ * xm_certify (Z = Q + grad F(X) - blkdiag(Lambda); primal tr(QX) + F(X); dual
+ * tr(Lambda_0) + F(X) - <grad F(X), X>) and xm_round (rho_hat includes F) on
+ * the handle.  xm_adjoint refuses a regularised handle (XM_EINVAL).  lambda
+ * must be finite and >= 0 (0 restores the plain objective).
+ */
+xm_status xm_set_scale_reg(xm_problem* p, double lambda);
 
 /* Fill `info` (host) for a handle. */
 xm_status xm_get_info(const xm_problem* p, xm_problem_info* info);
@@ -392,6 +424,52 @@ xm_status xm_round(xm_problem* p, const double* Y, int32_t r, double* R_out, dou
  */
 xm_status xm_recover_tp(xm_problem* p, const double* R, const double* s, double* t, double* pts,
                         void* stream);
+
+/*
+ * Similarity alignment of an estimate to a reference, the registration App.
+ * "Metrics" applies to camera positions before trajectory errors (there a
+ * robust registration; here its least-squares form, the correspondence being
+ * known): s > 0, R in SO(3), t minimising sum_i w_i |s R P_i + t - Q_i|^2, in
+ * closed form (R the rotation closest to the weighted cross-covariance of the
+ * centred points, s = tr(R^T C) / the weighted spread of P, t from the means).
+ * Used with the camera positions t of xm_recover_tp it gives the anchored
+ * gauge's similarity to a ground truth.
+ * n  number of points (>= 1);  P, Q device [n][3] FP64 (row i: point i);
+ * w  device [n] FP64 weights >= 0, or NULL for all 1.
+ * out host [14]: s, R (row-major, 9), t (3), and the weighted RMS residual
+ *    sqrt(sum_i w_i |s R P_i + t - Q_i|^2 / sum_i w_i).
+ * Errors: XM_EINVAL for n < 1, NULL P / Q / out, a negative or non-finite
+ * weight or point, a zero weight sum, or points P with no spread.  One
+ * workgroup, fixed-order sums (bitwise reproducible).  Synchronises `stream`.
+ */
+xm_status xm_align_similarity(int64_t n, const double* P, const double* Q, const double* w, double* out,
+                              void* stream);
+
+/*
+ * Residuals of eq. sba at anchored scaled rotations (R, s) (as from
+ * xm_round), with the translations and landmarks of eq. tpstar:
+ * e_o = s_i R_i u_o + t_i - p_k for every observation o = (i, k), and the
+ * score that ranks them for the XM^2 deletion: |e_o| (frame_units = 0) or
+ * |e_o| / s_i (frame_units = 1: the residual in the units of frame i's lifted
+ * keypoints, which does not favour deleting the anchored frame's
+ * observations when the optimum shrinks the other frames' scales).
+ * R device [N][3][3], s device [N]; e device [n_in][3] or NULL; score device
+ * [n_in] or NULL (not both NULL); caller's observation order, 0 for
+ * observations a masked build left out.  Synchronises `stream`.
+ */
+xm_status xm_residuals(xm_problem* p, const double* R, const double* s, int32_t frame_units, double* e,
+                       double* score, void* stream);
+
+/*
+ * The XM^2 deletion: keep[o] = 0 for the floor(frac * n) observations with the
+ * largest score, 1 for the others (ties: the lower index is deleted first).
+ * score device [n] (finite, >= 0), keep device uint8 [n]; *n_dropped (host,
+ * may be NULL) receives the number deleted.  Deterministic (stable radix sort
+ * of the 64-bit score keys).  XM_EINVAL for frac outside [0, 1], n outside
+ * [1, 2^31) or a negative / non-finite score.  Synchronises `stream`.
+ */
+xm_status xm_drop_largest(const double* score, int64_t n, double frac, uint8_t* keep, int64_t* n_dropped,
+                          void* stream);
 
 typedef struct {
   int32_t cg_iters;    /* CG iterations of the Hessian solve */

@@ -6,8 +6,8 @@ package only marshals torch device tensors and the current HIP stream into it.
 Importing the package does not touch the GPU; the first call that needs the
 library loads it and raises if it is missing (there is no CPU fallback).
 """
-from .api import (XMError, NotTightError, Problem, SolveOptions, XMSolve, build_Q, load_library,  # noqa: F401
-                  library_path, memory_info, memory_trim)
+from .api import (XMError, NotTightError, Problem, SolveOptions, XMSolve, align_similarity, build_Q,  # noqa: F401
+                  drop_largest, library_path, load_library, memory_info, memory_trim, xm2)
 
-__all__ = ["XMError", "NotTightError", "Problem", "SolveOptions", "XMSolve", "build_Q", "load_library",
-           "library_path", "memory_info", "memory_trim"]
+__all__ = ["XMError", "NotTightError", "Problem", "SolveOptions", "XMSolve", "align_similarity", "build_Q",
+           "drop_largest", "library_path", "load_library", "memory_info", "memory_trim", "xm2"]

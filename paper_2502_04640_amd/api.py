@@ -32,9 +32,10 @@ class XMError(RuntimeError):
 
 
 class _ProblemInfo(ctypes.Structure):
-    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("n_obs", ctypes.c_int64),
+    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("n_obs", ctypes.c_int64), ("n_in", ctypes.c_int64),
                 ("nnz_blocks", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("ld", ctypes.c_int32),
-                ("copies", ctypes.c_int32), ("qbar", ctypes.c_double), ("build_ms", ctypes.c_double)]
+                ("copies", ctypes.c_int32), ("qbar", ctypes.c_double), ("build_ms", ctypes.c_double),
+                ("scale_reg", ctypes.c_double)]
 
 
 class _SolveOpts(ctypes.Structure):
@@ -94,6 +95,17 @@ def load_library() -> ctypes.CDLL:
     lib.xm_build_Q.argtypes = [I32, I32, I64, V, V, V, ctypes.c_int, V, ctypes.c_int, U32, V,
                                ctypes.POINTER(ctypes.c_void_p)]
     lib.xm_build_Q.restype = ctypes.c_int
+    lib.xm_build_Q_masked.argtypes = [I32, I32, I64, V, V, V, ctypes.c_int, V, ctypes.c_int, V, U32, V,
+                                      ctypes.POINTER(ctypes.c_void_p)]
+    lib.xm_build_Q_masked.restype = ctypes.c_int
+    lib.xm_set_scale_reg.argtypes = [P, D]
+    lib.xm_set_scale_reg.restype = ctypes.c_int
+    lib.xm_residuals.argtypes = [P, V, V, I32, V, V, V]
+    lib.xm_residuals.restype = ctypes.c_int
+    lib.xm_drop_largest.argtypes = [V, I64, D, V, ctypes.POINTER(ctypes.c_int64), V]
+    lib.xm_drop_largest.restype = ctypes.c_int
+    lib.xm_align_similarity.argtypes = [I64, V, V, V, ctypes.POINTER(ctypes.c_double), V]
+    lib.xm_align_similarity.restype = ctypes.c_int
     lib.xm_free.argtypes = [P]
     lib.xm_free.restype = None
     lib.xm_get_info.argtypes = [P, ctypes.POINTER(_ProblemInfo)]
@@ -327,6 +339,21 @@ class Problem:
         _check(load_library().xm_recover_tp(self._h, _ptr(R), _ptr(s), _ptr(t), _ptr(pts), _stream()))
         return t, pts
 
+    def set_scale_reg(self, lam: float):
+        """xm_set_scale_reg: the objective gains lam sum_{k>=1} (s_k^2 - 1)^2."""
+        _check(load_library().xm_set_scale_reg(self._h, float(lam)))
+
+    def residuals(self, R: torch.Tensor, s: torch.Tensor, frame_units: bool = True):
+        """xm_residuals: (e [n,3], score [n]) at (R, s), caller's observation order."""
+        R = _dev_tensor(R, torch.float64, "R")
+        s = _dev_tensor(s, torch.float64, "s")
+        n = self.info()["n_in"]
+        e = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+        score = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(load_library().xm_residuals(self._h, _ptr(R), _ptr(s), 1 if frame_units else 0, _ptr(e), _ptr(score),
+                                           _stream()))
+        return e, score
+
     def adjoint(self, R, s, gR=None, gs=None, gcost: float = 0.0, dtype=torch.float64, cg_tol: float = 0.0,
                 cg_max: int = 0):
         """Gradients (dl/du [n,3], dl/dw [n], info) of a loss l(R, s, f*) with the given partials."""
@@ -334,7 +361,7 @@ class Problem:
         s = _dev_tensor(s, torch.float64, "s")
         gR = None if gR is None else _dev_tensor(gR.to(torch.float64), torch.float64, "gR")
         gs = None if gs is None else _dev_tensor(gs.to(torch.float64), torch.float64, "gs")
-        n = self.info()["n_obs"]
+        n = self.info()["n_in"]
         gu = torch.empty((n, 3), dtype=dtype, device="cuda")
         gw = torch.empty(n, dtype=dtype, device="cuda")
         gdt = XM_F64 if dtype == torch.float64 else XM_F32
@@ -400,9 +427,60 @@ class XMSolve(torch.autograd.Function):
         return gu.to(ctx.u_dtype), gw.to(ctx.w_dtype), None, None, None, None, None, None
 
 
+def drop_largest(score: torch.Tensor, frac: float = 0.1):
+    """xm_drop_largest: (keep mask uint8 [n], number dropped)."""
+    score = _dev_tensor(score, torch.float64, "score")
+    keep = torch.empty(score.shape[0], dtype=torch.uint8, device="cuda")
+    nd = ctypes.c_int64(0)
+    _check(load_library().xm_drop_largest(_ptr(score), score.shape[0], float(frac), _ptr(keep), ctypes.byref(nd),
+                                          _stream()))
+    return keep, nd.value
+
+
+def align_similarity(P: torch.Tensor, Q: torch.Tensor, w: Optional[torch.Tensor] = None) -> dict:
+    """xm_align_similarity: s, R [3,3], t [3] minimising sum w |s R P_i + t - Q_i|^2
+    (P, Q [n,3] float64 on the device), and the weighted RMS residual."""
+    P = _dev_tensor(P, torch.float64, "P")
+    Q = _dev_tensor(Q, torch.float64, "Q")
+    if P.dim() != 2 or P.shape[1] != 3 or Q.shape != P.shape:
+        raise ValueError("P and Q must both be [n, 3]")
+    if w is not None:
+        w = _dev_tensor(w, torch.float64, "w")
+        if w.shape != (P.shape[0],):
+            raise ValueError("w must be [n]")
+    out = (ctypes.c_double * 14)()
+    _check(load_library().xm_align_similarity(P.shape[0], _ptr(P), _ptr(Q), _ptr(w), out,
+                                              _stream()))
+    v = list(out)
+    return {"s": v[0], "R": torch.tensor(v[1:10], dtype=torch.float64).reshape(3, 3),
+            "t": torch.tensor(v[10:13], dtype=torch.float64), "rmse": v[13]}
+
+
+def xm2(N: int, M: int, frame: torch.Tensor, landmark: torch.Tensor, u: torch.Tensor,
+        w: Optional[torch.Tensor] = None, opts: Optional["SolveOptions"] = None, frac: float = 0.1,
+        frame_units: bool = True, keep=("f32",)):
+    """XM^2 (Section "Structure from Motion with XM"): xm_build_Q -> xm_bm_solve
+    -> xm_round -> xm_residuals -> xm_drop_largest -> xm_build_Q_masked ->
+    xm_bm_solve (started from the first solution) -> xm_round.  Returns a dict
+    with both passes' (R, s, rho_hat, info), the scores and the keep mask."""
+    opts = opts or SolveOptions()
+    P1 = build_Q(N, M, frame, landmark, u, w, keep=keep)
+    Y1, i1 = P1.solve(opts)
+    R1, s1, rho1 = P1.round(Y1)
+    _, score = P1.residuals(R1, s1, frame_units)
+    P1.close()
+    mask, n_drop = drop_largest(score, frac)
+    P2 = build_Q(N, M, frame, landmark, u, w, keep=keep, mask=mask)
+    Y2, i2 = P2.solve(opts, Y0=Y1[: i1["r"]])
+    R2, s2, rho2 = P2.round(Y2)
+    return {"first": (R1, s1, rho1, i1), "second": (R2, s2, rho2, i2), "score": score, "keep": mask,
+            "n_dropped": n_drop, "problem": P2, "Y": Y2}
+
+
 def build_Q(N: int, M: int, frame: torch.Tensor, landmark: torch.Tensor, u: torch.Tensor,
-            w: Optional[torch.Tensor] = None, keep=("f32",)) -> Problem:
-    """xm_build_Q on device tensors (frame/landmark int32, u [n,3] and w [n] float64 or float32)."""
+            w: Optional[torch.Tensor] = None, keep=("f32",), mask: Optional[torch.Tensor] = None) -> Problem:
+    """xm_build_Q on device tensors (frame/landmark int32, u [n,3] and w [n] float64 or float32);
+    with `mask` (uint8 [n], nonzero = use), xm_build_Q_masked."""
     lib = load_library()
     frame = _dev_tensor(frame, torch.int32, "frame")
     landmark = _dev_tensor(landmark, torch.int32, "landmark")
@@ -422,6 +500,13 @@ def build_Q(N: int, M: int, frame: torch.Tensor, landmark: torch.Tensor, u: torc
     for k in keep:
         copies |= {"f32": XM_KEEP_F32, "bf16": XM_KEEP_BF16}[k]
     h = ctypes.c_void_p(0)
-    _check(lib.xm_build_Q(N, M, frame.shape[0], _ptr(frame), _ptr(landmark), _ptr(u), u_dt, _ptr(w), w_dt,
-                          copies, _stream(), ctypes.byref(h)))
+    if mask is None:
+        _check(lib.xm_build_Q(N, M, frame.shape[0], _ptr(frame), _ptr(landmark), _ptr(u), u_dt, _ptr(w), w_dt,
+                              copies, _stream(), ctypes.byref(h)))
+    else:
+        mask = _dev_tensor(mask, torch.uint8, "mask")
+        if mask.shape != frame.shape:
+            raise ValueError("mask must have one entry per observation")
+        _check(lib.xm_build_Q_masked(N, M, frame.shape[0], _ptr(frame), _ptr(landmark), _ptr(u), u_dt, _ptr(w),
+                                     w_dt, _ptr(mask), copies, _stream(), ctypes.byref(h)))
     return Problem(h.value, N, M)

@@ -167,6 +167,31 @@ __global__ void obs_grad_kernel(int64_t n, const int32_t* __restrict__ fr_s, con
   gw[orig] = static_cast<TG>(g_w);
 }
 
+// residual export: e_o and its score in the caller's order (perm)
+__global__ void residual_out_kernel(int64_t n, const int32_t* __restrict__ fr_s, const int32_t* __restrict__ lm_s,
+                                    const double* __restrict__ u_s, const int64_t* __restrict__ perm,
+                                    const double* __restrict__ Yt, const double* __restrict__ t,
+                                    const double* __restrict__ pk, const double* __restrict__ s, int frame_units,
+                                    double* __restrict__ e_out, double* __restrict__ score_out) {
+  const int64_t o = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (o >= n) return;
+  double e[3];
+  residual(o, fr_s, lm_s, u_s, Yt, t, pk, e);
+  const int64_t orig = perm[o];
+  if (e_out)
+    for (int q = 0; q < 3; ++q) e_out[3 * orig + q] = e[q];
+  if (score_out) {
+    const double nrm = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    score_out[orig] = frame_units ? nrm / s[fr_s[o]] : nrm;
+  }
+}
+
+template <typename T>
+__global__ void fill_kernel(int64_t n, T v, T* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (i < n) out[i] = v;
+}
+
 // b = Riemannian gradient of l in the anchored chart: P_R(gR) (Stiefel), s^2 gs; frame 0 zero
 __global__ void rgrad_loss_kernel(int32_t N, const double* __restrict__ Rt, const double* __restrict__ s,
                                   const double* __restrict__ gR, const double* __restrict__ gs,
@@ -241,9 +266,36 @@ void recover_tp(xm_problem* p, const double* R, const double* s, double* t_out, 
   XM_HIP(hipStreamSynchronize(st));
 }
 
+void residuals(xm_problem* p, const double* R, const double* s, int frame_units, double* e_out, double* score_out,
+               hipStream_t st) {
+  require(R && s, XM_EINVAL, "R and s must be non-NULL");
+  require(e_out || score_out, XM_EINVAL, "at least one of e and score must be non-NULL");
+  const int N = p->N;
+  DevBuf<double> Rt(9 * static_cast<size_t>(N)), sv(N), Yt(9 * static_cast<size_t>(N));
+  hipLaunchKernelGGL(from_rs_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, st, N, R, s, Rt.ptr, sv.ptr, Yt.ptr);
+  XM_LAUNCH_CHECK("from_rs_kernel");
+  DevBuf<int32_t> mirror = build_mirror(p, st);
+  Recovered rec;
+  recover(p, Yt.ptr, mirror.ptr, rec, st);
+  if (p->n_in > p->n_obs) {  // observations the build's mask left out
+    if (e_out)
+      hipLaunchKernelGGL((fill_kernel<double>), dim3(cdiv(3 * p->n_in, kB)), dim3(kB), 0, st, 3 * p->n_in, 0.0,
+                         e_out);
+    if (score_out)
+      hipLaunchKernelGGL((fill_kernel<double>), dim3(cdiv(p->n_in, kB)), dim3(kB), 0, st, p->n_in, 0.0, score_out);
+    XM_LAUNCH_CHECK("fill_kernel");
+  }
+  const int64_t n = p->n_obs;
+  hipLaunchKernelGGL(residual_out_kernel, dim3(cdiv(n, kB)), dim3(kB), 0, st, n, p->fr_s.ptr, p->lm_s.ptr,
+                     p->u_s.ptr, p->perm.ptr, Yt.ptr, rec.t.ptr, rec.pk.ptr, sv.ptr, frame_units, e_out, score_out);
+  XM_LAUNCH_CHECK("residual_out_kernel");
+  XM_HIP(hipStreamSynchronize(st));
+}
+
 AdjointResult adjoint(xm_problem* p, const double* R, const double* s, const double* gR, const double* gs,
                       double gcost, void* gu, void* gw, xm_dtype gdt, double cg_tol, int cg_max, hipStream_t st) {
   require(R && s && gu && gw, XM_EINVAL, "R, s, gu and gw must be non-NULL");
+  require(p->scale_reg == 0.0, XM_EINVAL, "the adjoint is not available with the scale regulariser");
   require(gdt == XM_F64 || gdt == XM_F32, XM_EINVAL, "gradient dtype must be XM_F64 or XM_F32");
   const int N = p->N;
   const int64_t n3 = p->n3;
@@ -253,7 +305,7 @@ AdjointResult adjoint(xm_problem* p, const double* R, const double* s, const dou
   const size_t nv = 9 * static_cast<size_t>(N);
   DevBuf<double> Rt(nv), sv(N), Yt(nv), G(nv), gR_(nv), gs_(N), Sc(nv), ec(N);
   DevBuf<double> bR(nv), bs(N), etaR(nv), etas(N), HetaR(nv), Hetas(N), resR(nv), ress(N), dR(nv), ds(N);
-  DevBuf<double> HdR(nv), Hds(N), Ydot(nv), Gd(nv), part(static_cast<size_t>(cdiv(N, kB)) * 8);
+  DevBuf<double> HdR(nv), Hds(N), Ydot(nv), Gd(nv), part(static_cast<size_t>(cdiv(N, kFrameBlock)) * 8);
   Manifold<double> mf(N);
   const int nb = static_cast<int>(mf.blocks());
   hipLaunchKernelGGL(from_rs_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, st, N, R, s, Rt.ptr, sv.ptr, Yt.ptr);
@@ -326,6 +378,20 @@ AdjointResult adjoint(xm_problem* p, const double* R, const double* s, const dou
     recover(p, Ydot.ptr, mirror.ptr, recl, st);
   }
   const int64_t n = p->n_obs;
+  if (p->n_in > n) {  // observations the build's mask left out get zero gradients
+    if (gdt == XM_F64) {
+      hipLaunchKernelGGL((fill_kernel<double>), dim3(cdiv(3 * p->n_in, kB)), dim3(kB), 0, st, 3 * p->n_in, 0.0,
+                         static_cast<double*>(gu));
+      hipLaunchKernelGGL((fill_kernel<double>), dim3(cdiv(p->n_in, kB)), dim3(kB), 0, st, p->n_in, 0.0,
+                         static_cast<double*>(gw));
+    } else {
+      hipLaunchKernelGGL((fill_kernel<float>), dim3(cdiv(3 * p->n_in, kB)), dim3(kB), 0, st, 3 * p->n_in, 0.0f,
+                         static_cast<float*>(gu));
+      hipLaunchKernelGGL((fill_kernel<float>), dim3(cdiv(p->n_in, kB)), dim3(kB), 0, st, p->n_in, 0.0f,
+                         static_cast<float*>(gw));
+    }
+    XM_LAUNCH_CHECK("fill_kernel");
+  }
   const double* Yd = with_rot ? Ydot.ptr : Yt.ptr;
   const double* td = with_rot ? recl.t.ptr : rec.t.ptr;
   const double* pd = with_rot ? recl.pk.ptr : rec.pk.ptr;

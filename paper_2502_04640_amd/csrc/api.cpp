@@ -46,8 +46,42 @@ xm_status xm_build_Q(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame, 
   XM_API_TRY
   if (!out) return fail(XM_EINVAL, "out must be non-NULL");
   *out = nullptr;
-  auto P = xm::build_problem(N, M, n_obs, frame, landmark, u, u_dtype, w, w_dtype, copies, as_stream(stream));
+  auto P = xm::build_problem(N, M, n_obs, frame, landmark, u, u_dtype, w, w_dtype, nullptr, copies,
+                             as_stream(stream));
   *out = P.release();
+  return XM_OK;
+  XM_API_CATCH
+}
+
+xm_status xm_build_Q_masked(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame, const int32_t* landmark,
+                            const void* u, xm_dtype u_dtype, const void* w, xm_dtype w_dtype, const uint8_t* mask,
+                            uint32_t copies, void* stream, xm_problem** out) {
+  XM_API_TRY
+  if (!out) return fail(XM_EINVAL, "out must be non-NULL");
+  *out = nullptr;
+  auto P = xm::build_problem(N, M, n_obs, frame, landmark, u, u_dtype, w, w_dtype, mask, copies,
+                             as_stream(stream));
+  *out = P.release();
+  return XM_OK;
+  XM_API_CATCH
+}
+
+xm_status xm_residuals(xm_problem* p, const double* R, const double* s, int32_t frame_units, double* e,
+                       double* score, void* stream) {
+  XM_API_TRY
+  if (!p || !R || !s || (!e && !score)) return fail(XM_EINVAL, "NULL argument");
+  if (frame_units != 0 && frame_units != 1) return fail(XM_EINVAL, "frame_units must be 0 or 1");
+  xm::residuals(p, R, s, frame_units, e, score, as_stream(stream));
+  return XM_OK;
+  XM_API_CATCH
+}
+
+xm_status xm_drop_largest(const double* score, int64_t n, double frac, uint8_t* keep, int64_t* n_dropped,
+                          void* stream) {
+  XM_API_TRY
+  if (!score || !keep) return fail(XM_EINVAL, "NULL argument");
+  const int64_t k = xm::drop_largest(score, n, frac, keep, as_stream(stream));
+  if (n_dropped) *n_dropped = k;
   return XM_OK;
   XM_API_CATCH
 }
@@ -71,12 +105,22 @@ xm_status xm_get_info(const xm_problem* p, xm_problem_info* info) {
   info->N = p->N;
   info->M = p->M;
   info->n_obs = p->n_obs;
+  info->n_in = p->n_in;
   info->nnz_blocks = p->nnzb;
   info->n_pairs = p->n_pairs;
   info->ld = p->ld;
   info->copies = static_cast<int32_t>(p->copies);
   info->qbar = p->qbar;
   info->build_ms = p->build_ms;
+  info->scale_reg = p->scale_reg;
+  g_err.clear();
+  return XM_OK;
+}
+
+xm_status xm_set_scale_reg(xm_problem* p, double lambda) {
+  if (!p) return fail(XM_EINVAL, "NULL argument");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(XM_EINVAL, "lambda must be finite and >= 0");
+  p->scale_reg = lambda;
   g_err.clear();
   return XM_OK;
 }
@@ -266,6 +310,14 @@ xm_status xm_round(xm_problem* p, const double* Y, int32_t r, double* R_out, dou
   XM_API_TRY
   if (!p) return fail(XM_EINVAL, "NULL argument");
   xm::round_yt(p, Y, r, R_out, s_out, rho_hat, as_stream(stream));
+  return XM_OK;
+  XM_API_CATCH
+}
+
+xm_status xm_align_similarity(int64_t n, const double* P, const double* Q, const double* w, double* out,
+                              void* stream) {
+  XM_API_TRY
+  xm::align_similarity(n, P, Q, w, out, as_stream(stream));
   return XM_OK;
   XM_API_CATCH
 }

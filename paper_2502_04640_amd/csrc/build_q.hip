@@ -56,12 +56,22 @@ __global__ void validate_kernel(int32_t N, int32_t M, int64_t n, const int32_t* 
   }
 }
 
-__global__ void iota_kernel(const int32_t* __restrict__ landmark, int64_t n, uint32_t* keys,
-                            uint64_t* vals) {
+// sort keys: the landmark of each observation, or M (past every landmark, so
+// that masked-out observations sort to the end) where mask[e] == 0
+__global__ void iota_kernel(const int32_t* __restrict__ landmark, const uint8_t* __restrict__ mask, int32_t M,
+                            int64_t n, uint32_t* keys, uint64_t* vals) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
   if (e >= n) return;
-  keys[e] = static_cast<uint32_t>(landmark[e]);
+  keys[e] = (mask && !mask[e]) ? static_cast<uint32_t>(M) : static_cast<uint32_t>(landmark[e]);
   vals[e] = static_cast<uint64_t>(e);
+}
+
+// number of observations kept by the mask (integer sum: order-independent)
+__global__ void count_kept_kernel(const uint8_t* __restrict__ mask, int64_t n, unsigned long long* count) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  const bool k = e < n && mask[e] != 0;
+  const unsigned long long b = __ballot(k);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, static_cast<unsigned long long>(__popcll(b)));
 }
 
 __global__ void gather_obs_kernel(const uint64_t* __restrict__ order, int64_t n,
@@ -1242,7 +1252,7 @@ __global__ void q_rows_kernel(const double* __restrict__ Q, int32_t ld, int32_t 
 
 std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame,
                                           const int32_t* landmark, const void* u, xm_dtype u_dtype,
-                                          const void* w, xm_dtype w_dtype, uint32_t copies,
+                                          const void* w, xm_dtype w_dtype, const uint8_t* mask, uint32_t copies,
                                           hipStream_t s) {
   require(N >= 2 && N < 65536, XM_EINVAL, "N must be in [2, 65535]");
   require(M >= 1, XM_EINVAL, "M must be >= 1");
@@ -1258,10 +1268,10 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   XM_HIP(hipEventRecord(ev0, s));
 
   auto P = std::make_unique<xm_problem>();
-  P->N = N; P->M = M; P->n_obs = n_obs; P->n3 = 3 * N;
+  P->N = N; P->M = M; P->n_obs = n_obs; P->n_in = n_obs; P->n3 = 3 * N;
   P->ld = static_cast<int32_t>(round_up(3 * static_cast<size_t>(N), 64));
   const int u32 = (u_dtype == XM_F32), w32 = (w_dtype == XM_F32);
-  const int64_t n = n_obs;
+  int64_t n = n_obs;
 
   // a1: validate
   DevBuf<int> flags(8);
@@ -1275,14 +1285,30 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   require(!hflags[0], XM_EINVAL, "frame or landmark index out of range");
   require(!hflags[1], XM_EINVAL, "non-finite keypoint u");
   require(!hflags[2], XM_EINVAL, "weights must be finite and > 0");
+  if (mask) {
+    // observations with mask 0 are left out: they sort past every landmark and
+    // only the first n (kept) sorted entries are gathered
+    DevBuf<unsigned long long> cnt(1);
+    XM_HIP(hipMemsetAsync(cnt.ptr, 0, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(count_kept_kernel, dim3(cdiv(n_obs, kB)), dim3(kB), 0, s, mask, n_obs, cnt.ptr);
+    XM_LAUNCH_CHECK("count_kept_kernel");
+    unsigned long long kept = 0;
+    XM_HIP(hipMemcpyAsync(&kept, cnt.ptr, sizeof(kept), hipMemcpyDeviceToHost, s));
+    XM_HIP(hipStreamSynchronize(s));
+    require(kept >= 1, XM_EINVAL, "the mask keeps no observation");
+    n = static_cast<int64_t>(kept);
+    P->n_obs = n;
+  }
 
   // a1: sort observations by landmark
   {
-    DevBuf<uint32_t> keys(n), ktmp(n);
-    DevBuf<uint64_t> vals(n), vtmp(n);
-    hipLaunchKernelGGL(iota_kernel, dim3(cdiv(n, kB)), dim3(kB), 0, s, landmark, n, keys.ptr, vals.ptr);
+    DevBuf<uint32_t> keys(n_obs), ktmp(n_obs);
+    DevBuf<uint64_t> vals(n_obs), vtmp(n_obs);
+    hipLaunchKernelGGL(iota_kernel, dim3(cdiv(n_obs, kB)), dim3(kB), 0, s, landmark, mask, M, n_obs, keys.ptr,
+                       vals.ptr);
     XM_LAUNCH_CHECK("iota_kernel");
-    radix_sort_pairs(keys.ptr, vals.ptr, ktmp.ptr, vtmp.ptr, n, bits_for(static_cast<uint64_t>(M)), s);
+    radix_sort_pairs(keys.ptr, vals.ptr, ktmp.ptr, vtmp.ptr, n_obs,
+                     bits_for(static_cast<uint64_t>(M) + (mask ? 1 : 0)), s);
     P->fr_s.alloc(n); P->lm_s.alloc(n); P->u_s.alloc(3 * n); P->w_s.alloc(n); P->perm.alloc(n);
     hipLaunchKernelGGL(gather_obs_kernel, dim3(cdiv(n, kB)), dim3(kB), 0, s, vals.ptr, n, frame, landmark, u,
                        u32, w, w32, P->fr_s.ptr, P->lm_s.ptr, P->u_s.ptr, P->w_s.ptr, P->perm.ptr);

@@ -45,12 +45,18 @@ constexpr int kB = 256;
 // of the largest row norm
 constexpr double kDeflRel = 1e-3;
 
+// Lambda_k from (Q Y^T)_k.  With the scale regulariser (lam > 0, App. "Scale
+// Regularization") the stationarity condition carries Q + grad F(X), grad F
+// the diagonal 2 lam (X_{3k+2,3k+2} - 1) = 2 lam (alpha_k - 1) at row 3k+2 for
+// k >= 1; Z = Q + grad F - blkdiag(Lambda) is stored as Q - blkdiag(Lambda'),
+// Lambda'_k = Lambda_k - grad F_k.  part: {|Z Y^T|^2, tr(QX), tr(Lambda_0),
+// F(X), <grad F, X>}.
 template <int R>
 __global__ __launch_bounds__(kB) void lambda_kernel(int32_t N, const double* __restrict__ Yt,
-                                                    const double* __restrict__ G, double* __restrict__ Lam,
-                                                    double* part) {
+                                                    const double* __restrict__ G, double lam,
+                                                    double* __restrict__ Lam, double* part) {
   const int k = blockIdx.x * kB + threadIdx.x;
-  double v[3] = {0.0, 0.0, 0.0};
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (k < N) {
     double y[3][R], g[3][R];
     double nn = 0.0;
@@ -62,6 +68,11 @@ __global__ __launch_bounds__(kB) void lambda_kernel(int32_t N, const double* __r
         v[1] += y[c][a] * g[c][a];
       }
     const double alpha = nn / 3.0;
+    const double gF = (k == 0) ? 0.0 : 2.0 * lam * (alpha - 1.0);
+    if (gF != 0.0)
+      for (int a = 0; a < R; ++a) g[2][a] += gF * y[2][a];
+    v[3] = (k == 0) ? 0.0 : lam * (alpha - 1.0) * (alpha - 1.0);
+    v[4] = gF * alpha;
     double L[3][3];
     for (int c = 0; c < 3; ++c)
       for (int d = 0; d < 3; ++d) {
@@ -77,8 +88,9 @@ __global__ __launch_bounds__(kB) void lambda_kernel(int32_t N, const double* __r
     else
       v[2] = tr;
     for (int c = 0; c < 3; ++c)
-      for (int d = 0; d < 3; ++d) Lam[9 * static_cast<int64_t>(k) + 3 * c + d] = L[c][d];
-    // stationarity residual (Q Y^T)_k - Lambda_k Y_k^T
+      for (int d = 0; d < 3; ++d)
+        Lam[9 * static_cast<int64_t>(k) + 3 * c + d] = L[c][d] - ((c == 2 && d == 2) ? gF : 0.0);
+    // stationarity residual ((Q + grad F) Y^T)_k - Lambda_k Y_k^T
     for (int c = 0; c < 3; ++c)
       for (int a = 0; a < R; ++a) {
         double s = g[c][a];
@@ -86,10 +98,10 @@ __global__ __launch_bounds__(kB) void lambda_kernel(int32_t N, const double* __r
         v[0] += s * s;
       }
   }
-  __shared__ double lds[3 * (kB / 64)];
-  block_sum<3>(v, lds);
+  __shared__ double lds[5 * (kB / 64)];
+  block_sum<5>(v, lds);
   if (threadIdx.x == 0)
-    for (int q = 0; q < 3; ++q) part[blockIdx.x * 3 + q] = v[q];
+    for (int q = 0; q < 5; ++q) part[blockIdx.x * 5 + q] = v[q];
 }
 
 // w = Qx - blkdiag(Lambda) x
@@ -317,8 +329,9 @@ double small_sym_min_eig(const std::vector<double>& A, int n) {
 }
 
 template <int R>
-void launch_lambda(int32_t N, const double* Yt, const double* G, double* Lam, double* part, hipStream_t s) {
-  hipLaunchKernelGGL((lambda_kernel<R>), dim3(cdiv(N, kB)), dim3(kB), 0, s, N, Yt, G, Lam, part);
+void launch_lambda(int32_t N, const double* Yt, const double* G, double lam, double* Lam, double* part,
+                   hipStream_t s) {
+  hipLaunchKernelGGL((lambda_kernel<R>), dim3(cdiv(N, kB)), dim3(kB), 0, s, N, Yt, G, lam, Lam, part);
   XM_LAUNCH_CHECK("lambda_kernel");
 }
 
@@ -328,10 +341,11 @@ void launch_lambda(int32_t N, const double* Yt, const double* G, double* Lam, do
 // (page-locked) staging buffer, one per host thread, the copy is a single DMA
 // instead of a staged pageable transfer.  The buffer lives until the process
 // ends (it is not freed at thread exit, when the runtime may be gone).
-void read_partials(const double* dev, int blocks, int nq, double* out, hipStream_t s) {
+namespace {
+// the calling thread's pinned staging buffer, grown to at least n doubles
+double* staging(size_t n) {
   static thread_local double* h = nullptr;
   static thread_local size_t cap = 0;
-  const size_t n = static_cast<size_t>(blocks) * nq;
   if (n > cap) {
     void* ptr = nullptr;
     XM_HIP(hipHostMalloc(&ptr, n * sizeof(double), hipHostMallocDefault));
@@ -339,13 +353,35 @@ void read_partials(const double* dev, int blocks, int nq, double* out, hipStream
     h = static_cast<double*>(ptr);
     cap = n;
   }
-  XM_HIP(hipMemcpyAsync(h, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  XM_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+void sum_blocks(const double* h, int blocks, int nq, double* out) {
   for (int q = 0; q < nq; ++q) {
     double acc = 0.0;
     for (int b = 0; b < blocks; ++b) acc += h[static_cast<size_t>(b) * nq + q];
     out[q] = acc;
   }
+}
+}  // namespace
+
+void read_partials(const double* dev, int blocks, int nq, double* out, hipStream_t s) {
+  const size_t n = static_cast<size_t>(blocks) * nq;
+  double* h = staging(n);
+  XM_HIP(hipMemcpyAsync(h, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  XM_HIP(hipStreamSynchronize(s));
+  sum_blocks(h, blocks, nq, out);
+}
+
+void read_partials2(const double* dev, int blocks, int nq, double* out, const double* dev2, int n2, double* out2,
+                    hipStream_t s) {
+  const size_t n = static_cast<size_t>(blocks) * nq;
+  double* h = staging(n + n2);
+  XM_HIP(hipMemcpyAsync(h, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  XM_HIP(hipMemcpyAsync(h + n, dev2, n2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  XM_HIP(hipStreamSynchronize(s));
+  sum_blocks(h, blocks, nq, out);
+  for (int k = 0; k < n2; ++k) out2[k] = h[n + k];
 }
 
 CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int max_iter, double lanczos_tol,
@@ -360,23 +396,24 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
   if (lanczos_tol <= 0) lanczos_tol = 1e-6;
   CertResult out;
 
-  DevBuf<double> G(n * r), Lam(9 * static_cast<size_t>(N)), part(static_cast<size_t>(cdiv(N, kB)) * 3);
+  DevBuf<double> G(n * r), Lam(9 * static_cast<size_t>(N)), part(static_cast<size_t>(cdiv(N, kB)) * 5);
   spmm_yt<double>(p, XM_F64, Yt, r, G.ptr, s);
   switch (r) {
-    case 1: launch_lambda<1>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
-    case 2: launch_lambda<2>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
-    case 3: launch_lambda<3>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
-    case 4: launch_lambda<4>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
-    case 5: launch_lambda<5>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
-    case 6: launch_lambda<6>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
-    case 7: launch_lambda<7>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
-    case 8: launch_lambda<8>(N, Yt, G.ptr, Lam.ptr, part.ptr, s); break;
+    case 1: launch_lambda<1>(N, Yt, G.ptr, p->scale_reg, Lam.ptr, part.ptr, s); break;
+    case 2: launch_lambda<2>(N, Yt, G.ptr, p->scale_reg, Lam.ptr, part.ptr, s); break;
+    case 3: launch_lambda<3>(N, Yt, G.ptr, p->scale_reg, Lam.ptr, part.ptr, s); break;
+    case 4: launch_lambda<4>(N, Yt, G.ptr, p->scale_reg, Lam.ptr, part.ptr, s); break;
+    case 5: launch_lambda<5>(N, Yt, G.ptr, p->scale_reg, Lam.ptr, part.ptr, s); break;
+    case 6: launch_lambda<6>(N, Yt, G.ptr, p->scale_reg, Lam.ptr, part.ptr, s); break;
+    case 7: launch_lambda<7>(N, Yt, G.ptr, p->scale_reg, Lam.ptr, part.ptr, s); break;
+    case 8: launch_lambda<8>(N, Yt, G.ptr, p->scale_reg, Lam.ptr, part.ptr, s); break;
   }
-  double sums[3];
-  read_partials(part.ptr, cdiv(N, kB), 3, sums, s);
+  double sums[5];
+  read_partials(part.ptr, cdiv(N, kB), 5, sums, s);
   out.stat_res = std::sqrt(sums[0]);
-  out.primal = sums[1];
-  out.dual = sums[2];
+  // primal tr(QX) + F(X); dual tr(Lambda_0) + F(X) - <grad F(X), X> (F = 0 without the regulariser)
+  out.primal = sums[1] + sums[3];
+  out.dual = sums[2] + sums[3] - sums[4];
 
   // basis: [deflation rows D^{1/2} Y | Lanczos vectors of Zs]
   const int cap = r + max_iter + 1;

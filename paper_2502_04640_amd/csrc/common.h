@@ -142,6 +142,9 @@ void radix_sort_pairs(uint32_t* keys, uint64_t* vals, uint32_t* keys_tmp, uint64
 // Exclusive prefix sum of int64 values (in -> out, may alias).  Returns nothing;
 // the total is written to out[n] (out must hold n + 1 entries).
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+// keep[o] = 0 for the floor(frac n) largest scores (ties: lower index first),
+// 1 otherwise; scores must be finite and >= 0.  Returns the number dropped.
+int64_t drop_largest(const double* score, int64_t n, double frac, uint8_t* keep, hipStream_t s);
 
 // reduce.hip ----------------------------------------------------------------
 // Deterministic sum of `parts` rows of `nq` doubles laid out [parts][nq] into out[nq].

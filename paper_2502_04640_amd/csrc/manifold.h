@@ -5,6 +5,9 @@
 
 namespace xm {
 
+// threads per workgroup of the per-frame kernels (one thread per frame)
+constexpr int kFrameBlock = 256;
+
 // <a, b> over n entries, FP64 accumulation; `part` holds `blocks` doubles
 // (blocks <= 256).  Synchronises the stream.
 template <typename T>
@@ -17,8 +20,13 @@ struct Manifold {
   // pscale = mean_k s_k^2 q_kk at the current point
   const double* qkk = nullptr;
   double pscale = 1.0;
+  // scale regulariser lam sum_{k>=1} (s_k^2 - 1)^2 of App. "Scale
+  // Regularization" (0: the plain objective); it enters the cost, the scale
+  // part of the gradient and Hessian and the model's cost change
+  double lam = 0.0;
   explicit Manifold(int32_t n) : N(n) {}
-  unsigned blocks() const { return cdiv(N, 256); }
+  // workgroups of the per-frame kernels (one thread per frame)
+  unsigned blocks() const { return cdiv(N, kFrameBlock); }
 
   // G = Q Yt.  part: [blocks][5] = {cost, |grad|^2 (metric), |Y|_F^2, sum s^2 q_kk,
   //                                 pscale * <grad, P grad>}
@@ -35,11 +43,19 @@ struct Manifold {
   // part: [blocks][2] = {<res,res>, <res, P res>} (mode 0)
   void tcg_update(int r, const T* s, double alpha, int mode, const T* dR, const T* ds, const T* HdR, const T* Hds,
                   T* etaR, T* etas, T* HetaR, T* Hetas, T* resR, T* ress, double* part, hipStream_t st) const;
+  // the same update with its step chosen on the device from hess_kernel's
+  // partials (hess_part): interior alpha = z_r / <d,Hd>, or the boundary step
+  // when the curvature is not positive or |eta|_M would pass sqrt(delta2);
+  // ctl (device, 6 doubles) receives {step, mode, <d,Hd>, <d,Md>, <eta,Md>,
+  // <eta,M eta>}; part as tcg_update (mode 0)
+  void tcg_step_update(int r, const T* s, const double* hess_part, double z_r, double delta2, double* ctl,
+                       const T* dR, const T* ds, const T* HdR, const T* Hds, T* etaR, T* etas, T* HetaR,
+                       T* Hetas, T* resR, T* ress, double* part, hipStream_t st) const;
   void retract(int r, const T* Rt, const T* s, const T* etaR, const T* etas, T* Rt2, T* s2, T* Yt2,
                hipStream_t st) const;
-  // part: [blocks][3] = {<g,eta>, <eta,Heta>, <Y2-Y, G2+G> (the cost change)}
-  void model(int r, const T* s, const T* gR, const T* gs, const T* etaR, const T* etas, const T* HetaR,
-             const T* Hetas, const T* Yt, const T* G, const T* Yt2, const T* G2, double* part,
+  // part: [blocks][3] = {<g,eta>, <eta,Heta>, <Y2-Y, G2+G> + F(s2) - F(s) (the cost change)}
+  void model(int r, const T* s, const T* s2, const T* gR, const T* gs, const T* etaR, const T* etas,
+             const T* HetaR, const T* Hetas, const T* Yt, const T* G, const T* Yt2, const T* G2, double* part,
              hipStream_t st) const;
   // rank r -> r + 1 along [0; v^T] with step alpha; Rt2 / Yt2 have rank r + 1
   void escape(int r, const T* Rt, const T* s, const double* v, double alpha, T* Rt2, T* Yt2, hipStream_t st) const;

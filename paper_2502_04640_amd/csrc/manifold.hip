@@ -24,7 +24,8 @@
 namespace xm {
 namespace {
 
-constexpr int kB = 256;
+constexpr int kB = kFrameBlock;   // per-frame kernels
+constexpr int kVB = 256;          // vec_dot
 
 template <typename T, int R>
 struct Blk {
@@ -106,9 +107,10 @@ __device__ __forceinline__ double prec_weight(const double* qkk, double pscale, 
 // factor of the scale part relative to the rotation part (1 without a preconditioner)
 __device__ __forceinline__ double prec_sfac(const double* qkk) { return qkk ? 3.0 : 1.0; }
 
+// per-workgroup partial sums (workgroups of at most 256 threads: 4 waves)
 template <int NQ>
 __device__ __forceinline__ void write_partials(double (&v)[NQ], double* part) {
-  __shared__ double lds[NQ * (kB / 64)];
+  __shared__ double lds[NQ * 4];
   block_sum<NQ>(v, lds);
   if (threadIdx.x == 0)
     for (int q = 0; q < NQ; ++q) part[blockIdx.x * NQ + q] = v[q];
@@ -121,7 +123,7 @@ template <typename T, int R>
 __global__ __launch_bounds__(kB) void grad_kernel(int32_t N, const T* __restrict__ Rt, const T* __restrict__ s,
                                                   const T* __restrict__ G, T* __restrict__ gR, T* __restrict__ gs,
                                                   T* __restrict__ Sc, T* __restrict__ ec, const double* qkk,
-                                                  double* part) {
+                                                  double lam, double* part) {
   const int k = blockIdx.x * kB + threadIdx.x;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (k < N) {
@@ -133,7 +135,10 @@ __global__ __launch_bounds__(kB) void grad_kernel(int32_t N, const T* __restrict
 #pragma unroll
       for (int a = 0; a < R; ++a) Gam.v[c][a] *= T(2);
     const T sk = s[k];
-    const double e = dotb(Rk, Gam);
+    // df/ds_k: the quadratic part <R_k, Gamma_k> plus F'(s_k) = 4 lam s (s^2 - 1)
+    const double sdk = static_cast<double>(sk);
+    const double e = dotb(Rk, Gam) + ((k == 0) ? 0.0 : 4.0 * lam * sdk * (sdk * sdk - 1.0));
+    const double Fk = (k == 0) ? 0.0 : lam * (sdk * sdk - 1.0) * (sdk * sdk - 1.0);
     T M[3][3];
     xty(Rk, Gam, M);
 #pragma unroll
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(kB) void grad_kernel(int32_t N, const T* __restrict
 #pragma unroll
       for (int d = 0; d < 3; ++d) Sc[k * 9 + c * 3 + d] = static_cast<T>(M[c][d]);
     ec[k] = static_cast<T>(e);
-    v[0] = 0.5 * static_cast<double>(sk) * e;
+    v[0] = 0.5 * sdk * (e - ((k == 0) ? 0.0 : 4.0 * lam * sdk * (sdk * sdk - 1.0))) + Fk;
     v[1] = dotb(gt, gt) + ((k == 0) ? 0.0 : static_cast<double>(gsk) * gsk / (static_cast<double>(sk) * sk));
     v[2] = 3.0 * static_cast<double>(sk) * sk;
     // unnormalised preconditioner sums: s^2 q_kk and <g, M^{-1} g> * pscale
@@ -228,7 +233,7 @@ __global__ __launch_bounds__(kB) void hess_kernel(int32_t N, const T* __restrict
                                                   const T* __restrict__ ds, const T* __restrict__ Gd,
                                                   const T* __restrict__ etaR, const T* __restrict__ etas,
                                                   T* __restrict__ HR, T* __restrict__ Hs, const double* qkk,
-                                                  double pscale, double* part, int anchor0) {
+                                                  double pscale, double lam, double* part, int anchor0) {
   const int k = blockIdx.x * kB + threadIdx.x;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (k == 0 && anchor0) {
@@ -263,7 +268,11 @@ __global__ __launch_bounds__(kB) void hess_kernel(int32_t N, const T* __restrict
     sub_xs(Z, Rk, W);  // H_R = Z - R sym(R^T Z)
     Z.store(HR, k);
     const double sd = static_cast<double>(sk);
-    const double hs = (k == 0) ? 0.0 : sd * sd * edot + sd * static_cast<double>(ek) * static_cast<double>(dsk);
+    // s^2 d(df/ds)[sdot] + s (df/ds) sdot, with ek = df/ds (regulariser
+    // included) and the regulariser's second derivative 4 lam (3 s^2 - 1)
+    const double hs = (k == 0) ? 0.0
+                               : sd * sd * (edot + 4.0 * lam * (3.0 * sd * sd - 1.0) * static_cast<double>(dsk)) +
+                                     sd * static_cast<double>(ek) * static_cast<double>(dsk);
     Hs[k] = static_cast<T>(hs);
     const double is2 = (k == 0) ? 0.0 : 1.0 / (sd * sd);
     Blk<T, R> eta;
@@ -283,6 +292,7 @@ __global__ __launch_bounds__(kB) void hess_kernel(int32_t N, const T* __restrict
 // mode 1 (boundary): eta += a d, Heta += a Hd
 template <typename T, int R>
 __global__ __launch_bounds__(kB) void tcg_update_kernel(int32_t N, const T* __restrict__ s, double alpha, int mode,
+                                                        const double* __restrict__ ctl,
                                                         const T* __restrict__ dR, const T* __restrict__ ds,
                                                         const T* __restrict__ HdR, const T* __restrict__ Hds,
                                                         T* __restrict__ etaR, T* __restrict__ etas,
@@ -291,6 +301,10 @@ __global__ __launch_bounds__(kB) void tcg_update_kernel(int32_t N, const T* __re
                                                         double pscale, double* part) {
   const int k = blockIdx.x * kB + threadIdx.x;
   double v[2] = {0.0, 0.0};
+  if (ctl) {  // step and mode decided on the device (tcg_step_kernel)
+    alpha = ctl[0];
+    mode = static_cast<int>(ctl[1]);
+  }
   if (k < N) {
     const T a = static_cast<T>(alpha);
     Blk<T, R> d, hd, e, he;
@@ -327,6 +341,30 @@ __global__ __launch_bounds__(kB) void tcg_update_kernel(int32_t N, const T* __re
     }
   }
   write_partials<2>(v, part);
+}
+
+// The scalar step of a truncated-CG iteration, on the device so that the
+// update needs no host round trip: the partials of hess_kernel are added in
+// block order (as the host would), then alpha = z_r / <d, Hd>; if the curvature
+// is not positive or the step leaves the trust region, the boundary step tau
+// (|eta + tau d|_M = Delta) instead.  ctl = {step, mode (0 interior,
+// 1 boundary), <d,Hd>, <d,Md>, <eta,Md>, <eta,M eta>}.
+__global__ void tcg_step_kernel(const double* __restrict__ part, int nb, double z_r, double delta2,
+                                double* __restrict__ ctl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double q[4];
+  for (int j = 0; j < 4; ++j) {
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) acc += part[b * 4 + j];
+    q[j] = acc;
+  }
+  const double d_Hd = q[0], d_Pd = q[1], e_Pd = q[2], e_Pe = q[3];
+  const double alpha = z_r / d_Hd;
+  const double e_Pe_new = e_Pe + 2.0 * alpha * e_Pd + alpha * alpha * d_Pd;
+  const bool boundary = !(d_Hd > 0.0) || e_Pe_new >= delta2;
+  ctl[0] = boundary ? (-e_Pd + sqrt(e_Pd * e_Pd + d_Pd * (delta2 - e_Pe))) / d_Pd : alpha;
+  ctl[1] = boundary ? 1.0 : 0.0;
+  for (int j = 0; j < 4; ++j) ctl[2 + j] = q[j];
 }
 
 // Gram-Schmidt of the three columns of an r x 3 block (positive-diagonal QR).
@@ -380,7 +418,8 @@ __global__ __launch_bounds__(kB) void retract_kernel(int32_t N, const T* __restr
 
 // partials: <g, eta>, <eta, Heta>, <Y2 - Y, G2 + G>
 template <typename T, int R>
-__global__ __launch_bounds__(kB) void model_kernel(int32_t N, const T* __restrict__ s, const T* __restrict__ gR,
+__global__ __launch_bounds__(kB) void model_kernel(int32_t N, const T* __restrict__ s, const T* __restrict__ s2,
+                                                   double lam, const T* __restrict__ gR,
                                                    const T* __restrict__ gs, const T* __restrict__ etaR,
                                                    const T* __restrict__ etas, const T* __restrict__ HetaR,
                                                    const T* __restrict__ Hetas, const T* __restrict__ Yt,
@@ -408,6 +447,10 @@ __global__ __launch_bounds__(kB) void model_kernel(int32_t N, const T* __restric
       for (int a = 0; a < R; ++a)
         df += (static_cast<double>(y2.v[c][a]) - static_cast<double>(y.v[c][a])) *
               (static_cast<double>(g2.v[c][a]) + static_cast<double>(gg.v[c][a]));
+    if (k > 0 && lam != 0.0) {
+      const double a2 = static_cast<double>(s2[k]) * static_cast<double>(s2[k]) - 1.0, a1 = sd * sd - 1.0;
+      df += lam * (a2 - a1) * (a2 + a1);
+    }
     v[2] = df;
   }
   write_partials<3>(v, part);
@@ -501,11 +544,11 @@ __global__ void init_kernel(int32_t N, double lift, uint64_t seed, T* Rt, T* s) 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kB) void vec_dot_kernel(const T* __restrict__ a, const T* __restrict__ b, int64_t n,
+__global__ __launch_bounds__(kVB) void vec_dot_kernel(const T* __restrict__ a, const T* __restrict__ b, int64_t n,
                                                      double* part) {
   double v[1] = {0.0};
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kB)
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kVB + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kVB)
     v[0] += static_cast<double>(a[i]) * static_cast<double>(b[i]);
   write_partials<1>(v, part);
 }
@@ -514,7 +557,7 @@ __global__ __launch_bounds__(kB) void vec_dot_kernel(const T* __restrict__ a, co
 
 template <typename T>
 double vec_dot(const T* a, const T* b, int64_t n, double* part, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL((vec_dot_kernel<T>), dim3(blocks), dim3(kB), 0, st, a, b, n, part);
+  hipLaunchKernelGGL((vec_dot_kernel<T>), dim3(blocks), dim3(kVB), 0, st, a, b, n, part);
   XM_LAUNCH_CHECK("vec_dot_kernel");
   double out = 0.0;
   read_partials(part, blocks, 1, &out, st);
@@ -540,7 +583,7 @@ template <typename T>
 void Manifold<T>::grad(int r, const T* Rt, const T* s, const T* G, T* gR, T* gs, T* Sc, T* ec, double* part,
                        hipStream_t st) const {
   XM_DISPATCH_R(r, hipLaunchKernelGGL((grad_kernel<T, R>), dim3(blocks()), dim3(kB), 0, st, N, Rt, s, G, gR,
-                                      gs, Sc, ec, qkk, part));
+                                      gs, Sc, ec, qkk, lam, part));
   XM_LAUNCH_CHECK("grad_kernel");
 }
 
@@ -557,7 +600,7 @@ void Manifold<T>::hess(int r, const T* Rt, const T* s, const T* G, const T* Sc, 
                        const T* ds, const T* Gd, const T* etaR, const T* etas, T* HR, T* Hs, double* part,
                        hipStream_t st, bool anchor0) const {
   XM_DISPATCH_R(r, hipLaunchKernelGGL((hess_kernel<T, R>), dim3(blocks()), dim3(kB), 0, st, N, Rt, s, G, Sc, ec,
-                                      dR, ds, Gd, etaR, etas, HR, Hs, qkk, pscale, part, anchor0 ? 1 : 0));
+                                      dR, ds, Gd, etaR, etas, HR, Hs, qkk, pscale, lam, part, anchor0 ? 1 : 0));
   XM_LAUNCH_CHECK("hess_kernel");
 }
 
@@ -566,8 +609,22 @@ void Manifold<T>::tcg_update(int r, const T* s, double alpha, int mode, const T*
                              const T* Hds, T* etaR, T* etas, T* HetaR, T* Hetas, T* resR, T* ress, double* part,
                              hipStream_t st) const {
   XM_DISPATCH_R(r, hipLaunchKernelGGL((tcg_update_kernel<T, R>), dim3(blocks()), dim3(kB), 0, st, N, s, alpha,
-                                      mode, dR, ds, HdR, Hds, etaR, etas, HetaR, Hetas, resR, ress, qkk, pscale,
-                                      part));
+                                      mode, static_cast<const double*>(nullptr), dR, ds, HdR, Hds, etaR, etas, HetaR,
+                                      Hetas, resR, ress, qkk, pscale, part));
+  XM_LAUNCH_CHECK("tcg_update_kernel");
+}
+
+template <typename T>
+void Manifold<T>::tcg_step_update(int r, const T* s, const double* hess_part, double z_r, double delta2,
+                                  double* ctl, const T* dR, const T* ds, const T* HdR, const T* Hds, T* etaR,
+                                  T* etas, T* HetaR, T* Hetas, T* resR, T* ress, double* part,
+                                  hipStream_t st) const {
+  hipLaunchKernelGGL(tcg_step_kernel, dim3(1), dim3(64), 0, st, hess_part, static_cast<int>(blocks()), z_r, delta2,
+                     ctl);
+  XM_LAUNCH_CHECK("tcg_step_kernel");
+  XM_DISPATCH_R(r, hipLaunchKernelGGL((tcg_update_kernel<T, R>), dim3(blocks()), dim3(kB), 0, st, N, s, 0.0, 0,
+                                      static_cast<const double*>(ctl), dR, ds, HdR, Hds, etaR, etas, HetaR, Hetas,
+                                      resR, ress, qkk, pscale, part));
   XM_LAUNCH_CHECK("tcg_update_kernel");
 }
 
@@ -580,11 +637,11 @@ void Manifold<T>::retract(int r, const T* Rt, const T* s, const T* etaR, const T
 }
 
 template <typename T>
-void Manifold<T>::model(int r, const T* s, const T* gR, const T* gs, const T* etaR, const T* etas, const T* HetaR,
-                        const T* Hetas, const T* Yt, const T* G, const T* Yt2, const T* G2, double* part,
-                        hipStream_t st) const {
-  XM_DISPATCH_R(r, hipLaunchKernelGGL((model_kernel<T, R>), dim3(blocks()), dim3(kB), 0, st, N, s, gR, gs, etaR,
-                                      etas, HetaR, Hetas, Yt, G, Yt2, G2, part));
+void Manifold<T>::model(int r, const T* s, const T* s2, const T* gR, const T* gs, const T* etaR, const T* etas,
+                        const T* HetaR, const T* Hetas, const T* Yt, const T* G, const T* Yt2, const T* G2,
+                        double* part, hipStream_t st) const {
+  XM_DISPATCH_R(r, hipLaunchKernelGGL((model_kernel<T, R>), dim3(blocks()), dim3(kB), 0, st, N, s, s2, lam, gR, gs,
+                                      etaR, etas, HetaR, Hetas, Yt, G, Yt2, G2, part));
   XM_LAUNCH_CHECK("model_kernel");
 }
 

@@ -8,12 +8,15 @@
 
 struct xm_problem {
   int32_t N = 0, M = 0;
-  int64_t n_obs = 0;
+  int64_t n_obs = 0;   // observations used (those the build's mask kept)
+  int64_t n_in = 0;    // observations the caller passed (the length of per-observation outputs)
   int32_t n3 = 0;   // 3N
   int32_t ld = 0;   // leading dimension of the dense Q copies (multiple of 64)
   uint32_t copies = 1;
   double qbar = 0.0;
   double build_ms = 0.0;
+  // scale regulariser lam of App. "Scale Regularization" (xm_set_scale_reg)
+  double scale_reg = 0.0;
   int64_t nnzb = 0, n_pairs = 0;
   // device time of the main assembly kernels of the build (xm_build_stats)
   struct KernelStat {
@@ -113,7 +116,7 @@ T* take(Scratch* sc, DevBuf<B>& own, size_t count, hipStream_t s) {
 // build_q.hip
 std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, const int32_t* frame,
                                           const int32_t* landmark, const void* u, xm_dtype u_dtype,
-                                          const void* w, xm_dtype w_dtype, uint32_t copies,
+                                          const void* w, xm_dtype w_dtype, const uint8_t* mask, uint32_t copies,
                                           hipStream_t s);
 
 // spmm.hip: out (3N x r, row-major, frame-major "Yt" layout, ld = r) = Q * Yt.
@@ -154,6 +157,9 @@ xm_status bm_solve(xm_problem* p, const xm_solve_opts& o, const double* Y0, int 
 // round.hip
 void round_yt(xm_problem* p, const double* Y, int r, double* R_out, double* s_out, double* rho_hat,
               hipStream_t s);
+// similarity alignment of n points P to Q (device [n][3], weights device [n]
+// or NULL); out (host, 14): s, R row-major, t, weighted RMS residual
+void align_similarity(int64_t n, const double* P, const double* Q, const double* w, double* out, hipStream_t s);
 
 // adjoint.hip
 struct AdjointResult {
@@ -162,11 +168,19 @@ struct AdjointResult {
   bool converged = true, negative_curvature = false;
 };
 void recover_tp(xm_problem* p, const double* R, const double* s, double* t_out, double* p_out, hipStream_t st);
+// residuals e_o of eq. sba at (R, s) with t, p of eq. tpstar, in the caller's
+// order ([n_in][3] and [n_in]; observations left out by the build's mask get 0);
+// score_o = |e_o| (frame_units 0) or |e_o| / s_i (1)
+void residuals(xm_problem* p, const double* R, const double* s, int frame_units, double* e_out, double* score_out,
+               hipStream_t st);
 AdjointResult adjoint(xm_problem* p, const double* R, const double* s, const double* gR, const double* gs,
                       double gcost, void* gu, void* gw, xm_dtype gdt, double cg_tol, int cg_max, hipStream_t st);
 
 // Host sum of per-block partials [blocks][nq] (fixed order) after a stream sync.
 void read_partials(const double* dev, int blocks, int nq, double* out, hipStream_t s);
+// the same for `dev`, and n2 plain values of dev2 into out2, in one round trip
+void read_partials2(const double* dev, int blocks, int nq, double* out, const double* dev2, int n2, double* out2,
+                    hipStream_t s);
 // rows row0 .. row0 + nrows of Q (frame-index order) into out [nrows][3N]
 void get_q_rows(const xm_problem* p, int32_t row0, int32_t nrows, double* out, hipStream_t s);
 

@@ -54,7 +54,7 @@ struct Vecs {
       b->alloc(nv);
     for (DevBuf<T>* b : {&s, &s2, &gs, &ec, &etas, &Hetas, &ress, &ds, &Hds}) b->alloc(n);
     Sc.alloc(static_cast<size_t>(9) * n);
-    part.alloc(static_cast<size_t>(cdiv(n, 256)) * 8);
+    part.alloc(static_cast<size_t>(cdiv(n, kFrameBlock)) * 8);
   }
 };
 
@@ -112,6 +112,7 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
   const int N = p->N;
   Manifold<T> mf(N);
   if (o.precondition) mf.qkk = p->qkk.ptr;
+  mf.lam = p->scale_reg;
   const int nb = static_cast<int>(mf.blocks());
   const double qbar = p->qbar;
   const double Dbar = std::sqrt(3.0 * N);
@@ -165,6 +166,7 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
   // preconditioner scale at the current point and <g, P g>
   double pscale = sums[3] / N, gpg = sums[4] * pscale;
   const size_t nvr = static_cast<size_t>(3) * N * r;
+  DevBuf<double> ctl(8);  // the device-side step of each truncated-CG iteration
   int k = 0;
   for (k = 0; k < max_outer; ++k) {
     if (gnorm <= grad_tol * qbar * ynorm) {
@@ -189,20 +191,18 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
       ++out.spmm;
       mf.hess(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.Sc.ptr, V.ec.ptr, V.dR.ptr, V.ds.ptr, V.Gd.ptr, V.etaR.ptr,
               V.etas.ptr, V.HdR.ptr, V.Hds.ptr, V.part.ptr, st);
-      read_partials(V.part.ptr, nb, 4, sums, st);
-      const double d_Hd = sums[0], d_Pd = sums[1], e_Pd = sums[2], e_Pe = sums[3];
-      const double alpha = z_r / d_Hd;
-      const double e_Pe_new = e_Pe + 2.0 * alpha * e_Pd + alpha * alpha * d_Pd;
-      if (d_Hd <= 0.0 || e_Pe_new >= Delta * Delta) {
-        const double tau = (-e_Pd + std::sqrt(e_Pd * e_Pd + d_Pd * (Delta * Delta - e_Pe))) / d_Pd;
-        mf.tcg_update(r, V.s.ptr, tau, 1, V.dR.ptr, V.ds.ptr, V.HdR.ptr, V.Hds.ptr, V.etaR.ptr, V.etas.ptr,
-                      V.HetaR.ptr, V.Hetas.ptr, V.resR.ptr, V.ress.ptr, V.part.ptr, st);
+      // the step (interior alpha, or the boundary tau on non-positive
+      // curvature / leaving the region) is chosen on the device, and the
+      // update applied, before the one host round trip of the iteration
+      mf.tcg_step_update(r, V.s.ptr, V.part.ptr, z_r, Delta * Delta, ctl.ptr, V.dR.ptr, V.ds.ptr, V.HdR.ptr,
+                         V.Hds.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr, V.resR.ptr, V.ress.ptr,
+                         V.part.ptr, st);
+      double hctl[6];
+      read_partials2(V.part.ptr, nb, 2, sums, ctl.ptr, 6, hctl, st);
+      if (hctl[1] != 0.0) {
         boundary = true;
         break;
       }
-      mf.tcg_update(r, V.s.ptr, alpha, 0, V.dR.ptr, V.ds.ptr, V.HdR.ptr, V.Hds.ptr, V.etaR.ptr, V.etas.ptr,
-                    V.HetaR.ptr, V.Hetas.ptr, V.resR.ptr, V.ress.ptr, V.part.ptr, st);
-      read_partials(V.part.ptr, nb, 2, sums, st);
       const double r_r_new = sums[0], z_r_new = sums[1];
       if (std::sqrt(r_r_new) <= norm_r0 * std::min(std::pow(norm_r0, theta), kappa)) break;
       beta = z_r_new / z_r;
@@ -235,8 +235,8 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
       }
     }
     ++out.spmm;
-    mf.model(r, V.s.ptr, V.gR.ptr, V.gs.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr, V.Yt.ptr, V.G.ptr,
-             V.Yt2.ptr, V.G2.ptr, V.part.ptr, st);
+    mf.model(r, V.s.ptr, V.s2.ptr, V.gR.ptr, V.gs.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr,
+             V.Yt.ptr, V.G.ptr, V.Yt2.ptr, V.G2.ptr, V.part.ptr, st);
     read_partials(V.part.ptr, nb, 3, sums, st);
     const double mdec = -(sums[0] + 0.5 * sums[1]);
     const double df = sums[2];
@@ -245,11 +245,15 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
     // a candidate whose cost is not finite (a scale step that overflowed) is
     // rejected and the radius cut, like any poor model agreement
     const bool finite = std::isfinite(rho);
-    if (!finite || rho < 0.25) Delta *= 0.25;
-    else if (rho > 0.75 && boundary) Delta = std::min(2.0 * Delta, Dbar);
     // a step the (reduced-precision) model misjudges as an increase is still
     // taken when the evaluated cost went down
     const bool accept = finite && ((mdec > 0.0 && rho > rho_prime) || (mdec <= 0.0 && df < -reg));
+    // the ratio means nothing when the model predicts no decrease (rounding in
+    // <eta, H eta> at a radius far beyond the Newton step, e.g. along the flat
+    // directions of a rank-deficient point): such a step, unless the cost went
+    // down anyway, cuts the radius and never grows it
+    if (!finite || rho < 0.25 || (mdec <= 0.0 && !accept)) Delta *= 0.25;
+    else if (mdec > 0.0 && rho > 0.75 && boundary) Delta = std::min(2.0 * Delta, Dbar);
     if (o.verbose)
       std::fprintf(stderr, "[xm] r=%d it=%d f=%.12e |g|=%.3e Delta=%.3e rho=%.3f inner=%d %s%s\n", r, k, f, gnorm,
                    Delta, rho, std::min(j, max_inner), boundary ? "boundary" : "interior", accept ? "" : " rejected");
@@ -297,6 +301,7 @@ Check fp64_check(xm_problem* p, const double* Yt64, int r, hipStream_t st) {
   const int N = p->N;
   Vecs<double> V(N, r);
   Manifold<double> mf(N);
+  mf.lam = p->scale_reg;
   mf.split(r, Yt64, V.Rt.ptr, V.s.ptr, V.Yt.ptr, st);
   spmm_yt<double>(p, XM_F64, V.Yt.ptr, r, V.G.ptr, st);
   mf.grad(r, V.Rt.ptr, V.s.ptr, V.G.ptr, V.gR.ptr, V.gs.ptr, V.Sc.ptr, V.ec.ptr, V.part.ptr, st);

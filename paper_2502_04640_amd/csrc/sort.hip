@@ -10,6 +10,8 @@
 //   scatter: 16 rounds of 256 elements; the stable rank of an element among
 //            equal digits of its round comes from 8 wave ballots (wave64),
 //            per-wave digit counts in LDS give the cross-wave prefix.
+#include <cmath>
+
 #include "common.h"
 
 namespace xm {
@@ -160,6 +162,35 @@ __global__ void write_total_kernel(const int64_t* tile_sums, int64_t tiles, int6
   *out_n = tile_sums[tiles];
 }
 
+// Sort keys of a score: the bit pattern of a finite double >= 0 grows with its
+// value, so its complement sorts the largest first; split into the low and high
+// 32-bit words (two stable passes give the order of the whole 64-bit key).
+// flag[0] = 1 for a NaN, infinite or negative score.
+__global__ void score_keys_kernel(const double* __restrict__ score, int64_t n, uint32_t* __restrict__ lo,
+                                  uint32_t* __restrict__ hi, uint64_t* __restrict__ idx, int* flag) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= n) return;
+  const double v = score[e];
+  if (!(v >= 0.0) || isinf(v)) flag[0] = 1;
+  const uint64_t k = ~static_cast<uint64_t>(__double_as_longlong(v >= 0.0 ? v : 0.0));
+  lo[e] = static_cast<uint32_t>(k);
+  hi[e] = static_cast<uint32_t>(k >> 32);
+  idx[e] = static_cast<uint64_t>(e);
+}
+
+// high key words in the order of the first pass
+__global__ void gather_hi_kernel(const uint64_t* __restrict__ idx, int64_t n, const uint32_t* __restrict__ hi,
+                                 uint32_t* __restrict__ out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e < n) out[e] = hi[idx[e]];
+}
+
+// keep[o] = 0 for the first k entries of the sorted order, 1 for the rest
+__global__ void keep_mask_kernel(const uint64_t* __restrict__ idx, int64_t n, int64_t k, uint8_t* __restrict__ keep) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e < n) keep[idx[e]] = (e < k) ? 0 : 1;
+}
+
 }  // namespace
 
 void radix_sort_pairs(uint32_t* keys, uint64_t* vals, uint32_t* keys_tmp, uint64_t* vals_tmp,
@@ -191,6 +222,34 @@ void radix_sort_pairs(uint32_t* keys, uint64_t* vals, uint32_t* keys_tmp, uint64
   }
   // scratch buffers are freed at scope exit: make sure the kernels are done with them
   XM_HIP(hipStreamSynchronize(s));
+}
+
+int64_t drop_largest(const double* score, int64_t n, double frac, uint8_t* keep, hipStream_t s) {
+  require(score && keep, XM_EINVAL, "score and keep must be non-NULL");
+  require(n >= 1 && n < (int64_t(1) << 31), XM_EINVAL, "n must be in [1, 2^31)");
+  require(frac >= 0.0 && frac <= 1.0, XM_EINVAL, "frac must be in [0, 1]");
+  const int64_t k = static_cast<int64_t>(std::floor(frac * static_cast<double>(n)));
+  DevBuf<uint32_t> lo(n), hi(n), tmpk(n);
+  DevBuf<uint64_t> idx(n), tmpv(n);
+  DevBuf<int> flag(1);
+  XM_HIP(hipMemsetAsync(flag.ptr, 0, sizeof(int), s));
+  const unsigned g = static_cast<unsigned>((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(score_keys_kernel, dim3(g), dim3(kBlock), 0, s, score, n, lo.ptr, hi.ptr, idx.ptr, flag.ptr);
+  XM_LAUNCH_CHECK("score_keys_kernel");
+  int hflag = 0;
+  XM_HIP(hipMemcpyAsync(&hflag, flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+  XM_HIP(hipStreamSynchronize(s));
+  require(!hflag, XM_EINVAL, "scores must be finite and >= 0");
+  // stable LSD over the 64-bit key: low word first, then the high word; equal
+  // keys keep index order, so ties drop the lower index first
+  radix_sort_pairs(lo.ptr, idx.ptr, tmpk.ptr, tmpv.ptr, n, 32, s);
+  hipLaunchKernelGGL(gather_hi_kernel, dim3(g), dim3(kBlock), 0, s, idx.ptr, n, hi.ptr, lo.ptr);
+  XM_LAUNCH_CHECK("gather_hi_kernel");
+  radix_sort_pairs(lo.ptr, idx.ptr, tmpk.ptr, tmpv.ptr, n, 32, s);
+  hipLaunchKernelGGL(keep_mask_kernel, dim3(g), dim3(kBlock), 0, s, idx.ptr, n, k, keep);
+  XM_LAUNCH_CHECK("keep_mask_kernel");
+  XM_HIP(hipStreamSynchronize(s));
+  return k;
 }
 
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {

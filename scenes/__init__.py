@@ -316,11 +316,14 @@ def _large(seed, N=10155, M=2_000_000, k=50, clusters=20, sigma=0.02, outlier=0.
         lm = np.concatenate([lm, np.array(extra_lm, dtype=np.int64)])
     Mtot = x.shape[0]
     lo, hi = c.min(0) - 3.0, c.max(0) + 3.0
+    bad = []
     if outlier_model == "box":
-        u = _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=outlier, bbox=(lo, hi))
+        u = _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=outlier, bbox=(lo, hi), mask_out=bad)
     else:
-        u = _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=outlier, local=local)
-    return _finish("large", N, Mtot, fr, lm, u, np.ones(fr.shape[0]), _ground_truth(R_cfg, c, d, x))
+        u = _lift(rng, R_cfg, c, d, x, fr, lm, sigma, outlier_frac=outlier, local=local, mask_out=bad)
+    gt = _ground_truth(R_cfg, c, d, x)
+    gt["outlier"] = bad[0]
+    return _finish("large", N, Mtot, fr, lm, u, np.ones(fr.shape[0]), gt)
 
 
 def _diff(seed, N=500, M=50_000, sigma=0.01):

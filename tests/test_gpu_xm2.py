@@ -1,0 +1,157 @@
+"""XM^2 through the C ABI against the oracle: residual export (eq. sba at the
+rounded optimum, t and p of eq. tpstar), the deterministic deletion, the masked
+rebuild of Q and the whole loop on a seeded scene with injected outliers."""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import data_matrix as odm
+from oracle import staircase as ost
+from oracle import xm2 as oxm2
+
+from conftest import progress
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _xm():
+    import paper_2502_04640_amd as xm
+    xm.load_library()
+    return xm
+
+
+def _say(msg):
+    print(msg, flush=True)
+    progress(msg)
+
+
+def _dev(sc):
+    return (torch.from_numpy(sc.frame).cuda(), torch.from_numpy(sc.landmark).cuda(),
+            torch.from_numpy(sc.u).cuda(), torch.from_numpy(sc.w).cuda())
+
+
+def _rot_err(Ra, Rb):
+    d = np.linalg.norm(Ra - Rb, axis=(1, 2))
+    return float(np.max(2 * np.arcsin(np.minimum(1.0, d / (2 * np.sqrt(2))))))
+
+
+def _gap(a, b):
+    return abs(a - b) / (1 + abs(a) + abs(b))
+
+
+def _scene():
+    # noise-free, 1% of the observations moved up to 3 units off their landmark
+    return scenes.random_scene(50, 2000, L=4, sigma=0.0, seed=10, outlier=0.01, outlier_local=3.0)
+
+
+def test_residuals_match_oracle():
+    _say("case: residual export vs oracle (40 frames, weights, 2% outliers)")
+    xm = _xm()
+    sc = scenes.random_scene(40, 1500, L=4, sigma=0.02, seed=45, weights=(0.5, 1.5), outlier=0.02, outlier_local=2.0)
+    P = xm.build_Q(sc.N, sc.M, *_dev(sc), keep=())
+    Y, info = P.solve(xm.SolveOptions(compute="f64"))
+    R, s, _ = P.round(Y)
+    Rn, sn = R.cpu().numpy(), s.cpu().numpy()
+    e_o, _, _ = oxm2.residuals(sc.N, sc.M, sc.frame, sc.landmark, sc.u, sc.w, Rn, sn)
+    for frame_units in (False, True):
+        e, score = P.residuals(R, s, frame_units)
+        e, score = e.cpu().numpy(), score.cpu().numpy()
+        assert np.abs(e - e_o).max() <= 1e-10 * np.abs(e_o).max()
+        ref = oxm2.scores(e_o, sn, sc.frame, "frame" if frame_units else "world")
+        assert np.abs(score - ref).max() <= 1e-10 * ref.max()
+    # sum of weighted squared residuals = the rounded point's cost rho_hat
+    rho = P.round(Y)[2]
+    assert _gap(float(np.sum(sc.w * np.sum(e * e, axis=1))), rho) <= 1e-10
+
+
+def test_drop_largest_matches_definition():
+    _say("case: drop_largest against the oracle's deletion (ties, edge fractions, errors)")
+    xm = _xm()
+    rng = np.random.default_rng(3)
+    for n, frac in ((1, 0.5), (1000, 0.0), (1000, 0.1), (4097, 0.25), (100000, 0.1), (100000, 1.0)):
+        score = rng.random(n) * rng.choice([1e-3, 1.0, 1e3], n)
+        if n > 10:
+            score[rng.choice(n, n // 10)] = 0.5          # many exact ties
+            score[:3] = 0.0
+        keep, nd = xm.drop_largest(torch.from_numpy(score).cuda(), frac)
+        ref = oxm2.drop_mask(score, frac)
+        assert nd == int(np.floor(frac * n))
+        assert np.array_equal(keep.cpu().numpy().astype(bool), ref), (n, frac)
+    with pytest.raises(xm.XMError, match="XM_EINVAL"):
+        xm.drop_largest(torch.tensor([1.0, -1.0], dtype=torch.float64, device="cuda"), 0.5)
+    with pytest.raises(xm.XMError, match="XM_EINVAL"):
+        xm.drop_largest(torch.tensor([1.0, float("nan")], dtype=torch.float64, device="cuda"), 0.5)
+
+
+def test_masked_build_matches_oracle_q_of_kept_observations():
+    _say("case: masked build vs the oracle's Q of the kept observations")
+    xm = _xm()
+    sc = scenes.random_scene(60, 3000, L=5, sigma=0.02, seed=46, weights=(0.5, 1.5))
+    rng = np.random.default_rng(4)
+    keep = rng.random(sc.n_obs) > 0.1
+    P = xm.build_Q(sc.N, sc.M, *_dev(sc), keep=(), mask=torch.from_numpy(keep.astype(np.uint8)).cuda())
+    info = P.info()
+    assert info["n_obs"] == int(keep.sum()) and info["n_in"] == sc.n_obs
+    Q = P.Q_rows(0, 3 * sc.N).cpu().numpy()
+    Qo = odm.q_block_elimination(sc.N, sc.M, sc.frame[keep], sc.landmark[keep], sc.u[keep], sc.w[keep])
+    assert np.abs(Q - Qo).max() <= 1e-10 * np.abs(Qo).max()
+    # every product kernel on the masked build, the factored one included
+    Yr = rng.standard_normal((5, 3 * sc.N))
+    ref = Yr @ Qo
+    kinds = {role: P.spmm_kind("f64", role) for role in ("residual", "curvature")}
+    for kind in ("upper", "full", "factored"):
+        P.set_spmm_kind("f64", kind)
+        out = P.spmm(torch.from_numpy(Yr).cuda(), "f64").cpu().numpy()
+        assert np.abs(out - ref).max() <= 1e-10 * np.abs(ref).max(), kind
+    for role, kind in kinds.items():
+        P.set_spmm_kind("f64", kind, role=role)
+    Y, _ = P.solve(xm.SolveOptions(compute="f64"))
+    R, s, _ = P.round(Y)
+    e, score = P.residuals(R, s, True)
+    e, score = e.cpu().numpy(), score.cpu().numpy()
+    assert not np.any(e[~keep]) and not np.any(score[~keep])
+    e_o, _, _ = oxm2.residuals(sc.N, sc.M, sc.frame[keep], sc.landmark[keep], sc.u[keep], sc.w[keep],
+                               R.cpu().numpy(), s.cpu().numpy())
+    assert np.abs(e[keep] - e_o).max() <= 1e-10 * np.abs(e_o).max()
+    # a mask that keeps nothing, and one that strips every observation of frame 5
+    fr, lm, u, w = _dev(sc)
+    with pytest.raises(xm.XMError, match="XM_EINVAL"):
+        xm.build_Q(sc.N, sc.M, fr, lm, u, w, keep=(), mask=torch.zeros(sc.n_obs, dtype=torch.uint8, device="cuda"))
+    m5 = (sc.frame != 5).astype(np.uint8)
+    with pytest.raises(xm.XMError, match="XM_EGRAPH"):
+        xm.build_Q(sc.N, sc.M, fr, lm, u, w, keep=(), mask=torch.from_numpy(m5).cuda())
+
+
+@pytest.mark.parametrize("units", ["frame", "world"])
+def test_xm2_loop_matches_oracle(units):
+    _say(f"case: XM^2 loop vs oracle, 50 frames, 1% outliers, {units} units")
+    xm = _xm()
+    sc = _scene()
+    out = xm.xm2(sc.N, sc.M, *_dev(sc), opts=xm.SolveOptions(compute="f64", grad_tol=1e-11), frac=0.1,
+                 frame_units=(units == "frame"), keep=())
+    o = oxm2.xm2(sc.N, sc.M, sc.frame, sc.landmark, sc.u, sc.w, frac=0.1, rank=units)
+    # first pass: the same optimum, so the same scores (up to rounding) and,
+    # away from ties at the threshold, the same deletion
+    R1, s1, _, i1 = out["first"]
+    assert i1["certified"] == 1
+    assert _rot_err(R1.cpu().numpy(), o["first"][0]) <= 1e-6
+    keep = out["keep"].cpu().numpy().astype(bool)
+    score = out["score"].cpu().numpy()
+    assert out["n_dropped"] == int(0.1 * sc.n_obs)
+    diff = keep != o["keep"]
+    thr = np.sort(score)[::-1][out["n_dropped"] - 1]
+    assert np.all(np.abs(score[diff] - thr) <= 1e-9 * thr)
+    # second pass: the oracle's staircase on the GPU's kept set
+    R2, s2, rho2, i2 = out["second"]
+    assert i2["certified"] == 1
+    Q2 = odm.q_block_elimination(sc.N, sc.M, sc.frame[keep], sc.landmark[keep], sc.u[keep], sc.w[keep])
+    Ro, so, oinfo = ost.staircase(Q2, grad_tol=1e-11, tau=1e-7)
+    from oracle import manifold as omf, rounding as ord_
+    Rh, sh = ord_.round_solution(omf.to_U(Ro, so))
+    err = _rot_err(R2.cpu().numpy(), Rh)
+    _say(f"  second pass vs oracle: rotations {err:.2e} rad, cost gap {_gap(i2['cost'], oinfo['cost']):.2e}; "
+         f"vs ground truth: first {_rot_err(R1.cpu().numpy(), sc.gt['R']):.2e}, "
+         f"second {_rot_err(R2.cpu().numpy(), sc.gt['R']):.2e}")
+    assert err <= 1e-6 and np.abs(s2.cpu().numpy() / sh - 1).max() <= 1e-6
+    assert _gap(i2["cost"], oinfo["cost"]) <= 1e-8
