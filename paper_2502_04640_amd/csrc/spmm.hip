@@ -162,6 +162,54 @@ constexpr int kSymShift = (kSymBatch == 8) ? 3 : 4;  // lane >> kSymShift select
 #endif
 constexpr bool kSymScalarY = XM_SYM_SCALAR_Y && !XM_SYM_PERM;
 
+// The kSymBatch row segments of a batch (zero where a row is past the slab or,
+// in a tile that crosses the diagonal, where all V columns of the lane lie left
+// of the row, whose values would be masked to zero anyway).
+template <bool kMask, typename TQ, typename TA>
+__device__ __forceinline__ void sym_load(const TQ* __restrict__ q, int32_t ld, int i_base, int nb, int pi, int jcol,
+                                         TA (&qv)[kSymBatch][QVec<TQ>::V]) {
+  constexpr int V = QVec<TQ>::V;
+#pragma unroll
+  for (int b = 0; b < kSymBatch; ++b) {
+    const int row = b ^ pi;
+    if (row < nb && (!kMask || jcol + V - 1 >= i_base + row)) {
+      QVec<TQ>::load(q + static_cast<int64_t>(row) * ld, qv[b]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) qv[b][v] = TA(0);
+    }
+  }
+}
+
+template <bool kMask, typename TQ, typename TA, typename TV, int R>
+__device__ __forceinline__ void sym_fma(const TA (&qv)[kSymBatch][QVec<TQ>::V], int i_base, int pi, int jcol,
+                                        const TA* __restrict__ ys, const TV* __restrict__ Yt, int32_t n3,
+                                        const TA (&xc)[QVec<TQ>::V][R], TA (&acc)[QVec<TQ>::V][R],
+                                        TA (&p)[kSymBatch][R]) {
+  constexpr int V = QVec<TQ>::V;
+#pragma unroll
+  for (int b = 0; b < kSymBatch; ++b) {
+    const int row = b ^ pi;
+    const int i = i_base + row;  // global row
+#pragma unroll
+    for (int a = 0; a < R; ++a) p[b][a] = TA(0);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      TA qc = qv[b][v], qr = qv[b][v];
+      if (kMask) {
+        qc = (jcol + v >= i) ? qc : TA(0);
+        qr = (jcol + v > i) ? qr : TA(0);
+      }
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        const TA y = kSymScalarY ? static_cast<TA>(Yt[static_cast<int64_t>(min(i, n3 - 1)) * R + a]) : ys[row * R + a];
+        acc[v][a] += qc * y;
+        p[b][a] += qr * xc[v][a];
+      }
+    }
+  }
+}
+
 template <bool kMask, typename TQ, typename TA, typename TV, int R>
 __device__ __forceinline__ void sym_batch(const TQ* __restrict__ q, int32_t ld, int i_base, int nb, int pi, int jcol,
                                           const TA* __restrict__ ys, const TV* __restrict__ Yt, int32_t n3,
@@ -204,6 +252,18 @@ __device__ __forceinline__ void sym_batch(const TQ* __restrict__ q, int32_t ld, 
   }
 }
 
+// Small matrices (the G^{-1} of the factored product) give about two
+// workgroups per CU, too few to hide the latency of each batch's loads behind
+// other waves: there the kernel loads the next batch before the arithmetic of
+// the current one (kPre), at the price of its registers.  Measured at N = 10155
+// (G^{-1} of 10154 rows): FP64 r = 1 (the certificate's Lanczos) 109 -> 86 us,
+// FP32 r = 5 68 -> 66 us; FP64 r = 5 loses (163 -> 194 us: the doubled
+// registers halve the waves), and so does the 30465-row FP32 Q (389 -> 500 us).
+template <typename TQ, int R>
+constexpr bool sym_prefetch(int64_t active_blocks) {
+  return active_blocks < 1024 && (sizeof(TQ) == 4 || R <= 2);
+}
+
 #ifndef XM_SYM_WAVES
 #define XM_SYM_WAVES 0
 #endif
@@ -212,7 +272,7 @@ __device__ __forceinline__ void sym_batch(const TQ* __restrict__ q, int32_t ld, 
 #else
 #define XM_SYM_ATTR
 #endif
-template <typename TQ, typename TV, typename TA, int R, int RS>
+template <typename TQ, typename TV, typename TA, int R, int RS, bool kPre>
 __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __restrict__ Q, int32_t ld, int32_t n3,
                                                       const TV* __restrict__ Yt, TA* __restrict__ colpart,
                                                       TA* __restrict__ rowpart) {
@@ -246,15 +306,41 @@ __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __re
   const bool crossing = j0 < i1;
   const bool active = j < ld;  // lanes past the padded width read nothing
   const TQ* qbase = Q + static_cast<int64_t>(i0) * ld + (active ? j : 0);
-  for (int ib = 0; ib < nrows; ib += kSymBatch) {
-    const int nb = active ? min(kSymBatch, nrows - ib) : 0;
-    TA p[kSymBatch][R];
+  // kPre: qv holds the current batch, loaded one iteration ahead
+  TA qv[kSymBatch][V];
+  if (kPre) {
+    const int nb = active ? min(kSymBatch, nrows) : 0;
     if (crossing)
-      sym_batch<true, TQ, TA, TV, R>(qbase + static_cast<int64_t>(ib) * ld, ld, i0 + ib, nb, pi, j, ys + ib * R, Yt,
-                                     n3, xc, acc, p);
+      sym_load<true, TQ, TA>(qbase, ld, i0, nb, pi, j, qv);
     else
-      sym_batch<false, TQ, TA, TV, R>(qbase + static_cast<int64_t>(ib) * ld, ld, i0 + ib, nb, pi, j, ys + ib * R, Yt,
-                                      n3, xc, acc, p);
+      sym_load<false, TQ, TA>(qbase, ld, i0, nb, pi, j, qv);
+  }
+  for (int ib = 0; ib < nrows; ib += kSymBatch) {
+    TA p[kSymBatch][R];
+    if (kPre) {
+      TA qn[kSymBatch][V];
+      const int ibn = ib + kSymBatch;
+      const int nbn = (active && ibn < nrows) ? min(kSymBatch, nrows - ibn) : 0;
+      if (crossing) {
+        sym_load<true, TQ, TA>(qbase + static_cast<int64_t>(ibn) * ld, ld, i0 + ibn, nbn, pi, j, qn);
+        sym_fma<true, TQ, TA, TV, R>(qv, i0 + ib, pi, j, ys + ib * R, Yt, n3, xc, acc, p);
+      } else {
+        sym_load<false, TQ, TA>(qbase + static_cast<int64_t>(ibn) * ld, ld, i0 + ibn, nbn, pi, j, qn);
+        sym_fma<false, TQ, TA, TV, R>(qv, i0 + ib, pi, j, ys + ib * R, Yt, n3, xc, acc, p);
+      }
+#pragma unroll
+      for (int b = 0; b < kSymBatch; ++b)
+#pragma unroll
+        for (int v = 0; v < V; ++v) qv[b][v] = qn[b][v];
+    } else {
+      const int nb = active ? min(kSymBatch, nrows - ib) : 0;
+      if (crossing)
+        sym_batch<true, TQ, TA, TV, R>(qbase + static_cast<int64_t>(ib) * ld, ld, i0 + ib, nb, pi, j, ys + ib * R,
+                                       Yt, n3, xc, acc, p);
+      else
+        sym_batch<false, TQ, TA, TV, R>(qbase + static_cast<int64_t>(ib) * ld, ld, i0 + ib, nb, pi, j, ys + ib * R,
+                                        Yt, n3, xc, acc, p);
+    }
     // three halving steps (masks 32, 16, 8) leave row pi, summed over the 8
     // lanes that share the low 3 lane bits; masks 4, 2, 1 finish the wave sum
 #pragma unroll
@@ -417,8 +503,13 @@ void sym_product_rs(const TQ* M, int32_t ld, int32_t n, const TV* Yt, TV* out, D
   TA* colpart = take<TA>(sc, scratch, (static_cast<size_t>(nslabs) + nchunks) * per, s);
   TA* rowpart = colpart + static_cast<size_t>(nslabs) * per;
   if (ev) XM_HIP(hipEventRecord(ev->start, s));
-  hipLaunchKernelGGL((spmm_sym_kernel<TQ, TV, TA, R, RS>), dim3(nchunks, nslabs), dim3(kB), 0, s, M, ld, n, Yt,
-                     colpart, rowpart);
+  const int64_t active = sym_active_blocks(n, ld, C, RS);
+  if (sym_prefetch<TQ, R>(active))
+    hipLaunchKernelGGL((spmm_sym_kernel<TQ, TV, TA, R, RS, true>), dim3(nchunks, nslabs), dim3(kB), 0, s, M, ld, n,
+                       Yt, colpart, rowpart);
+  else
+    hipLaunchKernelGGL((spmm_sym_kernel<TQ, TV, TA, R, RS, false>), dim3(nchunks, nslabs), dim3(kB), 0, s, M, ld, n,
+                       Yt, colpart, rowpart);
   XM_LAUNCH_CHECK("spmm_sym_kernel");
   if (ev) XM_HIP(hipEventRecord(ev->stop, s));
   hipLaunchKernelGGL((spmm_sym_reduce_kernel<TA, TV, R, C, RS>), dim3(cdiv(per, 64)), dim3(kB), 0, s, colpart,
@@ -476,8 +567,10 @@ void launch_sym(const xm_problem* p, const TQ* Q, const TV* Yt, TV* out, hipStre
 //   3. per frame i: out[i] += sum_s A_rt[s] V[col s - 1] (col s >= 1).
 // One wavefront per frame, lanes over the frame's co-visible frames; the
 // factors are structure of arrays, so every factor load is coalesced across
-// the wave; Yt is first copied to rows padded to 16 bytes, so that a frame's
-// 3r values come in whole 16-byte loads.  Fixed-order wave sums: deterministic.
+// the wave (a block-major layout, each lane reading its block's 12 entries in
+// 16-byte pieces, measured slower: 0.168 -> 0.187 ms per FP32 r = 5 product);
+// Yt is first copied to rows padded to 16 bytes, so that a frame's 3r values
+// come in whole 16-byte loads.  Fixed-order wave sums: deterministic.
 
 template <typename T>
 struct V16;
@@ -514,6 +607,8 @@ __global__ void pad_rows_kernel(const T* __restrict__ Yt, int32_t N, T* __restri
 #endif
 constexpr int kFactU = XM_FACT_U;
 
+// One pass over the co-visibility pattern forms both A_rr Y^T and W = B^T Y^T
+// (they share the gather of the padded Yt rows).
 template <typename T, int R>
 __global__ __launch_bounds__(kB) void fact_rows_kernel(int32_t N, int64_t S, const int32_t* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col,
