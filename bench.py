@@ -33,8 +33,9 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6   # MI355X FP64, vector and matrix
 # HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain
 # copy kernel (profiles/hbm_traffic_sweep_update_large.md,
-# profiles/hbm_traffic_spmm_sym_f32_large.md); valid for the large workload and
-# the kernels as they were profiled -- re-measure after changing one.
+# profiles/hbm_traffic_spmm_sym_f32_large.md,
+# profiles/hbm_traffic_factored_product_large.md); valid for the large workload
+# and the kernels as they were profiled -- re-measure after changing one.
 PMC_TRAFFIC_BYTES = {("large", "sweep_update_kernel"): 0.948e9,
                      ("large", "spmm_sym_kernel (f32 Q)"): 1.921e9,
                      ("large", "spmm_sym_kernel (f32 G^-1, in the factored product)"): 0.219e9}

@@ -373,15 +373,13 @@ void read_partials(const double* dev, int blocks, int nq, double* out, hipStream
   sum_blocks(h, blocks, nq, out);
 }
 
-void read_partials2(const double* dev, int blocks, int nq, double* out, const double* dev2, int n2, double* out2,
+void read_partials2(const double* dev, int blocks, int nq, double* out, int64_t off2, int n2, double* out2,
                     hipStream_t s) {
-  const size_t n = static_cast<size_t>(blocks) * nq;
-  double* h = staging(n + n2);
-  XM_HIP(hipMemcpyAsync(h, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  XM_HIP(hipMemcpyAsync(h + n, dev2, n2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  double* h = staging(static_cast<size_t>(off2) + n2);
+  XM_HIP(hipMemcpyAsync(h, dev, (static_cast<size_t>(off2) + n2) * sizeof(double), hipMemcpyDeviceToHost, s));
   XM_HIP(hipStreamSynchronize(s));
   sum_blocks(h, blocks, nq, out);
-  for (int k = 0; k < n2; ++k) out2[k] = h[n + k];
+  for (int k = 0; k < n2; ++k) out2[k] = h[off2 + k];
 }
 
 CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int max_iter, double lanczos_tol,

@@ -344,20 +344,22 @@ __global__ __launch_bounds__(kB) void tcg_update_kernel(int32_t N, const T* __re
 }
 
 // The scalar step of a truncated-CG iteration, on the device so that the
-// update needs no host round trip: the partials of hess_kernel are added in
-// block order (as the host would), then alpha = z_r / <d, Hd>; if the curvature
-// is not positive or the step leaves the trust region, the boundary step tau
+// update needs no host round trip: one wavefront adds the partials of
+// hess_kernel (lane l takes blocks l, l + 64, ..., then a fixed xor tree:
+// deterministic), then alpha = z_r / <d, Hd>; if the curvature is not positive
+// or the step leaves the trust region, the boundary step tau
 // (|eta + tau d|_M = Delta) instead.  ctl = {step, mode (0 interior,
 // 1 boundary), <d,Hd>, <d,Md>, <eta,Md>, <eta,M eta>}.
-__global__ void tcg_step_kernel(const double* __restrict__ part, int nb, double z_r, double delta2,
-                                double* __restrict__ ctl) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(64) void tcg_step_kernel(const double* __restrict__ part, int nb, double z_r,
+                                                      double delta2, double* __restrict__ ctl) {
+  const int lane = threadIdx.x;
   double q[4];
   for (int j = 0; j < 4; ++j) {
     double acc = 0.0;
-    for (int b = 0; b < nb; ++b) acc += part[b * 4 + j];
-    q[j] = acc;
+    for (int b = lane; b < nb; b += 64) acc += part[b * 4 + j];
+    q[j] = wave_sum(acc);
   }
+  if (lane != 0) return;
   const double d_Hd = q[0], d_Pd = q[1], e_Pd = q[2], e_Pe = q[3];
   const double alpha = z_r / d_Hd;
   const double e_Pe_new = e_Pe + 2.0 * alpha * e_Pd + alpha * alpha * d_Pd;

@@ -178,8 +178,9 @@ AdjointResult adjoint(xm_problem* p, const double* R, const double* s, const dou
 
 // Host sum of per-block partials [blocks][nq] (fixed order) after a stream sync.
 void read_partials(const double* dev, int blocks, int nq, double* out, hipStream_t s);
-// the same for `dev`, and n2 plain values of dev2 into out2, in one round trip
-void read_partials2(const double* dev, int blocks, int nq, double* out, const double* dev2, int n2, double* out2,
+// the same for `dev`, and the n2 plain values at dev + off2 (off2 >= blocks *
+// nq) into out2, in one copy
+void read_partials2(const double* dev, int blocks, int nq, double* out, int64_t off2, int n2, double* out2,
                     hipStream_t s);
 // rows row0 .. row0 + nrows of Q (frame-index order) into out [nrows][3N]
 void get_q_rows(const xm_problem* p, int32_t row0, int32_t nrows, double* out, hipStream_t s);

@@ -54,7 +54,7 @@ struct Vecs {
       b->alloc(nv);
     for (DevBuf<T>* b : {&s, &s2, &gs, &ec, &etas, &Hetas, &ress, &ds, &Hds}) b->alloc(n);
     Sc.alloc(static_cast<size_t>(9) * n);
-    part.alloc(static_cast<size_t>(cdiv(n, kFrameBlock)) * 8);
+    part.alloc(static_cast<size_t>(cdiv(n, kFrameBlock)) * 8 + 8);
   }
 };
 
@@ -166,7 +166,9 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
   // preconditioner scale at the current point and <g, P g>
   double pscale = sums[3] / N, gpg = sums[4] * pscale;
   const size_t nvr = static_cast<size_t>(3) * N * r;
-  DevBuf<double> ctl(8);  // the device-side step of each truncated-CG iteration
+  // the device-side step of each truncated-CG iteration, after the hess
+  // kernel's partials in the same buffer (read back with them in one copy)
+  double* ctl = V.part.ptr + 4 * static_cast<size_t>(nb);
   int k = 0;
   for (k = 0; k < max_outer; ++k) {
     if (gnorm <= grad_tol * qbar * ynorm) {
@@ -194,11 +196,11 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
       // the step (interior alpha, or the boundary tau on non-positive
       // curvature / leaving the region) is chosen on the device, and the
       // update applied, before the one host round trip of the iteration
-      mf.tcg_step_update(r, V.s.ptr, V.part.ptr, z_r, Delta * Delta, ctl.ptr, V.dR.ptr, V.ds.ptr, V.HdR.ptr,
+      mf.tcg_step_update(r, V.s.ptr, V.part.ptr, z_r, Delta * Delta, ctl, V.dR.ptr, V.ds.ptr, V.HdR.ptr,
                          V.Hds.ptr, V.etaR.ptr, V.etas.ptr, V.HetaR.ptr, V.Hetas.ptr, V.resR.ptr, V.ress.ptr,
                          V.part.ptr, st);
       double hctl[6];
-      read_partials2(V.part.ptr, nb, 2, sums, ctl.ptr, 6, hctl, st);
+      read_partials2(V.part.ptr, nb, 2, sums, 4 * static_cast<int64_t>(nb), 6, hctl, st);
       if (hctl[1] != 0.0) {
         boundary = true;
         break;
