@@ -347,6 +347,9 @@ def main():
         txm2 = time.perf_counter() - t0
         R1, s1, rho1, i1 = o2["first"]
         R2, s2, rho2, i2 = o2["second"]
+        # the certificate's parts at the second optimum: the smallest eigenvalue
+        # of the scaled dual off rows(Y), the deflated block and their coupling
+        c2 = o2["problem"].certify(o2["Y"][: i2["r"]])
         kept = o2["keep"].cpu().numpy().astype(bool)
         bad = sc.gt["outlier"]
         out["xm2_variant"] = {
@@ -357,7 +360,9 @@ def main():
                       "eta": (rho1 - i1["cost"]) / (1 + abs(rho1) + abs(i1["cost"]))},
             "second": {"certified": bool(i2["certified"]), "rank": i2["r"], "cost": i2["cost"], "rho_hat": rho2,
                        "eta": (rho2 - i2["cost"]) / (1 + abs(rho2) + abs(i2["cost"])),
-                       "outer": i2["outer_iters"], "inner": i2["inner_iters"]}}
+                       "outer": i2["outer_iters"], "inner": i2["inner_iters"],
+                       "lambda_bound": c2["lambda_bound"], "lambda_complement_scaled": c2["lambda_min"],
+                       "deflated_block_min_scaled": c2["defl_min"], "coupling_scaled": c2["defl_cross"]}}
         log(f"xm2 variant: {out['xm2_variant']}")
         del o2
     if not args.no_cpu_baseline:

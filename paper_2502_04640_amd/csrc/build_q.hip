@@ -166,10 +166,30 @@ __global__ void segment_starts_kernel(const uint32_t* __restrict__ keys, const i
 #endif
 constexpr int kRedLanes = XM_RED_LANES;
 static_assert(kRedLanes == 8 || kRedLanes == 16 || kRedLanes == 32 || kRedLanes == 64, "lane groups of 8 to 64");
+// One 64-byte record per observation (landmark order) for the pair reduction:
+// keypoint u, weight w and w / sqrt(W_k) (W_k the weight sum of its landmark,
+// so that w_a w_b / W_k is the product of the two records' last entries).  A
+// pair's two gathers, which come from scattered landmarks in frame-pair order,
+// then touch one cache line each instead of four (keypoint, weight, landmark
+// index, landmark weight).
+__global__ void obs_record_kernel(int64_t n, const double* __restrict__ u_s, const double* __restrict__ w_s,
+                                  const int32_t* __restrict__ lm_s, const double* __restrict__ Wl,
+                                  double* __restrict__ rec) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
+  if (e >= n) return;
+  const double w = w_s[e];
+  double* r = rec + 8 * e;
+  r[0] = u_s[3 * e];
+  r[1] = u_s[3 * e + 1];
+  r[2] = u_s[3 * e + 2];
+  r[3] = w;
+  r[4] = w / sqrt(Wl[lm_s[e]]);
+  r[5] = r[6] = r[7] = 0.0;
+}
+
 __global__ __launch_bounds__(kB) void reduce_blocks_kernel(
     const int64_t* __restrict__ seg_start, const uint32_t* __restrict__ seg_key, int64_t S, int32_t N,
-    const uint64_t* __restrict__ vals, const double* __restrict__ u_s, const double* __restrict__ w_s,
-    const int32_t* __restrict__ lm_s, const double* __restrict__ Wl, const int32_t* __restrict__ pos, double* Q,
+    const uint64_t* __restrict__ vals, const double* __restrict__ rec, const int32_t* __restrict__ pos, double* Q,
     int32_t ld, double* Art, double* Att, double* fac) {
   const int64_t s = static_cast<int64_t>(blockIdx.x) * (kB / kRedLanes) + threadIdx.x / kRedLanes;
   const int lane = threadIdx.x % kRedLanes;
@@ -181,11 +201,14 @@ __global__ __launch_bounds__(kB) void reduce_blocks_kernel(
   for (int64_t q = lo + lane; q < hi; q += kRedLanes) {
     const uint64_t v = vals[q];
     const int64_t pa = static_cast<int64_t>(v >> 32), pb = static_cast<int64_t>(v & 0xffffffffull);
-    const double wa = w_s[pa], wb = w_s[pb];
-    const double Wk = Wl[lm_s[pa]];
-    const double coef = ((pa == pb) ? wa : 0.0) - wa * wb / Wk;
-    const double ha[4] = {u_s[3 * pa], u_s[3 * pa + 1], u_s[3 * pa + 2], 1.0};
-    const double hb[4] = {u_s[3 * pb], u_s[3 * pb + 1], u_s[3 * pb + 2], 1.0};
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2* ra = reinterpret_cast<const d2*>(rec + 8 * pa);
+    const d2* rb = reinterpret_cast<const d2*>(rec + 8 * pb);
+    const d2 a0 = ra[0], a1 = ra[1], a2 = ra[2], b0 = rb[0], b1 = rb[1], b2 = rb[2];
+    // w_a [a = b] - w_a w_b / W_k
+    const double coef = ((pa == pb) ? a1[1] : 0.0) - a2[0] * b2[0];
+    const double ha[4] = {a0[0], a0[1], a1[0], 1.0};
+    const double hb[4] = {b0[0], b0[1], b1[0], 1.0};
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const double ca = coef * ha[a];
@@ -1376,10 +1399,16 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
   P->Art.alloc(3 * S);
   P->Att.alloc(S);
   P->fac.alloc(15 * S);
-  hipLaunchKernelGGL(reduce_blocks_kernel, dim3(cdiv(S, kB / kRedLanes)), dim3(kB), 0, s, seg_start.ptr, seg_key.ptr,
-                     S, N, pvals.ptr, P->u_s.ptr, P->w_s.ptr, P->lm_s.ptr, P->Wl.ptr, P->pos.ptr, P->Q64.ptr,
-                     P->ld, P->Art.ptr, P->Att.ptr, P->fac.ptr);
-  XM_LAUNCH_CHECK("reduce_blocks_kernel");
+  {
+    DevBuf<double> rec(8 * static_cast<size_t>(n));
+    hipLaunchKernelGGL(obs_record_kernel, dim3(cdiv(n, kB)), dim3(kB), 0, s, n, P->u_s.ptr, P->w_s.ptr,
+                       P->lm_s.ptr, P->Wl.ptr, rec.ptr);
+    XM_LAUNCH_CHECK("obs_record_kernel");
+    hipLaunchKernelGGL(reduce_blocks_kernel, dim3(cdiv(S, kB / kRedLanes)), dim3(kB), 0, s, seg_start.ptr,
+                       seg_key.ptr, S, N, pvals.ptr, rec.ptr, P->pos.ptr, P->Q64.ptr, P->ld, P->Art.ptr, P->Att.ptr,
+                       P->fac.ptr);
+    XM_LAUNCH_CHECK("reduce_blocks_kernel");
+  }
   hipLaunchKernelGGL(check_diag_kernel, dim3(cdiv(N, kB)), dim3(kB), 0, s, P->row_ptr.ptr, P->col.ptr,
                      P->Att.ptr, N, flags.ptr);
   XM_LAUNCH_CHECK("check_diag_kernel");
