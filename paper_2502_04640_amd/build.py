@@ -57,6 +57,46 @@ def build(verbose: bool = False, out: str = OUT, build_dir: str = BUILD, defines
     return out
 
 
+# Host-code sanitizer build (AddressSanitizer + UndefinedBehaviorSanitizer on
+# the host side of every source; device code as usual), and the driver that
+# runs every entry point of the C ABI under it (tests/sanitize/host_driver.cpp).
+HOSTSAN_CC = ["-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+HOSTSAN_LD = ["-fsanitize=address", "-fsanitize=undefined", "-fno-gpu-sanitize"]
+HOSTSAN_LIB = os.path.join(HERE, "libxm_hostsan.so")
+HOSTSAN_DRIVER = os.path.join(ROOT, "tests", "sanitize", "xm_hostsan_driver")
+
+
+def build_hostsan(verbose: bool = False) -> str:
+    bdir = os.path.join(BUILD, "hostsan")
+    os.makedirs(bdir, exist_ok=True)
+
+    def cc(src_path, obj):
+        cmd = [HIPCC, "-x", "hip"] + FLAGS + HOSTSAN_CC + ["-c", src_path, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src_path}:\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8"))))
+    with ThreadPoolExecutor(workers) as ex:
+        objs = list(ex.map(lambda s: cc(os.path.join(CSRC, s), os.path.join(bdir, s + ".o")), SOURCES))
+    link = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950"] + HOSTSAN_LD + ["-o", HOSTSAN_LIB] + objs
+    r = subprocess.run(link, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    drv = cc(os.path.join(ROOT, "tests", "sanitize", "host_driver.cpp"), os.path.join(bdir, "host_driver.o"))
+    exe = [HIPCC, "--offload-arch=gfx950"] + HOSTSAN_LD + ["-o", HOSTSAN_DRIVER, drv, "-L" + HERE, "-lxm_hostsan",
+                                                         "-Wl,-rpath,$ORIGIN/../../paper_2502_04640_amd"]
+    r = subprocess.run(exe, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"driver link failed:\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print("built", HOSTSAN_LIB, "and", HOSTSAN_DRIVER)
+    return HOSTSAN_DRIVER
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    if "--hostsan" in sys.argv:
+        build_hostsan(verbose=True)
     sys.exit(0)
