@@ -135,6 +135,55 @@ def test_build_q_errors():
                    torch.from_numpy(np.r_[b.u, b.u]).cuda(), torch.from_numpy(np.r_[b.w, b.w]).cuda())
 
 
+def _two_clusters(bridge_w):
+    # two 30-frame scenes joined by one landmark seen by frame 3 of the first
+    # and frame 40 of the second: the grounded Laplacian's weakest link is that
+    # landmark's conductance w_a w_b / (w_a + w_b) = bridge_w / 2
+    a = scenes.random_scene(30, 600, L=4, sigma=0.02, seed=61)
+    b = scenes.random_scene(30, 600, L=4, sigma=0.02, seed=62)
+    rng = np.random.default_rng(5)
+    fr = np.r_[a.frame, b.frame + 30, [3, 40]].astype(np.int32)
+    lm = np.r_[a.landmark, b.landmark + 600, [1200, 1200]].astype(np.int32)
+    u = np.r_[a.u, b.u, rng.normal(size=(2, 3))]
+    w = np.r_[a.w, b.w, [bridge_w, bridge_w]]
+    return 60, 1201, fr, lm, u, w
+
+
+@pytest.mark.parametrize("bridge_w", [1e-3, 1e-6])
+def test_build_q_weakly_linked_clusters(bridge_w):
+    # the sweep's pivot test (a pivot of at most 1e-11 of the largest diagonal
+    # entry of the grounded Laplacian reads as a disconnected view graph) must
+    # not refuse a graph whose weakest link is small but far above FP64 noise.
+    # Q is well conditioned whatever the link (the oracle's Q with the anchor
+    # moved into the other cluster agrees to 1e-14); G^{-1} is not: its
+    # condition is about (largest diagonal entry ~ 1e2) / (link conductance
+    # bridge_w / 2), and the explicit inverse carries that into the correction
+    # term A_rt G^{-1} A_rt^T, whose large entries cancel down to Q's.  Bar:
+    # 1e-11 / bridge_w relative (FP64 eps x condition x the cancellation, with
+    # margin), at least 1e-10.
+    _say(f"case: weakly linked clusters, bridge weight {bridge_w}")
+    xm = _xm()
+    N, M, fr, lm, u, w = _two_clusters(bridge_w)
+    P = xm.build_Q(N, M, torch.from_numpy(fr).cuda(), torch.from_numpy(lm).cuda(), torch.from_numpy(u).cuda(),
+                   torch.from_numpy(w).cuda(), keep=())
+    Q = P.Q_rows(0, 3 * N).cpu().numpy()
+    Qo = odm.q_block_elimination(N, M, fr, lm, u, w)
+    rel = np.abs(Q - Qo).max() / np.abs(Qo).max()
+    _say(f"  Q relative error {rel:.2e} (bar {max(1e-10, 1e-11 / bridge_w):.1e})")
+    assert rel <= max(1e-10, 1e-11 / bridge_w)
+
+
+def test_build_q_numerically_disconnected_link_is_refused():
+    # a link of conductance 5e-15 (below the FP64 noise of the inversion,
+    # about 1e-12 of the largest diagonal entry) cannot be told from none
+    _say("case: numerically disconnected clusters -> XM_EGRAPH")
+    xm = _xm()
+    N, M, fr, lm, u, w = _two_clusters(1e-14)
+    with pytest.raises(xm.XMError, match="XM_EGRAPH"):
+        xm.build_Q(N, M, torch.from_numpy(fr).cuda(), torch.from_numpy(lm).cuda(), torch.from_numpy(u).cuda(),
+                   torch.from_numpy(w).cuda(), keep=())
+
+
 @pytest.mark.parametrize("r", [1, 3, 5, 8])
 def test_spmm_parity(r):
     _say(f"case: spmm r={r}")
