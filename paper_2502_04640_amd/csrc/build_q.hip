@@ -157,7 +157,8 @@ __global__ void segment_starts_kernel(const uint32_t* __restrict__ keys, const i
 }
 
 // One group of kRedLanes lanes per frame pair: sum the 4x4 contributions of
-// its observation pairs (strided over the group, then a fixed xor tree), write
+// its observation pairs (strided over the group, then a fixed tree by
+// recursive halving, so each lane ends with one of the 16 sums), write
 // the rotation block into Q and the A_rt / A_tt entries.  A frame pair holds
 // about ten observation pairs on average (the diagonal ones hundreds), so a
 // group narrower than the wavefront wastes fewer lanes and reduction steps.
@@ -165,7 +166,7 @@ __global__ void segment_starts_kernel(const uint32_t* __restrict__ keys, const i
 #define XM_RED_LANES 16
 #endif
 constexpr int kRedLanes = XM_RED_LANES;
-static_assert(kRedLanes == 8 || kRedLanes == 16 || kRedLanes == 32 || kRedLanes == 64, "lane groups of 8 to 64");
+static_assert(kRedLanes == 16 || kRedLanes == 32 || kRedLanes == 64, "lane groups of 16 to 64");
 // One 64-byte record per observation (landmark order) for the pair reduction:
 // keypoint u, weight w and w / sqrt(W_k) (W_k the weight sum of its landmark,
 // so that w_a w_b / W_k is the product of the two records' last entries).  A
@@ -216,30 +217,23 @@ __global__ __launch_bounds__(kB) void reduce_blocks_kernel(
       for (int b = 0; b < 4; ++b) acc[a * 4 + b] += ca * hb[b];
     }
   }
-#pragma unroll
-  for (int q = 0; q < 16; ++q)
-#pragma unroll
-    for (int off = kRedLanes / 2; off >= 1; off >>= 1) acc[q] += __shfl_xor(acc[q], off, kRedLanes);
-  if (lane == 0) {
-    const uint32_t key = seg_key[s];
-    const int64_t i = key / static_cast<uint32_t>(N), j = key % static_cast<uint32_t>(N);
+  // the 16 sums over the group: lane l with l % (kRedLanes / 16) = 0 holds
+  // entry (a, b) = (q / 4, q % 4) of the 4x4 block, q = group_split_index(l)
+  const double v = group_split_sum<16, kRedLanes>(acc, lane);
+  if ((lane & (kRedLanes / 16 - 1)) != 0) return;
+  const int q = group_split_index<16, kRedLanes>(lane), a = q >> 2, b = q & 3;
+  if (a < 3 && b < 3) {
     if (Q) {  // Q is stored in the frame order: block (pos[i], pos[j])
-      double* Qb = Q + (3 * static_cast<int64_t>(pos[i])) * ld + 3 * static_cast<int64_t>(pos[j]);
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) Qb[a * static_cast<int64_t>(ld) + b] = acc[a * 4 + b];
+      const uint32_t key = seg_key[s];
+      const int64_t i = key / static_cast<uint32_t>(N), j = key % static_cast<uint32_t>(N);
+      Q[(3 * static_cast<int64_t>(pos[i]) + a) * ld + 3 * static_cast<int64_t>(pos[j]) + b] = v;
     }
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) fac[(3 * a + b) * S + s] = acc[a * 4 + b];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) fac[(9 + a) * S + s] = acc[4 * a + 3];
-    Art[3 * s] = acc[3];
-    Art[3 * s + 1] = acc[7];
-    Art[3 * s + 2] = acc[11];
-    Att[s] = acc[15];
+    fac[(3 * a + b) * S + s] = v;
+  } else if (a < 3) {
+    fac[(9 + a) * S + s] = v;
+    Art[3 * s + a] = v;
+  } else if (b == 3) {
+    Att[s] = v;
   }
 }
 

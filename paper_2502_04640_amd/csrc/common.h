@@ -106,6 +106,69 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+template <int NV>
+struct Pow2Up {  // smallest power of two >= NV
+  static constexpr int v = NV <= 1 ? 1 : 2 * Pow2Up<(NV + 1) / 2>::v;
+};
+template <>
+struct Pow2Up<1> {
+  static constexpr int v = 1;
+};
+template <int P>
+struct Log2 {  // log2 of a power of two
+  static constexpr int v = 1 + Log2<P / 2>::v;
+};
+template <>
+struct Log2<1> {
+  static constexpr int v = 0;
+};
+
+// Sums each of NP per-lane values (NP a power of two, at most W) over aligned
+// groups of W lanes by recursive halving: at the exchange over lane distance o
+// a lane keeps the half of its values that its partner sends away and adds
+// the partner's copy of it, so the NP sums take NP - 1 exchanges, plus
+// log2(W / NP) for the last value, instead of NP log2(W).  `lane` is the
+// index within the group; it returns the total of value
+// group_split_index<NP, W>(lane), and the lanes whose bits below W / NP are
+// zero hold each index once.  Every total is summed over the lane bits from
+// the highest down, as wave_sum does, so the results are bitwise those of NP
+// separate wave_sum calls.
+template <int NP, int W, typename T>
+__device__ __forceinline__ T group_split_sum(T (&v)[NP], int lane) {
+  static_assert(NP >= 1 && (NP & (NP - 1)) == 0 && NP <= W && W <= 64 && (W & (W - 1)) == 0,
+                "NP and W: powers of two, NP <= W <= 64");
+  constexpr int kSteps = Log2<NP>::v, kAll = Log2<W>::v;
+#pragma unroll
+  for (int st = 0; st < kSteps; ++st) {
+    const int o = (W / 2) >> st, h = NP >> (st + 1);
+    const bool b = (lane & o) != 0;
+#pragma unroll
+    for (int k = 0; k < NP / 2; ++k) {
+      if (k < h) {
+        // the empty asm hands the two values over as opaque registers, so the
+        // selects stay selects of values (not of an index into v, which the
+        // compiler would expand into a select chain over the whole array)
+        T lo = v[k], hi = v[k + h];
+        asm("" : "+v"(lo), "+v"(hi));
+        const T send = b ? lo : hi;
+        const T keep = b ? hi : lo;
+        v[k] = keep + __shfl_xor(send, o, W);
+      }
+    }
+  }
+  T t = v[0];
+#pragma unroll
+  for (int st = kSteps; st < kAll; ++st) t += __shfl_xor(t, (W / 2) >> st, W);
+  return t;
+}
+template <int NP, int W>
+__device__ __forceinline__ int group_split_index(int lane) {
+  int idx = 0;
+#pragma unroll
+  for (int st = 0; st < Log2<NP>::v; ++st) idx += (lane & ((W / 2) >> st)) ? (NP >> (st + 1)) : 0;
+  return idx;
+}
+
 // Deterministic block reduction of NQ doubles per thread (fixed tree order).
 // `lds` must hold NQ * (blockDim.x / 64) doubles.  Result valid in thread 0.
 template <int NQ>

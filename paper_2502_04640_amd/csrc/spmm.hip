@@ -608,7 +608,9 @@ __global__ void pad_rows_kernel(const T* __restrict__ Yt, int32_t N, T* __restri
 constexpr int kFactU = XM_FACT_U;
 
 // One pass over the co-visibility pattern forms both A_rr Y^T and W = B^T Y^T
-// (they share the gather of the padded Yt rows).
+// (they share the gather of the padded Yt rows).  The column indices of a
+// step's blocks are loaded one step ahead, so a step waits for one round trip
+// (its factor loads and its gathers, issued together), not two.
 template <typename T, int R>
 __global__ __launch_bounds__(kB) void fact_rows_kernel(int32_t N, int64_t S, const int32_t* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col,
@@ -616,26 +618,37 @@ __global__ __launch_bounds__(kB) void fact_rows_kernel(int32_t N, int64_t S, con
                                                        T* __restrict__ out, T* __restrict__ W) {
   constexpr int RP = padded_row<T, R>();
   constexpr int K = V16<T>::K;
+  constexpr int NP = Pow2Up<4 * R>::v;
   typedef typename V16<T>::type vec;
   const int i = blockIdx.x * (kB / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= N) return;  // whole wavefronts only
-  T ao[3][R], aw[R];
+  // acc[c * R + a]: (A_rr Y^T)[3i + c][a]; acc[3R + a]: W[i - 1][a]; zero padding up to NP
+  T acc[NP];
 #pragma unroll
-  for (int a = 0; a < R; ++a) {
-    aw[a] = T(0);
+  for (int q = 0; q < NP; ++q) acc[q] = T(0);
+  const int32_t beg = row_ptr[i], end = row_ptr[i + 1];
+  int32_t cn[kFactU];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ao[c][a] = T(0);
+  for (int u = 0; u < kFactU; ++u) {
+    const int32_t s = beg + lane + 64 * u;
+    cn[u] = s < end ? col[s] : -1;
   }
-  const int32_t end = row_ptr[i + 1];
-  for (int32_t s0 = row_ptr[i] + lane; s0 < end; s0 += 64 * kFactU) {
+  for (int32_t s0 = beg + lane; s0 < end; s0 += 64 * kFactU) {
+    int32_t cc[kFactU];
+#pragma unroll
+    for (int u = 0; u < kFactU; ++u) {
+      const int32_t sn = s0 + 64 * (u + kFactU);
+      cc[u] = cn[u];
+      cn[u] = sn < end ? col[sn] : -1;  // the next step's column, in flight during this one
+    }
     T y[kFactU][RP], m[kFactU][9], t[kFactU][3];
 #pragma unroll
     for (int u = 0; u < kFactU; ++u) {
       const int32_t s = s0 + 64 * u;
-      const bool ok = s < end;  // a block past the row end contributes zero
+      const bool ok = cc[u] >= 0;  // a block past the row end contributes zero
       const int32_t sc = ok ? s : s0;
-      const vec* yp = reinterpret_cast<const vec*>(Ytp + static_cast<int64_t>(col[sc]) * RP);
+      const vec* yp = reinterpret_cast<const vec*>(Ytp + static_cast<int64_t>(ok ? cc[u] : 0) * RP);
 #pragma unroll
       for (int q = 0; q < RP / K; ++q) {
         const vec v = yp[q];
@@ -655,48 +668,52 @@ __global__ __launch_bounds__(kB) void fact_rows_kernel(int32_t N, int64_t S, con
         for (int a = 0; a < R; ++a) {
           const T yv = y[u][d * R + a];
 #pragma unroll
-          for (int c = 0; c < 3; ++c) ao[c][a] += m[u][3 * c + d] * yv;
-          aw[a] += t[u][d] * yv;
+          for (int c = 0; c < 3; ++c) acc[c * R + a] += m[u][3 * c + d] * yv;
+          acc[3 * R + a] += t[u][d] * yv;
         }
   }
-#pragma unroll
-  for (int a = 0; a < R; ++a) {
-    aw[a] = wave_sum(aw[a]);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ao[c][a] = wave_sum(ao[c][a]);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int a = 0; a < R; ++a) out[(3 * static_cast<int64_t>(i) + c) * R + a] = ao[c][a];
-    if (i > 0) {
-#pragma unroll
-      for (int a = 0; a < R; ++a) W[static_cast<int64_t>(i - 1) * R + a] = aw[a];
-    }
+  // the 4R sums, each lane writing the one it holds
+  const T v = group_split_sum<NP, 64>(acc, lane);
+  const int q = group_split_index<NP, 64>(lane);
+  if ((lane & (64 / NP - 1)) == 0) {
+    if (q < 3 * R) out[3 * static_cast<int64_t>(i) * R + q] = v;
+    else if (q < 4 * R && i > 0) W[static_cast<int64_t>(i - 1) * R + (q - 3 * R)] = v;
   }
 }
 
+// out[i] += sum_s A_rt[s] V[col s - 1], the column indices one step ahead as above
 template <typename T, int R>
 __global__ __launch_bounds__(kB) void fact_cols_kernel(int32_t N, int64_t S, const int32_t* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col,
                                                        const T* __restrict__ fac, const T* __restrict__ V,
                                                        T* __restrict__ out) {
+  constexpr int NP = Pow2Up<3 * R>::v;
   const int i = blockIdx.x * (kB / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= N) return;  // whole wavefronts only
-  T acc[3][R];
+  T acc[NP];  // acc[c * R + a]: out[3i + c][a]; zero padding up to NP
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int q = 0; q < NP; ++q) acc[q] = T(0);
+  const int32_t beg = row_ptr[i], end = row_ptr[i + 1];
+  int32_t cn[kFactU];
 #pragma unroll
-    for (int a = 0; a < R; ++a) acc[c][a] = T(0);
-  const int32_t end = row_ptr[i + 1];
-  for (int32_t s0 = row_ptr[i] + lane; s0 < end; s0 += 64 * kFactU) {
+  for (int u = 0; u < kFactU; ++u) {
+    const int32_t s = beg + lane + 64 * u;
+    cn[u] = s < end ? col[s] : 0;
+  }
+  for (int32_t s0 = beg + lane; s0 < end; s0 += 64 * kFactU) {
+    int32_t cc[kFactU];
+#pragma unroll
+    for (int u = 0; u < kFactU; ++u) {
+      const int32_t sn = s0 + 64 * (u + kFactU);
+      cc[u] = cn[u];
+      cn[u] = sn < end ? col[sn] : 0;
+    }
     T v[kFactU][R], b[kFactU][3];
 #pragma unroll
     for (int u = 0; u < kFactU; ++u) {
       const int32_t s = s0 + 64 * u;
-      const int j = (s < end) ? col[s] : 0;
+      const int j = cc[u];
       const bool ok = j > 0;  // frame 0 is anchored (no column of B); past the end: zero
       const T* vp = V + static_cast<int64_t>(ok ? j - 1 : 0) * R;
 #pragma unroll
@@ -709,18 +726,11 @@ __global__ __launch_bounds__(kB) void fact_cols_kernel(int32_t N, int64_t S, con
 #pragma unroll
       for (int a = 0; a < R; ++a)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c][a] += b[u][c] * v[u][a];
+        for (int c = 0; c < 3; ++c) acc[c * R + a] += b[u][c] * v[u][a];
   }
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int a = 0; a < R; ++a) acc[c][a] = wave_sum(acc[c][a]);
-  if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int a = 0; a < R; ++a) out[(3 * static_cast<int64_t>(i) + c) * R + a] += acc[c][a];
-  }
+  const T v = group_split_sum<NP, 64>(acc, lane);
+  const int q = group_split_index<NP, 64>(lane);
+  if ((lane & (64 / NP - 1)) == 0 && q < 3 * R) out[3 * static_cast<int64_t>(i) * R + q] += v;
 }
 
 // the factors of one precision: the sparse blocks (structure of arrays) and -G^{-1}

@@ -352,8 +352,14 @@ def test_round_matches_oracle_on_rank5_input():
     assert np.abs(sg.cpu().numpy() - sh_o).max() <= 1e-9 * np.abs(sh_o).max()
 
 
-def test_escape_from_spurious_minimum():
-    _say("case: staircase escape from a rank-3 local minimum")
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+def test_escape_from_spurious_minimum(compute):
+    # Thm. "Descent Direction": from a second-order critical point of rank 3
+    # whose dual is not PSD the staircase moves to rank 4 along the least
+    # eigenvector and reaches the global optimum.  FP32 solves compare the
+    # escape's cost change with FP64 products as well (the FP64 stage), so they
+    # must escape the same way; bars as for their end-to-end solves.
+    _say(f"case: staircase escape from a rank-3 local minimum ({compute})")
     xm = _xm()
     from oracle import rtr as ortr
     sc = scenes.random_scene(8, 40, L=3, sigma=0.5, seed=0)
@@ -367,12 +373,12 @@ def test_escape_from_spurious_minimum():
     assert c["lambda_min"] < -1e-3 * c["qbar"]
     _, _, ofin = ost.staircase(Qo, R0=R, s0=s, r_max=7, grad_tol=1e-11)
     P = _build(sc)
-    Y, ginfo = P.solve(xm.SolveOptions(compute="f64", r_max=7, grad_tol=1e-11),
+    Y, ginfo = P.solve(xm.SolveOptions(compute=compute, r_max=7, grad_tol=1e-11),
                        Y0=torch.from_numpy(omf.to_U(R, s)).cuda())
     assert ginfo["stair_steps"] >= 1
     assert ginfo["certified"] == 1 and ofin["certified"]
     assert ginfo["cost"] < info["cost"]
-    assert _gap(ginfo["cost"], ofin["cost"]) <= 1e-8
+    assert _gap(ginfo["cost"], ofin["cost"]) <= (1e-8 if compute == "f64" else 1e-5)
 
 
 @pytest.mark.parametrize("cfg", ["diff"])
