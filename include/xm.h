@@ -293,17 +293,20 @@ typedef struct {
                           XM_BF16: as XM_F32 with the BF16-stored Q for the
                           first stage's Hessian products */
   double grad_tol;     /* stop when ||grad|| <= grad_tol * qbar * ||Y||_F
-                          (<= 0: 1e-9 for XM_F64, 3e-7 otherwise); a reduced-
-                          precision stage also stops at the arithmetic's floor
-                          (6 consecutive rejected trust-region steps while
-                          ||grad|| <= 30 grad_tol * qbar * ||Y||_F).  XM_F32 /
-                          XM_BF16 solves then continue in an FP64 stage (FP64
-                          iterate, manifold arithmetic and gradient products;
-                          truncated-CG products with the FP32 Q)
-                          down to grad_tol / 300, the FP64 default: the dual
-                          certificate needs a point that close to stationary,
-                          which a reduced-precision iterate's own rounding does
-                          not allow */
+                          (<= 0: 1e-9 for XM_F64, 1e-6 otherwise); a stage
+                          also stops at the arithmetic's floor (6 consecutive
+                          rejected trust-region steps while ||grad|| <= 30
+                          grad_tol * qbar * ||Y||_F, or 12 at any gradient).
+                          XM_F32 / XM_BF16 solves then continue in an FP64
+                          stage (FP64 iterate, manifold arithmetic and
+                          gradient products; truncated-CG products with the
+                          FP32 Q) down to grad_tol / 1000.  A point whose
+                          certificate fails only through the stationarity
+                          terms of its bound is polished at the same rank
+                          with a 100x, then 10^4 x tighter tolerance.  The
+                          FP64 stage exists because the dual certificate needs
+                          a point closer to stationary than a reduced-precision
+                          iterate's own rounding allows */
   double cert_tol;     /* certified iff the lower bound on lambda_min(Z) >= -cert_tol * qbar
                           (<= 0: 1e-7 for XM_F64, 1e-5 otherwise) */
   int32_t max_outer;   /* trust-region iterations per rank (<= 0: 1000) */

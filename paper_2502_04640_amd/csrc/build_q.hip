@@ -857,7 +857,7 @@ __global__ void to_bf16_kernel(const double* __restrict__ in, int64_t n, uint16_
 // rows read on clustered scenes).  The order is a breadth-first search from
 // the anchored frame 0 in which each new level is sorted by the position of its
 // first discoverer, then by frame index: deterministic.
-constexpr int kGroup = 16;
+constexpr int kGroup = kFrameGroup;
 constexpr int32_t kUnset = 0x7f7f7f7f;  // key of a frame not reached yet (memset byte 0x7f)
 
 // key[u] = min position (in the order) of a frontier frame adjacent to u, for unplaced u
@@ -954,13 +954,14 @@ __global__ __launch_bounds__(kB) void group_count_kernel(int32_t N, const int32_
 // uid[k]: the union of group g in increasing frame order (k from ustart[g]);
 // coef[k][f][q] = A_rt[3 order[g kGroup + f] + q][uid[k]] for q < 3 (rows of 4,
 // the last one 0; zero where frame f does not see uid[k]; coef is cleared
-// beforehand)
+// beforehand); lidx[s] = k - ustart[g] for the stored block s = (i, uid[k]) of
+// a frame i of the group, -1 for s = (i, 0)
 __global__ __launch_bounds__(kB) void group_fill_kernel(int32_t N, const int32_t* __restrict__ order,
                                                         const int32_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ col,
                                                         const double* __restrict__ Art,
                                                         const int64_t* __restrict__ ustart, int32_t* uid,
-                                                        double* coef) {
+                                                        double* coef, int32_t* lidx) {
   extern __shared__ uint32_t bits[];
   const int nw = (N + 31) / 32;
   int* wpre = reinterpret_cast<int*>(bits + nw);  // exclusive prefix of set bits per word
@@ -990,9 +991,13 @@ __global__ __launch_bounds__(kB) void group_fill_kernel(int32_t N, const int32_t
     const int i = order[a];
     for (int32_t s = row_ptr[i] + threadIdx.x; s < row_ptr[i + 1]; s += kB) {
       const int j = col[s];
-      if (j == 0) continue;
+      if (j == 0) {
+        lidx[s] = -1;
+        continue;
+      }
       const int w = j >> 5;
       const int64_t k = base + wpre[w] + __popc(bits[w] & ((1u << (j & 31)) - 1u));
+      lidx[s] = static_cast<int32_t>(k - base);
 #pragma unroll
       for (int q = 0; q < 3; ++q) coef[(k * kGroup + f) * 4 + q] = Art[3 * static_cast<int64_t>(s) + q];
     }
@@ -1506,19 +1511,34 @@ std::unique_ptr<xm_problem> build_problem(int32_t N, int32_t M, int64_t n_obs, c
     const int32_t ngroups = static_cast<int32_t>(cdiv(N, kGroup));
     const int nw = (N + 31) / 32;
     const size_t lds = 2 * static_cast<size_t>(nw) * sizeof(uint32_t);
-    DevBuf<int64_t> ucount(ngroups), ustart(ngroups + 1);
+    DevBuf<int64_t> ucount(ngroups);
+    DevBuf<int64_t>& ustart = P->grp_ustart;
+    DevBuf<int32_t>& uid = P->grp_uid;
+    ustart.alloc(ngroups + 1);
     hipLaunchKernelGGL(group_count_kernel, dim3(ngroups), dim3(kB), lds, s, N, P->order.ptr, P->row_ptr.ptr,
                        P->col.ptr, ucount.ptr);
     XM_LAUNCH_CHECK("group_count_kernel");
     exclusive_scan_i64(ucount.ptr, ustart.ptr, ngroups, s);
-    int64_t total = 0;
-    XM_HIP(hipMemcpy(&total, ustart.ptr + ngroups, sizeof(int64_t), hipMemcpyDeviceToHost));
-    DevBuf<int32_t> uid(std::max<int64_t>(total, 1));
+    std::vector<int64_t> hcount(ngroups + 1);
+    XM_HIP(hipMemcpyAsync(hcount.data(), ustart.ptr, (ngroups + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    XM_HIP(hipStreamSynchronize(s));
+    const int64_t total = hcount[ngroups];
+    int64_t maxu = 0;
+    for (int32_t g = 0; g < ngroups; ++g) maxu = std::max(maxu, hcount[g + 1] - hcount[g]);
+    uid.alloc(std::max<int64_t>(total, 1));
+    P->lidx.alloc(std::max<int64_t>(P->nnzb, 1));
     DevBuf<double> coef(std::max<int64_t>(total, 1) * 4 * kGroup);
     XM_HIP(hipMemsetAsync(coef.ptr, 0, coef.bytes(), s));
     hipLaunchKernelGGL(group_fill_kernel, dim3(ngroups), dim3(kB), lds, s, N, P->order.ptr, P->row_ptr.ptr,
-                       P->col.ptr, P->Art.ptr, ustart.ptr, uid.ptr, coef.ptr);
+                       P->col.ptr, P->Art.ptr, ustart.ptr, uid.ptr, coef.ptr, P->lidx.ptr);
     XM_LAUNCH_CHECK("group_fill_kernel");
+    P->grp_maxu = static_cast<int32_t>(maxu);
+    {
+      int dev = 0, lmax = 0;
+      XM_HIP(hipGetDevice(&dev));
+      XM_HIP(hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      P->lds_max = static_cast<size_t>(std::max(lmax, 0));
+    }
     // workgroup lists of the two passes: tile-major (group, column tile) pairs;
     // the Q pass only takes the pairs with columns right of the group's first row
     auto tile_list = [&](int32_t K, bool upper, DevBuf<int32_t>& ts) {

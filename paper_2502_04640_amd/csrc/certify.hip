@@ -593,6 +593,7 @@ CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int ma
   // v^T Z v = (D^{1/2} v)^T Zs (D^{1/2} v) and d_min |v|^2 <= |D^{1/2} v|^2 <= d_max |v|^2
   out.lambda_bound = full * (full >= 0.0 ? p->dmin : p->dmax);
   out.certified = out.lambda_bound >= -tol * qbar;
+  out.complement_ok = lo * (lo >= 0.0 ? p->dmin : p->dmax) >= -tol * qbar;
   if (v_out) {
     const int m = static_cast<int>(y.size());
     DevBuf<double> yd(m);

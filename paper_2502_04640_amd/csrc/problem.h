@@ -49,6 +49,14 @@ struct xm_problem {
   // A_rt[3i+a][j]; rows 12+a: A_rt[3j+a][i] (the transposed block's entry)
   xm::DevBuf<double> fac;
   xm::DevBuf<double> fact_scratch;   // padded Y^T, W and V of the factored product
+  // groups of 16 frames consecutive in the Cuthill-McKee order: the union of
+  // each group's co-visible frames j >= 1 (frame indices, increasing, from
+  // grp_ustart[g]), the largest union, and per stored block s the position of
+  // col[s] in its row's group union (-1 for frame 0); grp_maxu < 0: not built
+  xm::DevBuf<int32_t> grp_uid, lidx;
+  xm::DevBuf<int64_t> grp_ustart;
+  int32_t grp_maxu = -1;
+  size_t lds_max = 0;  // LDS bytes a workgroup may take on the build's device
   xm::DevBuf<double> perm_scratch;   // Y^T and Y^T Q in the frame order (dense products)
   xm::DevBuf<float> mixed_scratch;   // FP32 copies of an FP64 operand and result (mixed products)
   // FP32 copies of the factors (with XM_KEEP_F32): fac as above, -G^{-1}
@@ -85,6 +93,10 @@ struct xm_problem {
 };
 
 namespace xm {
+
+// frames per group (consecutive in the Cuthill-McKee order) of the assembly's
+// correction products and of the grouped passes of the factored product
+constexpr int kFrameGroup = 16;
 
 // Temporary device memory of one Y Q product.  Without a fixed region (the
 // normal entry points) the handle's grow-only buffers serve, allocated on
@@ -146,6 +158,9 @@ struct CertResult {
   double defl_min = 0, defl_cross = 0;
   int iters = 0;
   bool certified = false;
+  // the bound from the complement of rows(Y) alone (Lanczos lower bound, no
+  // deflated block or coupling) passes the threshold
+  bool complement_ok = false;
 };
 CertResult certify_yt(xm_problem* p, const double* Yt, int r, double tol, int max_iter, double lanczos_tol,
                       double* v_out, hipStream_t s);

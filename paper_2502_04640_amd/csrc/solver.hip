@@ -16,7 +16,8 @@
 // sqrt(3N)/8; rho carries the usual max(1,|f|) 1e3 eps regularisation.
 // Stop when |grad| <= grad_tol qbar |Y|, or, at the precision floor of
 // reduced-precision products, after 6 rejected steps in a row with |grad|
-// within 30 grad_tol qbar |Y|.  A reduced-precision solve then continues from
+// within 30 grad_tol qbar |Y|, or after 12 rejected steps in a row at any
+// gradient (stagnation).  A reduced-precision solve then continues from
 // that point in an FP64 stage: the iterate, the manifold arithmetic and the
 // gradient products in FP64, the truncated-CG Hessian-vector products in
 // FP32 (an inexact-Newton / iterative-refinement split:
@@ -28,7 +29,10 @@
 // which stays accurate where f(Y+) - f(Y) would cancel.  The staircase escape
 // follows Theorem "Descent Direction": block k of [Y; alpha v^T] is
 // re-orthonormalised (scale kept), alpha halved until the cost drops, at most
-// 40 times.
+// 40 times.  It is taken only when the dual has a negative direction off
+// rows(Y): when the certificate's bound fails through its stationarity terms
+// alone, the point is instead polished at the same rank with a 100x (then
+// 10^4 x) tighter gradient tolerance.
 #include <chrono>
 #include <cmath>
 #include <memory>
@@ -264,6 +268,15 @@ RtrOut rtr(xm_problem* p, Vecs<T>& V, int r, xm_dtype qg, xm_dtype qh, const xm_
       ++k;
       break;
     }
+    // stagnation: twice as many rejections in a row (the radius down by 4^12)
+    // at any gradient; the products' rounding decides every ratio there
+    // (a reduced-precision stage hands its point to the FP64 stage)
+    if (!accept && rejections >= 2 * floor_rejections) {
+      out.floor = true;
+      out.converged = gnorm <= floor_tol * qbar * ynorm;
+      ++k;
+      break;
+    }
     if (accept) {
       rejections = 0;
       ++out.accepted;
@@ -364,9 +377,13 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   constexpr bool f64 = std::is_same<T, double>::value;
   const xm_dtype qg = f64 ? XM_F64 : XM_F32;
   const xm_dtype qh = f64 ? XM_F64 : (o.compute == XM_BF16 ? XM_BF16 : XM_F32);
-  const double grad_tol = (o.grad_tol > 0) ? o.grad_tol : (f64 ? 1e-9 : 3e-7);
+  // the reduced-precision stage stops well above its rounding floor: the
+  // FP64 stage after it finishes the job, and near the floor the stage's
+  // ratios are noise (on the 10155-frame clustered scenes a 3e-7 stage
+  // tolerance sometimes took twice the inner iterations)
+  const double grad_tol = (o.grad_tol > 0) ? o.grad_tol : (f64 ? 1e-9 : 1e-6);
   // tolerance of the FP64 stage of a reduced-precision solve: that of an FP64 solve
-  const double grad_tol64 = f64 ? grad_tol : grad_tol / 300.0;
+  const double grad_tol64 = f64 ? grad_tol : grad_tol / 1000.0;
   const double cert_tol = (o.cert_tol > 0) ? o.cert_tol : (f64 ? 1e-7 : 1e-5);
   const int rmax = o.r_max;
   Vecs<T> V(N, rmax + 1);
@@ -391,23 +408,35 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   double solve_ms = 0, cert_ms = 0;
   RtrOut ro;
   CertResult cr;
+  // refinements at the current rank: when the certificate fails only through
+  // the stationarity terms of its bound (the complement of rows(Y) alone
+  // certifies, so no escape direction exists), the point is polished with a
+  // 100x tighter gradient tolerance, at most twice per rank
+  int refines = 0;
   while (true) {
     auto t0 = std::chrono::steady_clock::now();
-    ro = rtr<T>(p, V, r, qg, qh, o, grad_tol, st);
+    const double tscale = refines == 0 ? 1.0 : (refines == 1 ? 1e-2 : 1e-4);
     Vecs<double>* X = nullptr;
     if constexpr (f64) {
+      ro = rtr<T>(p, V, r, qg, qh, o, grad_tol * tscale, st);
       X = &V;
     } else {
       // FP64 stage from the reduced-precision point (re-orthonormalised in
       // FP64), starting with the radius the first stage ended with; its
       // truncated-CG products use the FP32 Q (or factors) also in a BF16
-      // solve, whose coarser Hessian would slow the final Newton steps
-      transpose_rows<T, double>(V.Yt.ptr, 1, static_cast<int>(n3 * r), Yt64.ptr, st);
+      // solve, whose coarser Hessian would slow the final Newton steps.  A
+      // refinement runs the FP64 stage alone, from where it ended.
       X = W.get();
-      mf64.split(r, Yt64.ptr, X->Rt.ptr, X->s.ptr, X->Yt.ptr, st);
       xm_solve_opts o2 = o;
-      o2.delta0 = std::max(ro.Delta, std::sqrt(3.0 * N) / 512.0);
-      const RtrOut r2 = rtr<double>(p, *X, r, XM_F64, XM_F32, o2, grad_tol64, st);
+      if (refines == 0) {
+        ro = rtr<T>(p, V, r, qg, qh, o, grad_tol, st);
+        transpose_rows<T, double>(V.Yt.ptr, 1, static_cast<int>(n3 * r), Yt64.ptr, st);
+        mf64.split(r, Yt64.ptr, X->Rt.ptr, X->s.ptr, X->Yt.ptr, st);
+        o2.delta0 = std::max(ro.Delta, std::sqrt(3.0 * N) / 512.0);
+      } else {
+        ro = RtrOut{};
+      }
+      const RtrOut r2 = rtr<double>(p, *X, r, XM_F64, XM_F32, o2, grad_tol64 * tscale, st);
       if (o.verbose)
         std::fprintf(stderr, "[xm] rank %d: FP64 stage from |g|=%.3e: %d steps, %d products -> |g|=%.3e\n", r,
                      ro.gnorm, r2.outer, r2.spmm, r2.gnorm);
@@ -428,9 +457,15 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
       std::fprintf(stderr, "[xm] rank %d: f=%.12e |g|=%.3e lambda_s=%.6e (res %.2e, %d it) bound %.3e %s\n", r, ro.f,
                    ro.gnorm, cr.lambda_min, cr.ritz_residual, cr.iters, cr.lambda_bound,
                    cr.certified ? "certified" : "not certified");
-    if (cr.certified || r >= rmax) break;
+    if (cr.certified) break;
+    if (cr.complement_ok && refines < 2) {
+      ++refines;
+      continue;
+    }
+    if (r >= rmax) break;
     if (!escape_fp64(p, *X, Yt64.ptr, r, vmin.ptr, &info->spmm_count, st)) break;
     ++r;
+    refines = 0;
     ++info->stair_steps;
     if constexpr (!f64) {
       // back to the reduced-precision stage at the new rank

@@ -147,12 +147,25 @@ __global__ __launch_bounds__(kB) void spmm_split_kernel(const TQ* __restrict__ Q
 #ifndef XM_SYM_PERM
 #define XM_SYM_PERM 1
 #endif
-constexpr bool kSymPerm = XM_SYM_PERM;  // lane-permuted slots (else selects in the butterfly)
+#ifndef XM_SYM_XLANE
+#define XM_SYM_XLANE 1
+#endif
+// cross-lane moves of the butterfly: lane-swap and DPP instructions (no LDS
+// traffic), slot b holding row b in every lane
+#ifndef XM_SYM_XLANE_F32
+#define XM_SYM_XLANE_F32 1
+#endif
+template <typename TA>
+struct SymMode {
+  static constexpr bool xlane = XM_SYM_XLANE && (sizeof(TA) == 8 || XM_SYM_XLANE_F32);
+  static constexpr bool perm = XM_SYM_PERM && !xlane;  // lane-permuted slots (else selects in the butterfly)
+};
 #ifndef XM_SYM_BATCH
 #define XM_SYM_BATCH 8
 #endif
 constexpr int kSymBatch = XM_SYM_BATCH;  // rows per butterfly batch: 8 (3 halving steps) or 4 (2)
-static_assert(kSymBatch == 8 || (kSymBatch == 4 && XM_SYM_PERM), "batch of 4 rows needs the lane permutation");
+static_assert(kSymBatch == 8 || (kSymBatch == 4 && XM_SYM_PERM && !XM_SYM_XLANE),
+              "batch of 4 rows needs the lane permutation");
 constexpr int kSymShift = (kSymBatch == 8) ? 3 : 4;  // lane >> kSymShift selects the row of a lane
 
 // Without the lane permutation the row of every slot is the same for the whole
@@ -160,7 +173,7 @@ constexpr int kSymShift = (kSymBatch == 8) ? 3 : 4;  // lane >> kSymShift select
 #ifndef XM_SYM_SCALAR_Y
 #define XM_SYM_SCALAR_Y 0
 #endif
-constexpr bool kSymScalarY = XM_SYM_SCALAR_Y && !XM_SYM_PERM;
+constexpr bool kSymScalarY = XM_SYM_SCALAR_Y && !XM_SYM_PERM && !XM_SYM_XLANE;
 
 // The kSymBatch row segments of a batch (zero where a row is past the slab or,
 // in a tile that crosses the diagonal, where all V columns of the lane lie left
@@ -272,6 +285,64 @@ constexpr bool sym_prefetch(int64_t active_blocks) {
 #else
 #define XM_SYM_ATTR
 #endif
+// x + (the value of x in the lane at distance 32 / 16), by the lane-swap
+// instructions: with X' Y' = swap(X, Y), X' + Y' is X summed over the two
+// halves in the lower half (the even rows of 16) and Y summed in the upper
+// half (the odd rows), so one swap serves a halving step of the butterfly
+template <int D>
+__device__ __forceinline__ float xlane_pair_sum(float x, float y) {
+  static_assert(D == 16 || D == 32, "lane distance 16 or 32");
+  const unsigned a = __builtin_bit_cast(unsigned, x), b = __builtin_bit_cast(unsigned, y);
+  unsigned r0, r1;
+  if constexpr (D == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    r0 = r[0]; r1 = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    r0 = r[0]; r1 = r[1];
+  }
+  // the empty asm keeps the two results apart: without it this compiler folds
+  // the float view of the pair into r0 + r0 (the integer view is compiled right)
+  asm("" : "+v"(r0), "+v"(r1));
+  return __builtin_bit_cast(float, r0) + __builtin_bit_cast(float, r1);
+}
+template <int D>
+__device__ __forceinline__ double xlane_pair_sum(double x, double y) {
+  static_assert(D == 16 || D == 32, "lane distance 16 or 32");
+  const uint64_t a = __builtin_bit_cast(uint64_t, x), b = __builtin_bit_cast(uint64_t, y);
+  const unsigned alo = static_cast<unsigned>(a), ahi = static_cast<unsigned>(a >> 32);
+  const unsigned blo = static_cast<unsigned>(b), bhi = static_cast<unsigned>(b >> 32);
+  unsigned r0lo, r0hi, r1lo, r1hi;
+  if constexpr (D == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    r0lo = lo[0]; r1lo = lo[1]; r0hi = hi[0]; r1hi = hi[1];
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    r0lo = lo[0]; r1lo = lo[1]; r0hi = hi[0]; r1hi = hi[1];
+  }
+  asm("" : "+v"(r0lo), "+v"(r1lo), "+v"(r0hi), "+v"(r1hi));  // as for float
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(r0hi) << 32) | r0lo) +
+         __builtin_bit_cast(double, (static_cast<uint64_t>(r1hi) << 32) | r1lo);
+}
+// the value of x in another lane of the same row of 16 (a DPP move; kCtrl one
+// of the row permutations below, every lane a valid source)
+constexpr int kDppQuadXor1 = 0xB1, kDppQuadXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+template <int kCtrl>
+__device__ __forceinline__ float dpp_get(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kCtrl, 0xF, 0xF, false));
+}
+template <int kCtrl>
+__device__ __forceinline__ double dpp_get(double x) {
+  const uint64_t a = __builtin_bit_cast(uint64_t, x);
+  const unsigned lo = static_cast<unsigned>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<unsigned>(a)), kCtrl, 0xF, 0xF, false));
+  const unsigned hi = static_cast<unsigned>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<unsigned>(a >> 32)), kCtrl, 0xF, 0xF, false));
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 template <typename TQ, typename TV, typename TA, int R, int RS, bool kPre>
 __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __restrict__ Q, int32_t ld, int32_t n3,
                                                       const TV* __restrict__ Yt, TA* __restrict__ colpart,
@@ -290,6 +361,7 @@ __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __re
   for (int e = threadIdx.x; e < RS * R; e += kB)
     ys[e] = (e < nrows * R) ? static_cast<TA>(Yt[static_cast<int64_t>(i0) * R + e]) : TA(0);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr bool kSymXlane = SymMode<TA>::xlane, kSymPerm = SymMode<TA>::perm;
   const int pi = kSymPerm ? (lane >> kSymShift) & (kSymBatch - 1) : 0;
   const int j = j0 + threadIdx.x * V;
   TA xc[V][R];
@@ -347,7 +419,22 @@ __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __re
     for (int a = 0; a < R; ++a) {
       TA t4[4], t2[2];
       TA t1;
-      if (kSymBatch == 4) {
+      if (kSymXlane) {
+        // rows 0-3 / 4-7 to the lower / upper 32 lanes, then the even / odd
+        // rows of 16, then the two halves of each row of 16 (mirror), each
+        // lane keeping row 4 b5 + 2 b4 + b3 of its lane bits; the last three
+        // steps sum the 8 lanes that share them
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t4[k] = xlane_pair_sum<32>(p[k][a], p[k + 4][a]);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) t2[k] = xlane_pair_sum<16>(t4[k], t4[k + 2]);
+        const bool h8 = lane & 8;
+        const TA send = h8 ? t2[0] : t2[1], keep = h8 ? t2[1] : t2[0];
+        t1 = keep + dpp_get<kDppMirror>(send);
+        t1 += dpp_get<kDppHalfMirror>(t1);
+        t1 += dpp_get<kDppQuadXor2>(t1);
+        t1 += dpp_get<kDppQuadXor1>(t1);
+      } else if (kSymBatch == 4) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) t2[k] = p[k][a] + __shfl_xor(p[(k + 2) % kSymBatch][a], 32);
         t1 = t2[0] + __shfl_xor(t2[1], 16);
@@ -368,11 +455,15 @@ __global__ __launch_bounds__(kB) XM_SYM_ATTR void spmm_sym_kernel(const TQ* __re
         for (int k = 0; k < 2; ++k) t2[k] = (h16 ? t4[k + 2] : t4[k]) + __shfl_xor(h16 ? t4[k] : t4[k + 2], 16);
         t1 = (h8 ? t2[1] : t2[0]) + __shfl_xor(h8 ? t2[0] : t2[1], 8);
       }
-      t1 += __shfl_xor(t1, 4);
-      t1 += __shfl_xor(t1, 2);
-      t1 += __shfl_xor(t1, 1);
+      if (!kSymXlane) {
+        t1 += __shfl_xor(t1, 4);
+        t1 += __shfl_xor(t1, 2);
+        t1 += __shfl_xor(t1, 1);
+      }
       if ((lane & ((1 << kSymShift) - 1)) == 0) {
-        const int row = ib + ((lane >> kSymShift) & (kSymBatch - 1));
+        const int lr = kSymXlane ? ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1)
+                                 : (lane >> kSymShift) & (kSymBatch - 1);
+        const int row = ib + lr;
         if (row < nrows) rp[wave][row * R + a] = t1;
       }
     }
@@ -606,6 +697,14 @@ __global__ void pad_rows_kernel(const T* __restrict__ Yt, int32_t N, T* __restri
 #define XM_FACT_U 2
 #endif
 constexpr int kFactU = XM_FACT_U;
+// The factors and their index arrays are streamed once per product with
+// non-temporal loads: they then leave the last-level cache to the FP32 G^{-1}
+// (206 MB at N = 10155), whose product in the same factored product went from
+// 57.7 to 51.5 us.
+template <typename E>
+__device__ __forceinline__ E fact_ld(const E* p) {
+  return __builtin_nontemporal_load(p);
+}
 
 // One pass over the co-visibility pattern forms both A_rr Y^T and W = B^T Y^T
 // (they share the gather of the padded Yt rows).  The column indices of a
@@ -632,7 +731,7 @@ __global__ __launch_bounds__(kB) void fact_rows_kernel(int32_t N, int64_t S, con
 #pragma unroll
   for (int u = 0; u < kFactU; ++u) {
     const int32_t s = beg + lane + 64 * u;
-    cn[u] = s < end ? col[s] : -1;
+    cn[u] = s < end ? fact_ld(col + s) : -1;
   }
   for (int32_t s0 = beg + lane; s0 < end; s0 += 64 * kFactU) {
     int32_t cc[kFactU];
@@ -640,7 +739,7 @@ __global__ __launch_bounds__(kB) void fact_rows_kernel(int32_t N, int64_t S, con
     for (int u = 0; u < kFactU; ++u) {
       const int32_t sn = s0 + 64 * (u + kFactU);
       cc[u] = cn[u];
-      cn[u] = sn < end ? col[sn] : -1;  // the next step's column, in flight during this one
+      cn[u] = sn < end ? fact_ld(col + sn) : -1;  // the next step's column, in flight during this one
     }
     T y[kFactU][RP], m[kFactU][9], t[kFactU][3];
 #pragma unroll
@@ -656,9 +755,9 @@ __global__ __launch_bounds__(kB) void fact_rows_kernel(int32_t N, int64_t S, con
         for (int k = 0; k < K; ++k) y[u][q * K + k] = v[k];
       }
 #pragma unroll
-      for (int k = 0; k < 9; ++k) m[u][k] = ok ? fac[k * S + sc] : T(0);
+      for (int k = 0; k < 9; ++k) m[u][k] = ok ? fact_ld(fac + k * S + sc) : T(0);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) t[u][c] = ok ? fac[(12 + c) * S + sc] : T(0);
+      for (int c = 0; c < 3; ++c) t[u][c] = ok ? fact_ld(fac + (12 + c) * S + sc) : T(0);
     }
 #pragma unroll
     for (int u = 0; u < kFactU; ++u)
@@ -699,7 +798,7 @@ __global__ __launch_bounds__(kB) void fact_cols_kernel(int32_t N, int64_t S, con
 #pragma unroll
   for (int u = 0; u < kFactU; ++u) {
     const int32_t s = beg + lane + 64 * u;
-    cn[u] = s < end ? col[s] : 0;
+    cn[u] = s < end ? fact_ld(col + s) : 0;
   }
   for (int32_t s0 = beg + lane; s0 < end; s0 += 64 * kFactU) {
     int32_t cc[kFactU];
@@ -707,7 +806,7 @@ __global__ __launch_bounds__(kB) void fact_cols_kernel(int32_t N, int64_t S, con
     for (int u = 0; u < kFactU; ++u) {
       const int32_t sn = s0 + 64 * (u + kFactU);
       cc[u] = cn[u];
-      cn[u] = sn < end ? col[sn] : 0;
+      cn[u] = sn < end ? fact_ld(col + sn) : 0;
     }
     T v[kFactU][R], b[kFactU][3];
 #pragma unroll
@@ -719,7 +818,7 @@ __global__ __launch_bounds__(kB) void fact_cols_kernel(int32_t N, int64_t S, con
 #pragma unroll
       for (int a = 0; a < R; ++a) v[u][a] = vp[a];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) b[u][c] = ok ? fac[(9 + c) * S + s] : T(0);
+      for (int c = 0; c < 3; ++c) b[u][c] = ok ? fact_ld(fac + (9 + c) * S + s) : T(0);
     }
 #pragma unroll
     for (int u = 0; u < kFactU; ++u)
@@ -727,6 +826,144 @@ __global__ __launch_bounds__(kB) void fact_cols_kernel(int32_t N, int64_t S, con
       for (int a = 0; a < R; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[c * R + a] += b[u][c] * v[u][a];
+  }
+  const T v = group_split_sum<NP, 64>(acc, lane);
+  const int q = group_split_index<NP, 64>(lane);
+  if ((lane & (64 / NP - 1)) == 0 && q < 3 * R) out[3 * static_cast<int64_t>(i) * R + q] += v;
+}
+
+// Grouped form of passes 1 and 3, used when the frame groups' unions fit in
+// LDS.  The frames are taken in groups of kFactGroup consecutive in the
+// Cuthill-McKee order of the co-visibility graph (the groups of the assembly's
+// correction products); one workgroup per group, one wavefront per frame.  The
+// group's co-visible frames (its union, which the assembly lists) are staged
+// in LDS once, so each gathered row comes from LDS: on clustered scenes a
+// group's union holds about a quarter of its blocks' rows, and the gathers
+// otherwise dominate the requests from the vector caches to L2, which bound
+// these passes.  lidx[s] is the position of block s's column in its row's
+// group union (-1 for the anchored frame 0, staged after the union in pass 1
+// and without a column of B in pass 3).
+constexpr int kFactGroup = kFrameGroup;
+constexpr int kFactGroupThreads = 64 * kFactGroup;
+
+template <typename T, int R>
+__global__ __launch_bounds__(kFactGroupThreads) void fact_rows_group_kernel(
+    int32_t N, int64_t S, const int32_t* __restrict__ order, const int64_t* __restrict__ ustart,
+    const int32_t* __restrict__ uid, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ lidx,
+    const T* __restrict__ fac, const T* __restrict__ Yt, T* __restrict__ out, T* __restrict__ W) {
+  constexpr int RP = padded_row<T, R>();
+  constexpr int K = V16<T>::K;
+  constexpr int NP = Pow2Up<4 * R>::v;
+  typedef typename V16<T>::type vec;
+  extern __shared__ __align__(16) unsigned char fact_smem[];
+  T* ys = reinterpret_cast<T*>(fact_smem);  // [U + 1][RP]: the union's Yt rows, then frame 0's
+  const int g = blockIdx.x;
+  const int64_t u0 = ustart[g];
+  const int U = static_cast<int>(ustart[g + 1] - u0);
+  for (int e = threadIdx.x; e < (U + 1) * RP; e += kFactGroupThreads) {
+    const int k = e / RP, q = e - k * RP;
+    const int j = (k < U) ? uid[u0 + k] : 0;
+    ys[e] = (q < 3 * R) ? Yt[static_cast<int64_t>(j) * 3 * R + q] : T(0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int a = g * kFactGroup + (threadIdx.x >> 6);
+  if (a >= N) return;  // whole wavefronts, after the only barrier
+  const int i = order[a];
+  T acc[NP];  // as in fact_rows_kernel
+#pragma unroll
+  for (int q = 0; q < NP; ++q) acc[q] = T(0);
+  const int32_t beg = row_ptr[i], end = row_ptr[i + 1];
+  for (int32_t s0 = beg + lane; s0 < end; s0 += 64 * kFactU) {
+    int32_t lk[kFactU];
+    T m[kFactU][9], t[kFactU][3];
+#pragma unroll
+    for (int u = 0; u < kFactU; ++u) {
+      const int32_t s = s0 + 64 * u;
+      const bool ok = s < end;  // a block past the row end contributes zero
+      const int32_t sc = ok ? s : s0;
+      lk[u] = fact_ld(lidx + sc);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) m[u][k] = ok ? fact_ld(fac + k * S + sc) : T(0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t[u][c] = ok ? fact_ld(fac + (12 + c) * S + sc) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kFactU; ++u) {
+      const vec* yp = reinterpret_cast<const vec*>(ys + (lk[u] >= 0 ? lk[u] : U) * RP);
+      T y[RP];
+#pragma unroll
+      for (int q = 0; q < RP / K; ++q) {
+        const vec v = yp[q];
+#pragma unroll
+        for (int k = 0; k < K; ++k) y[q * K + k] = v[k];
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+          const T yv = y[d * R + b];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[c * R + b] += m[u][3 * c + d] * yv;
+          acc[3 * R + b] += t[u][d] * yv;
+        }
+    }
+  }
+  const T v = group_split_sum<NP, 64>(acc, lane);
+  const int q = group_split_index<NP, 64>(lane);
+  if ((lane & (64 / NP - 1)) == 0) {
+    if (q < 3 * R) out[3 * static_cast<int64_t>(i) * R + q] = v;
+    else if (q < 4 * R && i > 0) W[static_cast<int64_t>(i - 1) * R + (q - 3 * R)] = v;
+  }
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kFactGroupThreads) void fact_cols_group_kernel(
+    int32_t N, int64_t S, const int32_t* __restrict__ order, const int64_t* __restrict__ ustart,
+    const int32_t* __restrict__ uid, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ lidx,
+    const T* __restrict__ fac, const T* __restrict__ V, T* __restrict__ out) {
+  constexpr int NP = Pow2Up<3 * R>::v;
+  extern __shared__ __align__(16) unsigned char fact_smem[];
+  T* vs = reinterpret_cast<T*>(fact_smem);  // [U][R]: V rows of the union (all its frames are >= 1)
+  const int g = blockIdx.x;
+  const int64_t u0 = ustart[g];
+  const int U = static_cast<int>(ustart[g + 1] - u0);
+  for (int e = threadIdx.x; e < U * R; e += kFactGroupThreads) {
+    const int k = e / R, b = e - k * R;
+    vs[e] = V[static_cast<int64_t>(uid[u0 + k] - 1) * R + b];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int a = g * kFactGroup + (threadIdx.x >> 6);
+  if (a >= N) return;  // whole wavefronts, after the only barrier
+  const int i = order[a];
+  T acc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) acc[q] = T(0);
+  const int32_t beg = row_ptr[i], end = row_ptr[i + 1];
+  for (int32_t s0 = beg + lane; s0 < end; s0 += 64 * kFactU) {
+    int32_t lk[kFactU];
+    T bb[kFactU][3];
+#pragma unroll
+    for (int u = 0; u < kFactU; ++u) {
+      const int32_t s = s0 + 64 * u;
+      const bool ok = s < end;
+      const int32_t sc = ok ? s : s0;
+      lk[u] = ok ? fact_ld(lidx + sc) : -1;  // -1: past the row end, or frame 0 (no column of B)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) bb[u][c] = ok ? fact_ld(fac + (9 + c) * S + sc) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kFactU; ++u) {
+      const bool ok = lk[u] >= 0;
+      const T* vp = vs + (ok ? lk[u] : 0) * R;
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        const T vv = ok ? vp[b] : T(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c * R + b] += bb[u][c] * vv;
+      }
+    }
   }
   const T v = group_split_sum<NP, 64>(acc, lane);
   const int q = group_split_index<NP, 64>(lane);
@@ -775,19 +1012,41 @@ void launch_factored(const xm_problem* p, const T* Yt, T* out, hipStream_t s, Sc
       timed_launch(p, sizeof(T) == 8 ? XM_STATS_FACTORED : XM_STATS_FACTORED + 1,
                    (0.5 * static_cast<double>(ng) * (ng + 1) + static_cast<double>(S) * 15.0) * sizeof(T), sc);
   if (ev) XM_HIP(hipEventRecord(ev->start, s));
-  hipLaunchKernelGGL((pad_rows_kernel<T, R>), dim3(cdiv(static_cast<size_t>(N) * RP, kB)), dim3(kB), 0, s, Yt, N,
-                     Ytp);
-  XM_LAUNCH_CHECK("pad_rows_kernel");
+  // each pass grouped when the largest group union (and, for pass 1, frame 0's
+  // row) fits in half the LDS a workgroup may take: with one workgroup per CU
+  // nothing overlaps its staging, and pass 1 at r = 5 in FP32 (145 KB at
+  // N = 10155) measured slower grouped (66 against 53 us)
+  const size_t lds_rows = (static_cast<size_t>(std::max(p->grp_maxu, 0)) + 1) * RP * sizeof(T);
+  const size_t lds_cols = static_cast<size_t>(std::max(p->grp_maxu, 1)) * R * sizeof(T);
+  const bool grouped_rows = p->grp_maxu >= 0 && lds_rows <= p->lds_max / 2;
+  const bool grouped_cols = p->grp_maxu >= 0 && lds_cols <= p->lds_max / 2;
+  const unsigned ngroups = cdiv(N, kFactGroup);
   const unsigned gb = cdiv(N, kB / 64);
-  hipLaunchKernelGGL((fact_rows_kernel<T, R>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr, f.fac,
-                     Ytp, out, W);
-  XM_LAUNCH_CHECK("fact_rows_kernel");
+  if (grouped_rows) {
+    hipLaunchKernelGGL((fact_rows_group_kernel<T, R>), dim3(ngroups), dim3(kFactGroupThreads), lds_rows, s, N, S,
+                       p->order.ptr, p->grp_ustart.ptr, p->grp_uid.ptr, p->row_ptr.ptr, p->lidx.ptr, f.fac, Yt, out,
+                       W);
+    XM_LAUNCH_CHECK("fact_rows_group_kernel");
+  } else {
+    hipLaunchKernelGGL((pad_rows_kernel<T, R>), dim3(cdiv(static_cast<size_t>(N) * RP, kB)), dim3(kB), 0, s, Yt, N,
+                       Ytp);
+    XM_LAUNCH_CHECK("pad_rows_kernel");
+    hipLaunchKernelGGL((fact_rows_kernel<T, R>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr, f.fac,
+                       Ytp, out, W);
+    XM_LAUNCH_CHECK("fact_rows_kernel");
+  }
   xm_problem::TimedLaunch* evg = timed_launch(p, sizeof(T) == 8 ? XM_STATS_GINV : XM_STATS_GINV + 1,
                                               0.5 * static_cast<double>(ng) * (ng + 1) * sizeof(T), sc);
   sym_product<T, T, T, R>(f.Gm, p->ldg, ng, W, Vv, mp->spmm_scratch, sc, evg, s);
-  hipLaunchKernelGGL((fact_cols_kernel<T, R>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr, f.fac,
-                     Vv, out);
-  XM_LAUNCH_CHECK("fact_cols_kernel");
+  if (grouped_cols) {
+    hipLaunchKernelGGL((fact_cols_group_kernel<T, R>), dim3(ngroups), dim3(kFactGroupThreads), lds_cols, s, N, S,
+                       p->order.ptr, p->grp_ustart.ptr, p->grp_uid.ptr, p->row_ptr.ptr, p->lidx.ptr, f.fac, Vv, out);
+    XM_LAUNCH_CHECK("fact_cols_group_kernel");
+  } else {
+    hipLaunchKernelGGL((fact_cols_kernel<T, R>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr, f.fac,
+                       Vv, out);
+    XM_LAUNCH_CHECK("fact_cols_kernel");
+  }
   if (ev) XM_HIP(hipEventRecord(ev->stop, s));
 }
 
