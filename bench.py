@@ -37,8 +37,9 @@ FP64_PEAK_TFS = 78.6   # MI355X FP64, vector and matrix
 # profiles/hbm_traffic_factored_product_large.md); valid for the large workload
 # and the kernels as they were profiled -- re-measure after changing one.
 PMC_TRAFFIC_BYTES = {("large", "sweep_update_kernel"): 0.948e9,
-                     ("large", "spmm_sym_kernel (f32 Q)"): 1.921e9,
-                     ("large", "spmm_sym_kernel (f32 G^-1, in the factored product)"): 0.219e9}
+                     ("large", "spmm_sym_kernel (f32 Q)"): 1.923e9,
+                     ("large", "spmm_sym_kernel (f32 G^-1, in the factored product)"): 0.219e9,
+                     ("large", "fact_rows pass (f32, in the factored product)"): 0.215e9}
 
 
 def log(msg):
@@ -208,7 +209,9 @@ def main():
              "f64_ginv": "spmm_sym_kernel (f64 G^-1, in the factored product)",
              "f32_ginv": "spmm_sym_kernel (f32 G^-1, in the factored product)",
              "f64_factored": "factored product (f64: sparse A_rr, A_rt; dense G^-1)",
-             "f32_factored": "factored product (f32: sparse A_rr, A_rt; dense G^-1)"}
+             "f32_factored": "factored product (f32: sparse A_rr, A_rt; dense G^-1)",
+             "f64_fact_rows": "fact_rows pass (f64, in the factored product)",
+             "f32_fact_rows": "fact_rows pass (f32, in the factored product)"}
     composite = {names["f64_factored"], names["f32_factored"]}
     for k in stats:
         if stats[k]["launches"]:

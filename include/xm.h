@@ -303,7 +303,8 @@ typedef struct {
                           FP32 Q) down to grad_tol / 1000.  A point whose
                           certificate fails only through the stationarity
                           terms of its bound is polished at the same rank
-                          with a 100x, then 10^4 x tighter tolerance.  The
+                          with a 10x tighter tolerance (up to 3 times; FP64
+                          Hessian products).  The
                           FP64 stage exists because the dual certificate needs
                           a point closer to stationary than a reduced-precision
                           iterate's own rounding allows */
@@ -516,12 +517,16 @@ xm_status xm_adjoint(xm_problem* p, const double* R, const double* s, const doub
  * the pass that adds its partial sums); XM_STATS_FACTORED (3) and 4 for the
  * FP64 and FP32 factored products, bracketed whole (all their kernels);
  * XM_STATS_GINV (5) and 6 for the symmetric dense kernel over G^{-1} inside
- * the FP64 and FP32 factored products (that kernel alone).  reset != 0
+ * the FP64 and FP32 factored products (that kernel alone); XM_STATS_FACT_ROWS
+ * (7) and 8 for the pass of the FP64 and FP32 factored products that forms
+ * A_rr Y^T and B^T Y^T (its bytes: the factor values and indices it streams,
+ * each padded Y^T or staged union row once, and its outputs).  reset != 0
  * forgets the recorded launches.
  */
 #define XM_STATS_FACTORED 3
 #define XM_STATS_GINV 5
-#define XM_STATS_SLOTS 7
+#define XM_STATS_FACT_ROWS 7
+#define XM_STATS_SLOTS 9
 typedef struct {
   int64_t launches[XM_STATS_SLOTS];
   double total_ms[XM_STATS_SLOTS];

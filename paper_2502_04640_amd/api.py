@@ -72,8 +72,8 @@ class _AdjInfo(ctypes.Structure):
 
 
 class _SpmmStats(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 7), ("total_ms", ctypes.c_double * 7),
-                ("bytes_per_launch", ctypes.c_double * 7)]
+    _fields_ = [("launches", ctypes.c_int64 * 9), ("total_ms", ctypes.c_double * 9),
+                ("bytes_per_launch", ctypes.c_double * 9)]
 
 
 def library_path() -> str:
@@ -286,7 +286,7 @@ class Problem:
         _check(load_library().xm_spmm_stats(self._h, ctypes.byref(st), int(reset)))
         out = {}
         for name, k in list(_DT.items()) + [("f64_factored", 3), ("f32_factored", 4), ("f64_ginv", 5),
-                                            ("f32_ginv", 6)]:
+                                            ("f32_ginv", 6), ("f64_fact_rows", 7), ("f32_fact_rows", 8)]:
             out[name] = {"launches": st.launches[k], "total_ms": st.total_ms[k],
                          "bytes_per_launch": st.bytes_per_launch[k]}
         return out

@@ -31,8 +31,8 @@
 // re-orthonormalised (scale kept), alpha halved until the cost drops, at most
 // 40 times.  It is taken only when the dual has a negative direction off
 // rows(Y): when the certificate's bound fails through its stationarity terms
-// alone, the point is instead polished at the same rank with a 100x (then
-// 10^4 x) tighter gradient tolerance.
+// alone, the point is instead polished at the same rank with a 10x tighter
+// gradient tolerance (up to three times; FP64 Hessian products).
 #include <chrono>
 #include <cmath>
 #include <memory>
@@ -411,11 +411,14 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   // refinements at the current rank: when the certificate fails only through
   // the stationarity terms of its bound (the complement of rows(Y) alone
   // certifies, so no escape direction exists), the point is polished with a
-  // 100x tighter gradient tolerance, at most twice per rank
+  // 10x tighter gradient tolerance, at most three times per rank (FP64
+  // Hessian products in a reduced-precision solve: near its floor the FP32
+  // model gains little per step)
+  constexpr int kMaxRefines = 3;
   int refines = 0;
   while (true) {
     auto t0 = std::chrono::steady_clock::now();
-    const double tscale = refines == 0 ? 1.0 : (refines == 1 ? 1e-2 : 1e-4);
+    const double tscale = std::pow(0.1, refines);
     Vecs<double>* X = nullptr;
     if constexpr (f64) {
       ro = rtr<T>(p, V, r, qg, qh, o, grad_tol * tscale, st);
@@ -436,7 +439,7 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
       } else {
         ro = RtrOut{};
       }
-      const RtrOut r2 = rtr<double>(p, *X, r, XM_F64, XM_F32, o2, grad_tol64 * tscale, st);
+      const RtrOut r2 = rtr<double>(p, *X, r, XM_F64, refines == 0 ? XM_F32 : XM_F64, o2, grad_tol64 * tscale, st);
       if (o.verbose)
         std::fprintf(stderr, "[xm] rank %d: FP64 stage from |g|=%.3e: %d steps, %d products -> |g|=%.3e\n", r,
                      ro.gnorm, r2.outer, r2.spmm, r2.gnorm);
@@ -458,7 +461,7 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
                    ro.gnorm, cr.lambda_min, cr.ritz_residual, cr.iters, cr.lambda_bound,
                    cr.certified ? "certified" : "not certified");
     if (cr.certified) break;
-    if (cr.complement_ok && refines < 2) {
+    if (cr.complement_ok && refines < kMaxRefines) {
       ++refines;
       continue;
     }

@@ -1022,19 +1022,32 @@ void launch_factored(const xm_problem* p, const T* Yt, T* out, hipStream_t s, Sc
   const bool grouped_cols = p->grp_maxu >= 0 && lds_cols <= p->lds_max / 2;
   const unsigned ngroups = cdiv(N, kFactGroup);
   const unsigned gb = cdiv(N, kB / 64);
+  // bytes of pass 1: the 12 factor values and the index of every block, each
+  // Y^T row once (the staged union rows when grouped), A_rr Y^T and W written
+  const double rows_bytes =
+      static_cast<double>(S) * (12.0 * sizeof(T) + 4.0) +
+      (grouped_rows ? static_cast<double>(p->grp_uid.n + ngroups) * 3 * R * sizeof(T)
+                    : static_cast<double>(N) * RP * sizeof(T)) +
+      (3.0 * N + (N - 1)) * R * sizeof(T);
+  xm_problem::TimedLaunch* evr =
+      timed_launch(p, sizeof(T) == 8 ? XM_STATS_FACT_ROWS : XM_STATS_FACT_ROWS + 1, rows_bytes, sc);
+  if (!grouped_rows) {
+    hipLaunchKernelGGL((pad_rows_kernel<T, R>), dim3(cdiv(static_cast<size_t>(N) * RP, kB)), dim3(kB), 0, s, Yt, N,
+                       Ytp);
+    XM_LAUNCH_CHECK("pad_rows_kernel");
+  }
+  if (evr) XM_HIP(hipEventRecord(evr->start, s));
   if (grouped_rows) {
     hipLaunchKernelGGL((fact_rows_group_kernel<T, R>), dim3(ngroups), dim3(kFactGroupThreads), lds_rows, s, N, S,
                        p->order.ptr, p->grp_ustart.ptr, p->grp_uid.ptr, p->row_ptr.ptr, p->lidx.ptr, f.fac, Yt, out,
                        W);
     XM_LAUNCH_CHECK("fact_rows_group_kernel");
   } else {
-    hipLaunchKernelGGL((pad_rows_kernel<T, R>), dim3(cdiv(static_cast<size_t>(N) * RP, kB)), dim3(kB), 0, s, Yt, N,
-                       Ytp);
-    XM_LAUNCH_CHECK("pad_rows_kernel");
     hipLaunchKernelGGL((fact_rows_kernel<T, R>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr, f.fac,
                        Ytp, out, W);
     XM_LAUNCH_CHECK("fact_rows_kernel");
   }
+  if (evr) XM_HIP(hipEventRecord(evr->stop, s));
   xm_problem::TimedLaunch* evg = timed_launch(p, sizeof(T) == 8 ? XM_STATS_GINV : XM_STATS_GINV + 1,
                                               0.5 * static_cast<double>(ng) * (ng + 1) * sizeof(T), sc);
   sym_product<T, T, T, R>(f.Gm, p->ldg, ng, W, Vv, mp->spmm_scratch, sc, evg, s);

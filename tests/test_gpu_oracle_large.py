@@ -167,3 +167,28 @@ def test_large_tight_twin_against_oracle():
     _say(f"  FP32 vs oracle-certified FP64 optimum: rotations {err:.2e} rad, scales {serr:.2e}, "
          f"rho gap {_gap(rho32, rho64):.2e}")
     assert err <= 1e-4 and serr <= 1e-4 and _gap(rho32, rho64) <= 1e-5
+
+
+def test_large_polished_point_against_oracle():
+    # Another seed of the workload: the FP64 solve first stops (|g| <= 1e-9
+    # qbar |Y|) at a rank-5 point whose whole-spectrum bound fails only through
+    # its stationarity terms (the complement of rows(Y) is positive, so there is
+    # no escape direction); the solver polishes the point at the same rank with
+    # a 10x tighter gradient tolerance and certifies it.  The oracle's
+    # certificate at the polished point agrees.
+    _say("case: large workload, seed 2: FP64 solve polished at rank 5, against the oracle's certificate")
+    xm = _xm()
+    sc = scenes.make_scene("large", 2)
+    P = xm.build_Q(sc.N, sc.M, torch.from_numpy(sc.frame).cuda(), torch.from_numpy(sc.landmark).cuda(),
+                   torch.from_numpy(sc.u).cuda(), torch.from_numpy(sc.w).cuda())
+    Y, info = P.solve(xm.SolveOptions(compute="f64"))
+    r = info["r"]
+    ynorm = float(torch.linalg.norm(Y[:r]))
+    qbar = P.info()["qbar"]
+    c = P.certify(Y, tol=1e-7, max_iter=400)
+    _say(f"  gpu: r={r} certified={info['certified']} |g|={info['grad_norm']:.3e} "
+         f"(1e-9 qbar |Y| = {1e-9 * qbar * ynorm:.3e}) bound={c['lambda_bound']:.3e}")
+    assert info["certified"] == 1
+    # polished beyond the default tolerance (10x per refinement)
+    assert info["grad_norm"] <= 1e-10 * qbar * ynorm
+    _check_certificate(_oracle_op(sc), {"Y": Y.cpu().numpy(), "info": info, "cert": c}, 1e-7)
