@@ -352,8 +352,9 @@ typedef struct {
  * Y_out  device [opts->r_max][3N]; rows [0, info->r) hold the solution, the
  *        rest are zero.
  * info   host, filled on return.
- * Returns XM_OK, or XM_ENOCONV if an iteration cap stopped the final local
- * solve (Y_out still holds the last iterate).  Synchronises `stream`.
+ * Returns XM_OK, or XM_ENOCONV if an iteration cap or a stagnation stopped the
+ * final local solve short of its tolerance and the point is not certified
+ * (Y_out still holds the last iterate).  Synchronises `stream`.
  */
 xm_status xm_bm_solve(xm_problem* p, const xm_solve_opts* opts, const double* Y0, int32_t r_in,
                       double* Y_out, xm_solve_info* info, void* stream);

@@ -494,7 +494,9 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   info->dual = cr.dual;
   info->solve_ms = solve_ms;
   info->cert_ms = cert_ms;
-  return ro.converged ? XM_OK : XM_ENOCONV;
+  // a certified point is a global optimum whatever stopped the last stage
+  // (a polish that ended on stagnation above its tighter tolerance)
+  return (ro.converged || cr.certified) ? XM_OK : XM_ENOCONV;
 }
 
 }  // namespace
