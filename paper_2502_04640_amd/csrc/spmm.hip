@@ -10,6 +10,8 @@
 // workgroups to fill 256 CUs; their partial sums are added by a second,
 // deterministic pass.  Q is read exactly once per product: HBM-bound, with
 // 2 r FLOP per stored element.
+#include <type_traits>
+
 #include "problem.h"
 
 namespace xm {
@@ -680,15 +682,16 @@ constexpr int padded_row() {
   return (3 * R + V16<T>::K - 1) / V16<T>::K * V16<T>::K;
 }
 
-// Ytp[j][e] = Yt[3j + e / R][e % R] for e < 3R, 0 for the padding
-template <typename T, int R>
-__global__ void pad_rows_kernel(const T* __restrict__ Yt, int32_t N, T* __restrict__ Ytp) {
+// Ytp[j][e] = Yt[3j + e / R][e % R] for e < 3R, 0 for the padding (Yt in the
+// product's precision or, for a mixed product, FP64 rounded here)
+template <typename T, int R, typename TS>
+__global__ void pad_rows_kernel(const TS* __restrict__ Yt, int32_t N, T* __restrict__ Ytp) {
   constexpr int RP = padded_row<T, R>();
   const int64_t e = static_cast<int64_t>(blockIdx.x) * kB + threadIdx.x;
   if (e >= static_cast<int64_t>(N) * RP) return;
   const int64_t j = e / RP;
   const int k = static_cast<int>(e - j * RP);
-  Ytp[e] = (k < 3 * R) ? Yt[j * 3 * R + k] : T(0);
+  Ytp[e] = (k < 3 * R) ? static_cast<T>(Yt[j * 3 * R + k]) : T(0);
 }
 
 // Each lane takes kFactU blocks of the row per step (64 apart), all their loads
@@ -780,12 +783,14 @@ __global__ __launch_bounds__(kB) void fact_rows_kernel(int32_t N, int64_t S, con
   }
 }
 
-// out[i] += sum_s A_rt[s] V[col s - 1], the column indices one step ahead as above
-template <typename T, int R>
+// out[i] = part[i] + sum_s A_rt[s] V[col s - 1] (part: pass 1's result; the
+// same array as out unless a mixed product widens to FP64 here), the column
+// indices one step ahead as above
+template <typename T, int R, typename TO>
 __global__ __launch_bounds__(kB) void fact_cols_kernel(int32_t N, int64_t S, const int32_t* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col,
                                                        const T* __restrict__ fac, const T* __restrict__ V,
-                                                       T* __restrict__ out) {
+                                                       const T* part, TO* out) {
   constexpr int NP = Pow2Up<3 * R>::v;
   const int i = blockIdx.x * (kB / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -829,7 +834,10 @@ __global__ __launch_bounds__(kB) void fact_cols_kernel(int32_t N, int64_t S, con
   }
   const T v = group_split_sum<NP, 64>(acc, lane);
   const int q = group_split_index<NP, 64>(lane);
-  if ((lane & (64 / NP - 1)) == 0 && q < 3 * R) out[3 * static_cast<int64_t>(i) * R + q] += v;
+  if ((lane & (64 / NP - 1)) == 0 && q < 3 * R) {
+    const int64_t o = 3 * static_cast<int64_t>(i) * R + q;
+    out[o] = static_cast<TO>(part[o] + v);
+  }
 }
 
 // Grouped form of passes 1 and 3, used when the frame groups' unions fit in
@@ -846,11 +854,11 @@ __global__ __launch_bounds__(kB) void fact_cols_kernel(int32_t N, int64_t S, con
 constexpr int kFactGroup = kFrameGroup;
 constexpr int kFactGroupThreads = 64 * kFactGroup;
 
-template <typename T, int R>
+template <typename T, int R, typename TS>
 __global__ __launch_bounds__(kFactGroupThreads) void fact_rows_group_kernel(
     int32_t N, int64_t S, const int32_t* __restrict__ order, const int64_t* __restrict__ ustart,
     const int32_t* __restrict__ uid, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ lidx,
-    const T* __restrict__ fac, const T* __restrict__ Yt, T* __restrict__ out, T* __restrict__ W) {
+    const T* __restrict__ fac, const TS* __restrict__ Yt, T* __restrict__ out, T* __restrict__ W) {
   constexpr int RP = padded_row<T, R>();
   constexpr int K = V16<T>::K;
   constexpr int NP = Pow2Up<4 * R>::v;
@@ -863,7 +871,7 @@ __global__ __launch_bounds__(kFactGroupThreads) void fact_rows_group_kernel(
   for (int e = threadIdx.x; e < (U + 1) * RP; e += kFactGroupThreads) {
     const int k = e / RP, q = e - k * RP;
     const int j = (k < U) ? uid[u0 + k] : 0;
-    ys[e] = (q < 3 * R) ? Yt[static_cast<int64_t>(j) * 3 * R + q] : T(0);
+    ys[e] = (q < 3 * R) ? static_cast<T>(Yt[static_cast<int64_t>(j) * 3 * R + q]) : T(0);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -917,11 +925,11 @@ __global__ __launch_bounds__(kFactGroupThreads) void fact_rows_group_kernel(
   }
 }
 
-template <typename T, int R>
+template <typename T, int R, typename TO>
 __global__ __launch_bounds__(kFactGroupThreads) void fact_cols_group_kernel(
     int32_t N, int64_t S, const int32_t* __restrict__ order, const int64_t* __restrict__ ustart,
     const int32_t* __restrict__ uid, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ lidx,
-    const T* __restrict__ fac, const T* __restrict__ V, T* __restrict__ out) {
+    const T* __restrict__ fac, const T* __restrict__ V, const T* part, TO* out) {
   constexpr int NP = Pow2Up<3 * R>::v;
   extern __shared__ __align__(16) unsigned char fact_smem[];
   T* vs = reinterpret_cast<T*>(fact_smem);  // [U][R]: V rows of the union (all its frames are >= 1)
@@ -967,7 +975,10 @@ __global__ __launch_bounds__(kFactGroupThreads) void fact_cols_group_kernel(
   }
   const T v = group_split_sum<NP, 64>(acc, lane);
   const int q = group_split_index<NP, 64>(lane);
-  if ((lane & (64 / NP - 1)) == 0 && q < 3 * R) out[3 * static_cast<int64_t>(i) * R + q] += v;
+  if ((lane & (64 / NP - 1)) == 0 && q < 3 * R) {
+    const int64_t o = 3 * static_cast<int64_t>(i) * R + q;
+    out[o] = static_cast<TO>(part[o] + v);
+  }
 }
 
 // the factors of one precision: the sparse blocks (structure of arrays) and -G^{-1}
@@ -996,8 +1007,11 @@ size_t sym_scratch_bytes(int32_t n, int32_t ld, int V, size_t a, int R) {
   return (nslabs + nchunks) * static_cast<size_t>(n) * R * a;
 }
 
-template <typename T, int R>
-void launch_factored(const xm_problem* p, const T* Yt, T* out, hipStream_t s, Scratch* sc) {
+// TIO: the type of Yt and out; a mixed product (FP64 vectors, FP32 factors)
+// rounds Yt in pass 1 and widens the result in pass 3, with pass 1's result
+// in `part` (FP32, 3N x R), instead of converting both vectors separately.
+template <typename T, int R, typename TIO>
+void launch_factored(const xm_problem* p, const TIO* Yt, TIO* out, hipStream_t s, Scratch* sc, T* part) {
   auto* mp = const_cast<xm_problem*>(p);
   const Factors<T> f = factors(p, static_cast<T*>(nullptr));
   const int32_t N = p->N, ng = N - 1;
@@ -1032,19 +1046,19 @@ void launch_factored(const xm_problem* p, const T* Yt, T* out, hipStream_t s, Sc
   xm_problem::TimedLaunch* evr =
       timed_launch(p, sizeof(T) == 8 ? XM_STATS_FACT_ROWS : XM_STATS_FACT_ROWS + 1, rows_bytes, sc);
   if (!grouped_rows) {
-    hipLaunchKernelGGL((pad_rows_kernel<T, R>), dim3(cdiv(static_cast<size_t>(N) * RP, kB)), dim3(kB), 0, s, Yt, N,
-                       Ytp);
+    hipLaunchKernelGGL((pad_rows_kernel<T, R, TIO>), dim3(cdiv(static_cast<size_t>(N) * RP, kB)), dim3(kB), 0, s, Yt,
+                       N, Ytp);
     XM_LAUNCH_CHECK("pad_rows_kernel");
   }
   if (evr) XM_HIP(hipEventRecord(evr->start, s));
   if (grouped_rows) {
-    hipLaunchKernelGGL((fact_rows_group_kernel<T, R>), dim3(ngroups), dim3(kFactGroupThreads), lds_rows, s, N, S,
-                       p->order.ptr, p->grp_ustart.ptr, p->grp_uid.ptr, p->row_ptr.ptr, p->lidx.ptr, f.fac, Yt, out,
-                       W);
+    hipLaunchKernelGGL((fact_rows_group_kernel<T, R, TIO>), dim3(ngroups), dim3(kFactGroupThreads), lds_rows, s, N,
+                       S, p->order.ptr, p->grp_ustart.ptr, p->grp_uid.ptr, p->row_ptr.ptr, p->lidx.ptr, f.fac, Yt,
+                       part, W);
     XM_LAUNCH_CHECK("fact_rows_group_kernel");
   } else {
     hipLaunchKernelGGL((fact_rows_kernel<T, R>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr, f.fac,
-                       Ytp, out, W);
+                       Ytp, part, W);
     XM_LAUNCH_CHECK("fact_rows_kernel");
   }
   if (evr) XM_HIP(hipEventRecord(evr->stop, s));
@@ -1052,28 +1066,32 @@ void launch_factored(const xm_problem* p, const T* Yt, T* out, hipStream_t s, Sc
                                               0.5 * static_cast<double>(ng) * (ng + 1) * sizeof(T), sc);
   sym_product<T, T, T, R>(f.Gm, p->ldg, ng, W, Vv, mp->spmm_scratch, sc, evg, s);
   if (grouped_cols) {
-    hipLaunchKernelGGL((fact_cols_group_kernel<T, R>), dim3(ngroups), dim3(kFactGroupThreads), lds_cols, s, N, S,
-                       p->order.ptr, p->grp_ustart.ptr, p->grp_uid.ptr, p->row_ptr.ptr, p->lidx.ptr, f.fac, Vv, out);
+    hipLaunchKernelGGL((fact_cols_group_kernel<T, R, TIO>), dim3(ngroups), dim3(kFactGroupThreads), lds_cols, s, N,
+                       S, p->order.ptr, p->grp_ustart.ptr, p->grp_uid.ptr, p->row_ptr.ptr, p->lidx.ptr, f.fac, Vv,
+                       part, out);
     XM_LAUNCH_CHECK("fact_cols_group_kernel");
   } else {
-    hipLaunchKernelGGL((fact_cols_kernel<T, R>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr, f.fac,
-                       Vv, out);
+    hipLaunchKernelGGL((fact_cols_kernel<T, R, TIO>), dim3(gb), dim3(kB), 0, s, N, S, p->row_ptr.ptr, p->col.ptr,
+                       f.fac, Vv, part, out);
     XM_LAUNCH_CHECK("fact_cols_kernel");
   }
   if (ev) XM_HIP(hipEventRecord(ev->stop, s));
 }
 
-template <typename T>
-void dispatch_factored(const xm_problem* p, const T* Yt, int r, T* out, hipStream_t s, Scratch* sc) {
+// part: pass 1's result for a mixed product (T other than TIO); else out serves
+template <typename T, typename TIO = T>
+void dispatch_factored(const xm_problem* p, const TIO* Yt, int r, TIO* out, hipStream_t s, Scratch* sc,
+                       T* part = nullptr) {
+  if constexpr (std::is_same<T, TIO>::value) part = out;
   switch (r) {
-    case 1: launch_factored<T, 1>(p, Yt, out, s, sc); return;
-    case 2: launch_factored<T, 2>(p, Yt, out, s, sc); return;
-    case 3: launch_factored<T, 3>(p, Yt, out, s, sc); return;
-    case 4: launch_factored<T, 4>(p, Yt, out, s, sc); return;
-    case 5: launch_factored<T, 5>(p, Yt, out, s, sc); return;
-    case 6: launch_factored<T, 6>(p, Yt, out, s, sc); return;
-    case 7: launch_factored<T, 7>(p, Yt, out, s, sc); return;
-    case 8: launch_factored<T, 8>(p, Yt, out, s, sc); return;
+    case 1: launch_factored<T, 1, TIO>(p, Yt, out, s, sc, part); return;
+    case 2: launch_factored<T, 2, TIO>(p, Yt, out, s, sc, part); return;
+    case 3: launch_factored<T, 3, TIO>(p, Yt, out, s, sc, part); return;
+    case 4: launch_factored<T, 4, TIO>(p, Yt, out, s, sc, part); return;
+    case 5: launch_factored<T, 5, TIO>(p, Yt, out, s, sc, part); return;
+    case 6: launch_factored<T, 6, TIO>(p, Yt, out, s, sc, part); return;
+    case 7: launch_factored<T, 7, TIO>(p, Yt, out, s, sc, part); return;
+    case 8: launch_factored<T, 8, TIO>(p, Yt, out, s, sc, part); return;
     default: throw Error(XM_EINVAL, "rank must be in [1, 8]");
   }
 }
@@ -1155,6 +1173,11 @@ void spmm_yt<double>(const xm_problem* p, xm_dtype qtype, const double* Yt, int 
     auto* mp = const_cast<xm_problem*>(p);
     const size_t n = static_cast<size_t>(p->n3) * r;
     float* a = take<float>(sc, mp->mixed_scratch, 2 * n, s);
+    if (qtype == XM_F32 && p->spmm_kind[role][XM_F32] == XM_SPMM_FACTORED) {
+      // the factored passes round and widen themselves (bitwise the same result)
+      dispatch_factored<float, double>(p, Yt, r, out, s, sc, a);
+      return;
+    }
     float* b = a + n;
     transpose_rows<double, float>(Yt, 1, static_cast<int>(n), a, s);
     spmm_yt<float>(p, qtype, a, r, b, s, role, sc);
