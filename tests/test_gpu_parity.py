@@ -528,3 +528,22 @@ def test_large_tight_twin_rotations_fp32_vs_fp64():
     # scales: max relative error, with the FP32 rotation bar
     assert np.abs(s32.cpu().numpy() / s64.cpu().numpy() - 1).max() <= 1e-4
     assert _gap(rho32, rho64) <= 1e-5
+
+
+@pytest.mark.parametrize("seed", [1, 3])
+def test_large_workload_other_seeds_certify(seed):
+    # Other seeds of the benchmark's generator: the default FP32 and FP64 solves
+    # both certify at the same optimum, in a bounded number of steps (a
+    # reduced-precision stage that stalls near its rounding floor hands over to
+    # the FP64 stage instead of running to its step cap at a collapsed radius)
+    _say(f"case: large workload, seed {seed}: default FP32 and FP64 solves certify")
+    xm = _xm()
+    sc = scenes.make_scene("large", seed)
+    P = _build(sc, keep=("f32",))
+    Y32, i32 = P.solve(xm.SolveOptions(compute="f32"))
+    Y64, i64 = P.solve(xm.SolveOptions(compute="f64"))
+    _say(f"  f32: certified={i32['certified']} r={i32['r']} outer={i32['outer_iters']} inner={i32['inner_iters']}; "
+         f"f64: certified={i64['certified']} r={i64['r']} outer={i64['outer_iters']} inner={i64['inner_iters']}")
+    assert i32["certified"] == 1 and i64["certified"] == 1
+    assert i32["outer_iters"] <= 300 and i64["outer_iters"] <= 300
+    assert _gap(i32["cost"], i64["cost"]) <= 1e-8
