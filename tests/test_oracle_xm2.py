@@ -62,3 +62,61 @@ def test_xm2_removes_injected_outliers(rank):
     # the second solve is the staircase on the kept observations
     Q2 = dm.q_block_elimination(sc.N, sc.M, sc.frame[keep], sc.landmark[keep], sc.u[keep], sc.w[keep])
     assert np.abs(Q2 - out["Q2"]).max() <= 1e-12 * np.abs(Q2).max()
+
+
+def _guard_case():
+    # four frames, five landmarks; observations (frame, landmark) with the two
+    # partners of frame 3's landmarks deleted: frame 3 keeps both of its own
+    # observations but none of them is a link any more
+    obs = [(0, 0), (1, 0), (0, 1), (2, 1), (1, 2), (2, 2), (3, 3), (3, 4), (0, 3), (2, 4)]
+    frame = np.array([f for f, _ in obs], np.int32)
+    landmark = np.array([k for _, k in obs], np.int32)
+    keep = np.ones(len(obs), bool)
+    keep[[8, 9]] = False
+    return frame, landmark, keep
+
+
+def test_guard_frames_worked_example():
+    frame, landmark, keep = _guard_case()
+    # links: frames 0, 1, 2 have two each, frame 3 none
+    out, n = xm2.guard_frames(4, 5, frame, landmark, keep, 1)
+    assert n == 2 and out.all()             # (0, 3) and (2, 4) come back: landmarks of frame 3
+    out, n = xm2.guard_frames(4, 5, frame, landmark, keep, 0)
+    assert n == 0 and (out == keep).all()   # disabled
+    # min_links 3: every frame is starved, so every landmark is rescued
+    out, n = xm2.guard_frames(4, 5, frame, landmark, keep, 3)
+    assert n == 2 and out.all()
+    # frame 1 loses (1, 2): landmark 2 keeps one observation, so frames 1 and 2
+    # drop to one link; with min_links 2 they are starved with frame 3
+    keep2 = keep.copy()
+    keep2[4] = False
+    out, n = xm2.guard_frames(4, 5, frame, landmark, keep2, 2)
+    assert n == 3 and out.all()
+    # only frame 3 starved (min_links 1): its landmarks 3, 4 come back, the
+    # deleted (1, 2) stays deleted
+    out, n = xm2.guard_frames(4, 5, frame, landmark, keep2, 1)
+    assert n == 2 and not out[4] and out[[0, 1, 2, 3, 5, 6, 7, 8, 9]].all()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_guard_frames_invariants(seed):
+    # random deletions on a random scene: afterwards every frame has at least
+    # min_links links or keeps every observation of it and of its landmarks;
+    # nothing kept is deleted; a second pass changes nothing
+    rng = np.random.default_rng(seed)
+    N, M, n = 40, 300, 1500
+    frame = rng.integers(0, N, n).astype(np.int32)
+    landmark = rng.integers(0, M, n).astype(np.int32)
+    keep = rng.random(n) > 0.5
+    for mlinks in (1, 4, 8):
+        out, nr = xm2.guard_frames(N, M, frame, landmark, keep, mlinks)
+        assert nr == int((out & ~keep).sum()) and not (keep & ~out).any()
+        again, nr2 = xm2.guard_frames(N, M, frame, landmark, out, mlinks)
+        assert nr2 == 0 and (again == out).all()
+        for i in range(N):
+            mine = frame == i
+            links = sum(1 for o in np.flatnonzero(mine & out)
+                        if np.count_nonzero(out & (landmark == landmark[o])) >= 2)
+            if links < mlinks:
+                seen = np.isin(landmark, landmark[mine])
+                assert out[mine].all() and out[seen].all()
