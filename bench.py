@@ -357,7 +357,7 @@ def main():
         bad = sc.gt["outlier"]
         out["xm2_variant"] = {
             "workload": "as the timed workload, then XM^2: the 10% largest residuals |e_o|/s_i deleted, re-solved",
-            "wall_s": round(txm2, 3), "dropped": o2["n_dropped"],
+            "wall_s": round(txm2, 3), "dropped": o2["n_dropped"], "restored": o2["n_restored"],
             "injected_outliers_deleted": round(float((bad & ~kept).sum() / max(1, bad.sum())), 4),
             "first": {"certified": bool(i1["certified"]), "rank": i1["r"], "cost": i1["cost"], "rho_hat": rho1,
                       "eta": (rho1 - i1["cost"]) / (1 + abs(rho1) + abs(i1["cost"]))},

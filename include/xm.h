@@ -476,6 +476,24 @@ xm_status xm_residuals(xm_problem* p, const double* R, const double* s, int32_t 
 xm_status xm_drop_largest(const double* score, int64_t n, double frac, uint8_t* keep, int64_t* n_dropped,
                           void* stream);
 
+/*
+ * Frame guard of the XM^2 deletion (Section "Structure from Motion with XM",
+ * solver paragraph; the paper leaves open what happens to a frame the
+ * deletion leaves undetermined).  A kept observation of landmark k is a link
+ * of its frame when k keeps at least two observations; a frame with fewer
+ * than min_links links is starved, and every observation of a starved frame
+ * or of a landmark a starved frame sees is kept again.  One pass; afterwards
+ * every frame has min_links links or all the links it can have, so a second
+ * call changes nothing.  frame, landmark device int32 [n] (frame in [0, N),
+ * landmark in [0, M)); keep device uint8 [n], nonzero = kept, updated in place
+ * (restored entries become 1); *n_restored (host, may be NULL) receives the
+ * number of entries restored.  Deterministic (integer counts).  XM_EINVAL for
+ * N or M < 1, n outside [1, 2^31), min_links < 0 or an index out of range
+ * (keep untouched).  Synchronises `stream`.
+ */
+xm_status xm_guard_frames(int32_t N, int32_t M, int64_t n, const int32_t* frame, const int32_t* landmark,
+                          int32_t min_links, uint8_t* keep, int64_t* n_restored, void* stream);
+
 typedef struct {
   int32_t cg_iters;    /* CG iterations of the Hessian solve */
   double cg_residual;  /* final relative CG residual */

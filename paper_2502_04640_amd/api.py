@@ -104,6 +104,8 @@ def load_library() -> ctypes.CDLL:
     lib.xm_residuals.restype = ctypes.c_int
     lib.xm_drop_largest.argtypes = [V, I64, D, V, ctypes.POINTER(ctypes.c_int64), V]
     lib.xm_drop_largest.restype = ctypes.c_int
+    lib.xm_guard_frames.argtypes = [I32, I32, I64, V, V, I32, V, ctypes.POINTER(ctypes.c_int64), V]
+    lib.xm_guard_frames.restype = ctypes.c_int
     lib.xm_align_similarity.argtypes = [I64, V, V, V, ctypes.POINTER(ctypes.c_double), V]
     lib.xm_align_similarity.restype = ctypes.c_int
     lib.xm_free.argtypes = [P]
@@ -437,6 +439,20 @@ def drop_largest(score: torch.Tensor, frac: float = 0.1):
     return keep, nd.value
 
 
+def guard_frames(N: int, M: int, frame: torch.Tensor, landmark: torch.Tensor, keep: torch.Tensor,
+                 min_links: int = 6):
+    """xm_guard_frames on a copy of `keep` (uint8 [n]): (guarded keep mask, number restored)."""
+    frame = _dev_tensor(frame, torch.int32, "frame")
+    landmark = _dev_tensor(landmark, torch.int32, "landmark")
+    if landmark.shape != frame.shape or keep.shape != frame.shape:
+        raise ValueError("frame, landmark and keep must have one entry per observation")
+    out = _dev_tensor(keep, torch.uint8, "keep").clone()
+    nr = ctypes.c_int64(0)
+    _check(load_library().xm_guard_frames(N, M, frame.shape[0], _ptr(frame), _ptr(landmark), int(min_links),
+                                          _ptr(out), ctypes.byref(nr), _stream()))
+    return out, nr.value
+
+
 def align_similarity(P: torch.Tensor, Q: torch.Tensor, w: Optional[torch.Tensor] = None) -> dict:
     """xm_align_similarity: s, R [3,3], t [3] minimising sum w |s R P_i + t - Q_i|^2
     (P, Q [n,3] float64 on the device), and the weighted RMS residual."""
@@ -458,11 +474,12 @@ def align_similarity(P: torch.Tensor, Q: torch.Tensor, w: Optional[torch.Tensor]
 
 def xm2(N: int, M: int, frame: torch.Tensor, landmark: torch.Tensor, u: torch.Tensor,
         w: Optional[torch.Tensor] = None, opts: Optional["SolveOptions"] = None, frac: float = 0.1,
-        frame_units: bool = True, keep=("f32",)):
+        frame_units: bool = True, keep=("f32",), min_links: int = 6):
     """XM^2 (Section "Structure from Motion with XM"): xm_build_Q -> xm_bm_solve
-    -> xm_round -> xm_residuals -> xm_drop_largest -> xm_build_Q_masked ->
-    xm_bm_solve (started from the first solution) -> xm_round.  Returns a dict
-    with both passes' (R, s, rho_hat, info), the scores and the keep mask."""
+    -> xm_round -> xm_residuals -> xm_drop_largest -> xm_guard_frames ->
+    xm_build_Q_masked -> xm_bm_solve (started from the first solution) ->
+    xm_round.  Returns a dict with both passes' (R, s, rho_hat, info), the
+    scores, the keep mask, the numbers deleted and restored."""
     opts = opts or SolveOptions()
     P1 = build_Q(N, M, frame, landmark, u, w, keep=keep)
     Y1, i1 = P1.solve(opts)
@@ -470,11 +487,12 @@ def xm2(N: int, M: int, frame: torch.Tensor, landmark: torch.Tensor, u: torch.Te
     _, score = P1.residuals(R1, s1, frame_units)
     P1.close()
     mask, n_drop = drop_largest(score, frac)
+    mask, n_rest = guard_frames(N, M, frame, landmark, mask, min_links)
     P2 = build_Q(N, M, frame, landmark, u, w, keep=keep, mask=mask)
     Y2, i2 = P2.solve(opts, Y0=Y1[: i1["r"]])
     R2, s2, rho2 = P2.round(Y2)
     return {"first": (R1, s1, rho1, i1), "second": (R2, s2, rho2, i2), "score": score, "keep": mask,
-            "n_dropped": n_drop, "problem": P2, "Y": Y2}
+            "n_dropped": n_drop - n_rest, "n_restored": n_rest, "problem": P2, "Y": Y2}
 
 
 def build_Q(N: int, M: int, frame: torch.Tensor, landmark: torch.Tensor, u: torch.Tensor,

@@ -86,6 +86,16 @@ xm_status xm_drop_largest(const double* score, int64_t n, double frac, uint8_t* 
   XM_API_CATCH
 }
 
+xm_status xm_guard_frames(int32_t N, int32_t M, int64_t n, const int32_t* frame, const int32_t* landmark,
+                          int32_t min_links, uint8_t* keep, int64_t* n_restored, void* stream) {
+  XM_API_TRY
+  if (!frame || !landmark || !keep) return fail(XM_EINVAL, "NULL argument");
+  const int64_t r = xm::guard_frames(N, M, n, frame, landmark, min_links, keep, as_stream(stream));
+  if (n_restored) *n_restored = r;
+  return XM_OK;
+  XM_API_CATCH
+}
+
 void xm_free(xm_problem* p) { delete p; }
 
 xm_status xm_memory_info(int64_t* live_bytes, int64_t* cached_bytes) {

@@ -208,6 +208,12 @@ void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t 
 // keep[o] = 0 for the floor(frac n) largest scores (ties: lower index first),
 // 1 otherwise; scores must be finite and >= 0.  Returns the number dropped.
 int64_t drop_largest(const double* score, int64_t n, double frac, uint8_t* keep, hipStream_t s);
+// Frame guard of the deletion: a kept observation of landmark k links its
+// frame when k keeps >= 2 observations; for a frame with < min_links links,
+// every observation of it and of the landmarks it sees is kept again.  Frame
+// and landmark indices are range-checked.  Returns the number restored.
+int64_t guard_frames(int32_t N, int32_t M, int64_t n, const int32_t* frame, const int32_t* landmark,
+                     int32_t min_links, uint8_t* keep, hipStream_t s);
 
 // reduce.hip ----------------------------------------------------------------
 // Deterministic sum of `parts` rows of `nq` doubles laid out [parts][nq] into out[nq].

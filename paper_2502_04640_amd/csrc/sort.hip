@@ -191,6 +191,54 @@ __global__ void keep_mask_kernel(const uint64_t* __restrict__ idx, int64_t n, in
   if (e < n) keep[idx[e]] = (e < k) ? 0 : 1;
 }
 
+// Frame guard of the XM^2 deletion.  cnt[k] = kept observations of landmark k;
+// flag[0] = 1 for a frame or landmark index out of range.
+__global__ void guard_count_kernel(const int32_t* __restrict__ frame, const int32_t* __restrict__ landmark,
+                                   const uint8_t* __restrict__ keep, int64_t n, int32_t N, int32_t M,
+                                   int32_t* __restrict__ cnt, int* flag) {
+  const int64_t o = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (o >= n) return;
+  const int32_t i = frame[o], k = landmark[o];
+  if (i < 0 || i >= N || k < 0 || k >= M) {
+    flag[0] = 1;
+    return;
+  }
+  if (keep[o]) atomicAdd(cnt + k, 1);
+}
+
+// links[i] = kept observations of frame i whose landmark keeps >= 2
+__global__ void guard_links_kernel(const int32_t* __restrict__ frame, const int32_t* __restrict__ landmark,
+                                   const uint8_t* __restrict__ keep, int64_t n,
+                                   const int32_t* __restrict__ cnt, int32_t* __restrict__ links) {
+  const int64_t o = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (o >= n) return;
+  if (keep[o] && cnt[landmark[o]] >= 2) atomicAdd(links + frame[o], 1);
+}
+
+// rescued[k] = 1 for every landmark seen by a frame with fewer than min_links
+// links (every writer stores the same value)
+__global__ void guard_rescue_kernel(const int32_t* __restrict__ frame, const int32_t* __restrict__ landmark,
+                                    int64_t n, const int32_t* __restrict__ links, int32_t min_links,
+                                    uint8_t* __restrict__ rescued) {
+  const int64_t o = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (o >= n) return;
+  if (links[frame[o]] < min_links) rescued[landmark[o]] = 1;
+}
+
+// keep[o] = 1 again when o's frame is starved or its landmark rescued;
+// restored[0] counts the flips
+__global__ void guard_restore_kernel(const int32_t* __restrict__ frame, const int32_t* __restrict__ landmark,
+                                     int64_t n, const int32_t* __restrict__ links, int32_t min_links,
+                                     const uint8_t* __restrict__ rescued, uint8_t* __restrict__ keep,
+                                     unsigned long long* restored) {
+  const int64_t o = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (o >= n) return;
+  if (!keep[o] && (links[frame[o]] < min_links || rescued[landmark[o]])) {
+    keep[o] = 1;
+    atomicAdd(restored, 1ull);
+  }
+}
+
 }  // namespace
 
 void radix_sort_pairs(uint32_t* keys, uint64_t* vals, uint32_t* keys_tmp, uint64_t* vals_tmp,
@@ -250,6 +298,45 @@ int64_t drop_largest(const double* score, int64_t n, double frac, uint8_t* keep,
   XM_LAUNCH_CHECK("keep_mask_kernel");
   XM_HIP(hipStreamSynchronize(s));
   return k;
+}
+
+int64_t guard_frames(int32_t N, int32_t M, int64_t n, const int32_t* frame, const int32_t* landmark,
+                     int32_t min_links, uint8_t* keep, hipStream_t s) {
+  require(frame && landmark && keep, XM_EINVAL, "frame, landmark and keep must be non-NULL");
+  require(N >= 1 && M >= 1, XM_EINVAL, "N and M must be >= 1");
+  require(n >= 1 && n < (int64_t(1) << 31), XM_EINVAL, "n must be in [1, 2^31)");
+  require(min_links >= 0, XM_EINVAL, "min_links must be >= 0");
+  DevBuf<int32_t> cnt(M), links(N);
+  DevBuf<uint8_t> rescued(M);
+  DevBuf<int> flag(1);
+  DevBuf<unsigned long long> restored(1);
+  XM_HIP(hipMemsetAsync(cnt.ptr, 0, M * sizeof(int32_t), s));
+  XM_HIP(hipMemsetAsync(links.ptr, 0, N * sizeof(int32_t), s));
+  XM_HIP(hipMemsetAsync(rescued.ptr, 0, M * sizeof(uint8_t), s));
+  XM_HIP(hipMemsetAsync(flag.ptr, 0, sizeof(int), s));
+  XM_HIP(hipMemsetAsync(restored.ptr, 0, sizeof(unsigned long long), s));
+  const unsigned g = static_cast<unsigned>((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(guard_count_kernel, dim3(g), dim3(kBlock), 0, s, frame, landmark,
+                     static_cast<const uint8_t*>(keep), n, N, M, cnt.ptr, flag.ptr);
+  XM_LAUNCH_CHECK("guard_count_kernel");
+  int hflag = 0;
+  XM_HIP(hipMemcpyAsync(&hflag, flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+  XM_HIP(hipStreamSynchronize(s));
+  require(!hflag, XM_EINVAL, "frame or landmark index out of range");
+  hipLaunchKernelGGL(guard_links_kernel, dim3(g), dim3(kBlock), 0, s, frame, landmark,
+                     static_cast<const uint8_t*>(keep), n, static_cast<const int32_t*>(cnt.ptr), links.ptr);
+  XM_LAUNCH_CHECK("guard_links_kernel");
+  hipLaunchKernelGGL(guard_rescue_kernel, dim3(g), dim3(kBlock), 0, s, frame, landmark, n,
+                     static_cast<const int32_t*>(links.ptr), min_links, rescued.ptr);
+  XM_LAUNCH_CHECK("guard_rescue_kernel");
+  hipLaunchKernelGGL(guard_restore_kernel, dim3(g), dim3(kBlock), 0, s, frame, landmark, n,
+                     static_cast<const int32_t*>(links.ptr), min_links, static_cast<const uint8_t*>(rescued.ptr),
+                     keep, restored.ptr);
+  XM_LAUNCH_CHECK("guard_restore_kernel");
+  unsigned long long hr = 0;
+  XM_HIP(hipMemcpyAsync(&hr, restored.ptr, sizeof(hr), hipMemcpyDeviceToHost, s));
+  XM_HIP(hipStreamSynchronize(s));
+  return static_cast<int64_t>(hr);
 }
 
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {

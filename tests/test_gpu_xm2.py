@@ -138,9 +138,9 @@ def test_xm2_loop_matches_oracle(units):
     assert _rot_err(R1.cpu().numpy(), o["first"][0]) <= 1e-6
     keep = out["keep"].cpu().numpy().astype(bool)
     score = out["score"].cpu().numpy()
-    assert out["n_dropped"] == int(0.1 * sc.n_obs)
+    assert out["n_dropped"] + out["n_restored"] == int(0.1 * sc.n_obs)
     diff = keep != o["keep"]
-    thr = np.sort(score)[::-1][out["n_dropped"] - 1]
+    thr = np.sort(score)[::-1][int(0.1 * sc.n_obs) - 1]
     assert np.all(np.abs(score[diff] - thr) <= 1e-9 * thr)
     # second pass: the oracle's staircase on the GPU's kept set
     R2, s2, rho2, i2 = out["second"]
@@ -155,3 +155,56 @@ def test_xm2_loop_matches_oracle(units):
          f"second {_rot_err(R2.cpu().numpy(), sc.gt['R']):.2e}")
     assert err <= 1e-6 and np.abs(s2.cpu().numpy() / sh - 1).max() <= 1e-6
     assert _gap(i2["cost"], oinfo["cost"]) <= 1e-8
+
+
+def test_guard_frames_matches_oracle():
+    # random deletions (half the observations) on a 200-frame scene, so that
+    # frames starve at every threshold; the guard is integer work: bit-exact
+    _say("case: frame guard vs oracle, 200 frames, random half deleted")
+    xm = _xm()
+    sc = scenes.random_scene(200, 3000, L=3, sigma=0.01, seed=21)
+    rng = np.random.default_rng(21)
+    fr, lm = torch.from_numpy(sc.frame).cuda(), torch.from_numpy(sc.landmark).cuda()
+    for p_keep in (0.5, 0.8):
+        keep = rng.random(sc.n_obs) < p_keep
+        kd = torch.from_numpy(keep.astype(np.uint8)).cuda()
+        for mlinks in (0, 1, 4, 8, 30):
+            got, nr = xm.guard_frames(sc.N, sc.M, fr, lm, kd, mlinks)
+            ref, nr_ref = oxm2.guard_frames(sc.N, sc.M, sc.frame, sc.landmark, keep, mlinks)
+            assert nr == nr_ref
+            assert np.array_equal(got.cpu().numpy().astype(bool), ref)
+            again, nr2 = xm.guard_frames(sc.N, sc.M, fr, lm, got, mlinks)
+            assert nr2 == 0 and torch.equal(again, got)
+    # one observation; all kept; none kept
+    one = torch.zeros(1, dtype=torch.uint8, device="cuda")
+    got, nr = xm.guard_frames(1, 1, fr[:1] * 0, lm[:1] * 0, one, 1)
+    assert nr == 1 and int(got[0]) == 1
+    allk = torch.ones(sc.n_obs, dtype=torch.uint8, device="cuda")
+    got, nr = xm.guard_frames(sc.N, sc.M, fr, lm, allk, 8)
+    assert nr == 0 and torch.equal(got, allk)
+    got, nr = xm.guard_frames(sc.N, sc.M, fr, lm, allk * 0, 1)
+    assert nr == sc.n_obs and bool(got.all())
+    # an index out of range is an error and leaves the mask alone
+    bad = fr.clone()
+    bad[7] = sc.N
+    with pytest.raises(xm.XMError, match="XM_EINVAL"):
+        xm.guard_frames(sc.N, sc.M, bad, lm, allk * 0, 1)
+    with pytest.raises(xm.XMError, match="XM_EINVAL"):
+        xm.guard_frames(sc.N, sc.M, fr, lm, allk, -1)
+
+
+def test_xm2_large_guarded_deletion_certifies():
+    # the 10155-frame workload, seed 1: the deletion starves a few frames (one
+    # or two links left); with the guard the second pass certifies
+    _say("case: XM^2 on the 10155-frame workload, seed 1, FP32")
+    xm = _xm()
+    sc = scenes.make_scene("large", 1)
+    out = xm.xm2(sc.N, sc.M, *_dev(sc), opts=xm.SolveOptions(compute="f32"), frac=0.1, frame_units=True)
+    i1, i2 = out["first"][3], out["second"][3]
+    _say(f"  restored {out['n_restored']}, deleted {out['n_dropped']}; second pass certified {i2['certified']}, "
+         f"outer {i2['outer_iters']}, inner {i2['inner_iters']}")
+    assert i1["certified"] == 1 and i2["certified"] == 1
+    assert out["n_restored"] > 0 and out["n_dropped"] + out["n_restored"] == int(0.1 * sc.n_obs)
+    keep = out["keep"].cpu().numpy().astype(bool)
+    ref, _ = oxm2.guard_frames(sc.N, sc.M, sc.frame, sc.landmark, keep, 6)
+    assert np.array_equal(ref, keep)        # the guarded mask is a fixed point of the guard
