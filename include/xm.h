@@ -303,8 +303,11 @@ typedef struct {
                           FP32 Q) down to grad_tol / 1000.  A point whose
                           certificate fails only through the stationarity
                           terms of its bound is polished at the same rank
-                          with a 10x tighter tolerance (up to 3 times; FP64
-                          Hessian products).  The
+                          (up to 3 times; FP64 Hessian products) to the
+                          reached |g| times (cert tol qbar / 2|bound|)^(1/k),
+                          k in [1, 2] fitted to the bound's fall with |g|
+                          (2 at first), and at least 10x below the previous
+                          tolerance.  The
                           FP64 stage exists because the dual certificate needs
                           a point closer to stationary than a reduced-precision
                           iterate's own rounding allows */

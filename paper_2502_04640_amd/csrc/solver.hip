@@ -410,15 +410,22 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
   CertResult cr;
   // refinements at the current rank: when the certificate fails only through
   // the stationarity terms of its bound (the complement of rows(Y) alone
-  // certifies, so no escape direction exists), the point is polished with a
-  // 10x tighter gradient tolerance, at most three times per rank (FP64
-  // Hessian products in a reduced-precision solve: near its floor the FP32
-  // model gains little per step)
+  // certifies, so no escape direction exists), the point is polished to a
+  // tighter gradient tolerance, at most three times per rank (FP64 Hessian
+  // products in a reduced-precision solve: near its floor the FP32 model
+  // gains little per step).  Those terms shrink like a power |g|^k of the
+  // gradient, 1 <= k <= 2 (the deflated block linearly, the coupling through
+  // its square); the next target is the reached |g| times
+  // (tol qbar / (2 |bound|))^(1/k), k = 2 for the first polish and fitted to
+  // the last two (|g|, bound) pairs after that; the new tolerance is that
+  // target or 10x the previous tolerance, whichever is lower, and never more
+  // than 1e4x below the previous one.
   constexpr int kMaxRefines = 3;
+  const double base_tol = grad_tol64;  // the tolerance the polish stages scale
   int refines = 0;
+  double tscale = 1.0, g_prev = 0.0, b_prev = 0.0;
   while (true) {
     auto t0 = std::chrono::steady_clock::now();
-    const double tscale = std::pow(0.1, refines);
     Vecs<double>* X = nullptr;
     if constexpr (f64) {
       ro = rtr<T>(p, V, r, qg, qh, o, grad_tol * tscale, st);
@@ -462,6 +469,15 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
                    cr.certified ? "certified" : "not certified");
     if (cr.certified) break;
     if (cr.complement_ok && refines < kMaxRefines) {
+      const double b = std::fabs(cr.lambda_bound), need = 0.5 * cert_tol * p->qbar / b;
+      double k = 2.0;
+      if (refines > 0 && g_prev > ro.gnorm && b_prev > b)
+        k = std::fmin(2.0, std::fmax(1.0, std::log(b_prev / b) / std::log(g_prev / ro.gnorm)));
+      const double t = std::fmin(1.0, std::fmax(1e-4, std::pow(need, 1.0 / k)));
+      const double reached = ro.gnorm / (p->qbar * ro.ynorm);  // relative, as the tolerance
+      tscale = std::fmax(1e-4 * tscale, std::fmin(0.1 * tscale, t * reached / base_tol));
+      g_prev = ro.gnorm;
+      b_prev = b;
       ++refines;
       continue;
     }
@@ -469,6 +485,7 @@ xm_status staircase(xm_problem* p, const xm_solve_opts& o, const double* Y0, int
     if (!escape_fp64(p, *X, Yt64.ptr, r, vmin.ptr, &info->spmm_count, st)) break;
     ++r;
     refines = 0;
+    tscale = 1.0;
     ++info->stair_steps;
     if constexpr (!f64) {
       // back to the reduced-precision stage at the new rank
