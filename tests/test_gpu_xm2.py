@@ -193,18 +193,26 @@ def test_guard_frames_matches_oracle():
         xm.guard_frames(sc.N, sc.M, fr, lm, allk, -1)
 
 
-def test_xm2_large_guarded_deletion_certifies():
-    # the 10155-frame workload, seed 1: the deletion starves a few frames (one
-    # or two links left); with the guard the second pass certifies
-    _say("case: XM^2 on the 10155-frame workload, seed 1, FP32")
+@pytest.mark.parametrize("seed", [1, 2])
+def test_xm2_large_guarded_deletion_certifies(seed):
+    # the 10155-frame workload. Seed 1: the deletion starves a few frames (one
+    # or two links left); with the guard the second pass certifies. Seed 2: no
+    # frame starves; the second pass certifies only after polishing, whose
+    # tolerance model keeps it near 2400 inner iterations (13416 with a fixed
+    # 10x per polish)
+    _say(f"case: XM^2 on the 10155-frame workload, seed {seed}, FP32")
     xm = _xm()
-    sc = scenes.make_scene("large", 1)
+    sc = scenes.make_scene("large", seed)
     out = xm.xm2(sc.N, sc.M, *_dev(sc), opts=xm.SolveOptions(compute="f32"), frac=0.1, frame_units=True)
     i1, i2 = out["first"][3], out["second"][3]
     _say(f"  restored {out['n_restored']}, deleted {out['n_dropped']}; second pass certified {i2['certified']}, "
          f"outer {i2['outer_iters']}, inner {i2['inner_iters']}")
     assert i1["certified"] == 1 and i2["certified"] == 1
-    assert out["n_restored"] > 0 and out["n_dropped"] + out["n_restored"] == int(0.1 * sc.n_obs)
+    assert out["n_dropped"] + out["n_restored"] == int(0.1 * sc.n_obs)
+    if seed == 1:
+        assert out["n_restored"] > 0
+    else:
+        assert i2["inner_iters"] <= 5000
     keep = out["keep"].cpu().numpy().astype(bool)
     ref, _ = oxm2.guard_frames(sc.N, sc.M, sc.frame, sc.landmark, keep, 6)
     assert np.array_equal(ref, keep)        # the guarded mask is a fixed point of the guard
